@@ -1,0 +1,154 @@
+/*
+ * tn.h -- C ABI of the MI355X exact planar-lattice contraction library.
+ *
+ * The problem (paper §4): an Lh x Lw planar square lattice of tensors with no
+ * external indices -- corner tensors of order 2, edge tensors of order 3,
+ * bulk tensors of order 4 -- is summed over all internal indices to one
+ * scalar by a sequence of pairwise contractions.  The order of contraction
+ * changes memory and cost, not the result (§4, "the order of the
+ * contraction matters"; the method is exact).
+ *
+ * Conventions used by every call:
+ *   - Sites are listed row-major, site (0,0) at the top-left.
+ *   - Bond h(r,c) joins (r,c)-(r,c+1); bond v(r,c) joins (r,c)-(r+1,c).
+ *   - A site tensor's legs are ordered (left, up, right, down) with absent
+ *     legs omitted; entries are float64, C-order (last leg fastest).
+ *   - Results are exact up to rounding: Z = mantissa * 2^exp2_sum with
+ *     |mantissa| in [0.5, 1), sign in {-1, 0, +1}, log_abs = ln|Z|.
+ *
+ * Every call returns a tn_status; no C++ exception, abort or exit crosses
+ * the ABI.  tn_last_error() returns a message for the calling thread's last
+ * failure.  Device memory is always supplied by the caller (pointer +
+ * bytes); the library allocates none on the contraction path.  Streams are
+ * the caller's hipStream_t passed as void*.
+ */
+#ifndef TN_H_
+#define TN_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tn_status;
+#define TN_OK          0
+#define TN_PENDING     1    /* tn_poll: the request has not finished yet          */
+#define TN_EINVAL     -1    /* bad shape, dimension, pointer or enum               */
+#define TN_ENOMEM     -2    /* workspace / arena / text buffer too small           */
+#define TN_EBUSY      -3    /* server queue full                                   */
+#define TN_EDEVICE    -4    /* a HIP runtime call failed                           */
+#define TN_ENOTFOUND  -5    /* unknown or already retired ticket                   */
+#define TN_ENONFINITE -6    /* NaN/Inf in the inputs or in an intermediate          */
+#define TN_EOVERFLOW  -7    /* a plan integer (size, flops) exceeds int64          */
+
+/* Contraction orders (paper §4 and Fig. 2).
+ *   COLSWEEP : one boundary tensor absorbs the lattice column by column, top to
+ *              bottom -- the sequential form of the paper's row contraction
+ *              (boundary of chi^L entries between columns).
+ *   QUADRANT : the four quadrants are swept from their outer corners towards the
+ *              middle; the ring of four tensors is then closed by two matrix
+ *              products and an elementwise dot.
+ *   HEURISTIC: the candidate (sweep, transposed sweep, every quadrant split)
+ *              with the smallest bottleneck tensor; ties broken by total flops,
+ *              then by enumeration order (§4, last paragraph).                 */
+#define TN_ORDER_COLSWEEP  0
+#define TN_ORDER_QUADRANT  1
+#define TN_ORDER_HEURISTIC 2
+
+/* Arithmetic of the contraction.
+ *   F64    : every step in float64.
+ *   F32    : boundary and sites in float32, float32 products and sums; the
+ *            last column of a sweep and the ring's final dot in float64.
+ *   BF16X3 : float32 storage; every product formed from bf16 hi/lo splits of
+ *            both operands as hi*hi + hi*lo + lo*hi on MFMA with float32
+ *            accumulation; last column and final dot in float64.
+ * Rescaling is exact in all three: after every column the boundary is scaled
+ * by 2^-e, e = exponent of its largest magnitude, and e is summed in int64. */
+#define TN_PREC_F64    0
+#define TN_PREC_F32    1
+#define TN_PREC_BF16X3 2
+
+typedef struct {
+  int32_t rows;            /* Lh >= 1                                            */
+  int32_t cols;            /* Lw >= 1                                            */
+  int32_t D;               /* uniform bond dimension (>= 1), used when hdim/vdim */
+                           /* are NULL                                           */
+  const int32_t* hdim;     /* NULL or rows*(cols-1) dims of h(r,c), row-major    */
+  const int32_t* vdim;     /* NULL or (rows-1)*cols dims of v(r,c), row-major    */
+} tn_grid;
+
+typedef struct {
+  int32_t sign;            /* -1, 0 or +1                                        */
+  int32_t status;          /* TN_OK or TN_ENONFINITE                             */
+  double  log_abs;         /* ln|Z|; -inf when Z == 0                            */
+  double  value;           /* Z as a double (may be +-inf when |Z| > DBL_MAX)    */
+  double  mantissa;        /* Z = mantissa * 2^exp2_sum, |mantissa| in [0.5,1)   */
+  int64_t exp2_sum;
+} tn_result;
+
+typedef struct {
+  int32_t order;           /* order actually planned (never HEURISTIC)           */
+  int32_t transpose;       /* COLSWEEP: 1 if the sweep runs along rows           */
+  int32_t quad_h, quad_w;  /* QUADRANT split (rows [0,h), cols [0,w))            */
+  int32_t n_steps;         /* INIT + ABSORB steps over all units                 */
+  int32_t n_units;         /* 1 (sweep) or 4 (quadrant)                          */
+  int32_t n_slots;         /* rescale points                                     */
+  int32_t reserved;
+  int64_t peak_entries;    /* bottleneck: largest intermediate, in entries       */
+  int64_t flops;           /* algorithmic: sum of 2 * d(out) * d(shared)         */
+  int64_t moved_entries;   /* algorithmic boundary traffic: sum of d(in)+d(out)  */
+  int64_t workspace_bytes[3]; /* per precision (TN_PREC_*): bytes tn_contract_grid needs */
+  int64_t hbm_bytes[3];       /* per precision: algorithmic HBM bytes of one contraction */
+} tn_plan_info;
+
+typedef struct tn_plan tn_plan;
+typedef struct tn_server tn_server;
+
+/* Message describing the calling thread's last error ("" if none).  The
+ * pointer stays valid until the thread's next library call.                */
+const char* tn_last_error(void);
+
+/* Plan the contraction of `grid` in `order` (TN_ORDER_*).  quad_h / quad_w
+ * select the QUADRANT split (0 = ceil(rows/2) / ceil(cols/2)); ignored for the
+ * other orders.  Host only, integer only, deterministic.  The plan is
+ * immutable and may be shared between threads; free it with tn_plan_free.
+ * Errors: TN_EINVAL (rows/cols/D < 1, a dim < 1, QUADRANT on a lattice with
+ * fewer than 2 rows or columns, split out of range), TN_EOVERFLOW.         */
+tn_status tn_plan_grid(const tn_grid* grid, int32_t order, int32_t quad_h,
+                       int32_t quad_w, tn_plan** out);
+
+/* Sizes and costs of a plan (§4: element counts of every pairwise step and
+ * the bottleneck).                                                          */
+tn_status tn_plan_stats(const tn_plan* plan, tn_plan_info* out);
+
+/* Canonical text of a plan, used for bit-exact comparison.  On entry *len is
+ * the capacity of buf; on return it is the size needed including the NUL.
+ * Returns TN_ENOMEM (nothing written) if the capacity is too small.          */
+tn_status tn_plan_text(const tn_plan* plan, char* buf, size_t* len);
+
+void tn_plan_free(tn_plan* plan);
+
+/* Contract one lattice to its scalar on the GPU (paper §4: the sum over all
+ * internal indices, by pairwise contractions along `plan`).
+ *   sites           : rows*cols pointers (a host array) to the float64 site
+ *                     tensors in canonical leg order; each points to device
+ *                     memory if sites_on_device != 0, else to host memory
+ *                     (copied in on `stream`).  Borrowed for the call only.
+ *   precision       : TN_PREC_*.
+ *   workspace       : device memory of at least tn_plan_info.workspace_bytes
+ *                     [precision] bytes, 256-byte aligned, owned by the caller;
+ *                     its contents on entry are ignored.
+ *   hip_stream      : hipStream_t (NULL = the null stream).
+ * Blocks until *out is written.  Errors: TN_EINVAL, TN_ENOMEM (workspace
+ * too small), TN_EDEVICE, TN_ENONFINITE (also stored in out->status).      */
+tn_status tn_contract_grid(const tn_plan* plan, const double* const* sites,
+                           int32_t sites_on_device, int32_t precision,
+                           void* workspace, size_t ws_bytes, void* hip_stream,
+                           tn_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TN_H_ */

@@ -1,0 +1,17 @@
+"""Exact contraction of planar square-lattice tensor networks on MI355X.
+
+A thin ctypes binding over ``libtn.so`` (the C ABI in ``include/tn.h``): it
+only marshals arguments.  Every step of a contraction runs in the library's
+HIP kernels; PyTorch supplies device memory and the stream.  Importing this
+package fails loudly if the library has not been built
+(``python -m paper_1908_08553_amd.build``).
+"""
+from ._native import (  # noqa: F401
+    TN_OK, TN_PENDING, TN_EINVAL, TN_ENOMEM, TN_EBUSY, TN_EDEVICE, TN_ENOTFOUND,
+    TN_ENONFINITE, TN_EOVERFLOW,
+    TN_ORDER_COLSWEEP, TN_ORDER_QUADRANT, TN_ORDER_HEURISTIC,
+    TN_PREC_F64, TN_PREC_F32, TN_PREC_BF16X3,
+    TnError, Plan, Result, lib, library_path,
+    tn_plan_grid, tn_plan_stats, tn_plan_text, tn_contract_grid,
+    plan_grid, contract_grid, device_sites, workspace_for,
+)

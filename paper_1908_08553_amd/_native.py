@@ -1,0 +1,215 @@
+"""ctypes marshalling for include/tn.h (no arithmetic happens here)."""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libtn.so")
+
+if not os.path.exists(library_path):
+    raise ImportError(
+        f"{library_path} is missing: build it with `python -m paper_1908_08553_amd.build`")
+
+# PyTorch bundles its own HIP runtime under the same soname
+# (libamdhip64.so.7).  Loading torch first makes libtn.so bind to that
+# already-loaded runtime, so the process holds exactly one HIP runtime and the
+# library sees the same devices, streams and allocations as torch.
+import torch  # noqa: E402,F401
+
+lib = C.CDLL(library_path)
+
+TN_OK, TN_PENDING = 0, 1
+TN_EINVAL, TN_ENOMEM, TN_EBUSY, TN_EDEVICE = -1, -2, -3, -4
+TN_ENOTFOUND, TN_ENONFINITE, TN_EOVERFLOW = -5, -6, -7
+TN_ORDER_COLSWEEP, TN_ORDER_QUADRANT, TN_ORDER_HEURISTIC = 0, 1, 2
+TN_PREC_F64, TN_PREC_F32, TN_PREC_BF16X3 = 0, 1, 2
+
+_ORDERS = {"colsweep": 0, "quadrant": 1, "heuristic": 2}
+_PRECS = {"f64": 0, "f32": 1, "bf16x3": 2}
+
+
+class tn_grid(C.Structure):
+    _fields_ = [("rows", C.c_int32), ("cols", C.c_int32), ("D", C.c_int32),
+                ("hdim", C.POINTER(C.c_int32)), ("vdim", C.POINTER(C.c_int32))]
+
+
+class tn_result(C.Structure):
+    _fields_ = [("sign", C.c_int32), ("status", C.c_int32), ("log_abs", C.c_double),
+                ("value", C.c_double), ("mantissa", C.c_double), ("exp2_sum", C.c_int64)]
+
+
+class tn_plan_info(C.Structure):
+    _fields_ = [("order", C.c_int32), ("transpose", C.c_int32), ("quad_h", C.c_int32),
+                ("quad_w", C.c_int32), ("n_steps", C.c_int32), ("n_units", C.c_int32),
+                ("n_slots", C.c_int32), ("reserved", C.c_int32),
+                ("peak_entries", C.c_int64), ("flops", C.c_int64),
+                ("moved_entries", C.c_int64), ("workspace_bytes", C.c_int64 * 3),
+                ("hbm_bytes", C.c_int64 * 3)]
+
+
+_P = C.c_void_p
+lib.tn_last_error.restype = C.c_char_p
+lib.tn_last_error.argtypes = []
+lib.tn_plan_grid.restype = C.c_int32
+lib.tn_plan_grid.argtypes = [C.POINTER(tn_grid), C.c_int32, C.c_int32, C.c_int32, C.POINTER(_P)]
+lib.tn_plan_stats.restype = C.c_int32
+lib.tn_plan_stats.argtypes = [_P, C.POINTER(tn_plan_info)]
+lib.tn_plan_text.restype = C.c_int32
+lib.tn_plan_text.argtypes = [_P, C.c_char_p, C.POINTER(C.c_size_t)]
+lib.tn_plan_free.restype = None
+lib.tn_plan_free.argtypes = [_P]
+lib.tn_contract_grid.restype = C.c_int32
+lib.tn_contract_grid.argtypes = [_P, C.POINTER(C.c_void_p), C.c_int32, C.c_int32, _P,
+                                 C.c_size_t, _P, C.POINTER(tn_result)]
+
+
+class TnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"tn status {status}: {msg}")
+        self.status = status
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise TnError(status, lib.tn_last_error().decode())
+    return status
+
+
+@dataclass
+class Result:
+    sign: int
+    status: int
+    log_abs: float
+    value: float
+    mantissa: float
+    exp2_sum: int
+
+    @classmethod
+    def from_c(cls, r: tn_result) -> "Result":
+        return cls(r.sign, r.status, r.log_abs, r.value, r.mantissa, r.exp2_sum)
+
+
+def _int_array(v) -> Optional[C.Array]:
+    if v is None:
+        return None
+    import numpy as np
+    flat = [int(x) for x in np.asarray(v, dtype=np.int64).reshape(-1)]
+    return (C.c_int32 * max(len(flat), 1))(*flat)
+
+
+class Plan:
+    """Owns a tn_plan*; freed when garbage-collected."""
+
+    def __init__(self, handle: int, grid_keepalive=None):
+        self._h = C.c_void_p(handle)
+        self._keep = grid_keepalive
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.tn_plan_free(self._h)
+            self._h = None
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    def info(self) -> dict:
+        return tn_plan_stats(self)
+
+    def text(self) -> str:
+        return tn_plan_text(self)
+
+
+def tn_plan_grid(rows: int, cols: int, D: int = 2, hdim=None, vdim=None,
+                 order=TN_ORDER_COLSWEEP, quad_h: int = 0, quad_w: int = 0) -> Plan:
+    if isinstance(order, str):
+        order = _ORDERS[order]
+    h = _int_array(hdim)
+    v = _int_array(vdim)
+    g = tn_grid(rows, cols, D,
+                C.cast(h, C.POINTER(C.c_int32)) if h is not None else None,
+                C.cast(v, C.POINTER(C.c_int32)) if v is not None else None)
+    out = C.c_void_p()
+    _check(lib.tn_plan_grid(C.byref(g), order, quad_h, quad_w, C.byref(out)))
+    return Plan(out.value)
+
+
+def tn_plan_stats(plan: Plan) -> dict:
+    info = tn_plan_info()
+    _check(lib.tn_plan_stats(plan.handle, C.byref(info)))
+    return {"order": info.order, "transpose": info.transpose,
+            "quad": (info.quad_h, info.quad_w), "n_steps": info.n_steps,
+            "n_units": info.n_units, "n_slots": info.n_slots,
+            "peak_entries": info.peak_entries, "flops": info.flops,
+            "moved_entries": info.moved_entries,
+            "workspace_bytes": list(info.workspace_bytes),
+            "hbm_bytes": list(info.hbm_bytes)}
+
+
+def tn_plan_text(plan: Plan) -> str:
+    n = C.c_size_t(0)
+    lib.tn_plan_text(plan.handle, None, C.byref(n))
+    buf = C.create_string_buffer(n.value)
+    _check(lib.tn_plan_text(plan.handle, buf, C.byref(n)))
+    return buf.value.decode()
+
+
+def tn_contract_grid(plan: Plan, site_ptrs: Sequence[int], sites_on_device: bool,
+                     precision: int, workspace_ptr: int, ws_bytes: int,
+                     stream_ptr: int) -> Result:
+    arr = (C.c_void_p * len(site_ptrs))(*site_ptrs)
+    out = tn_result()
+    status = lib.tn_contract_grid(plan.handle, arr, 1 if sites_on_device else 0, precision,
+                                  C.c_void_p(workspace_ptr), ws_bytes, C.c_void_p(stream_ptr),
+                                  C.byref(out))
+    if status == TN_ENONFINITE:
+        return Result.from_c(out)
+    _check(status)
+    return Result.from_c(out)
+
+
+# ------------------------------------------------------------ conveniences
+
+plan_grid = tn_plan_grid
+
+
+def device_sites(sites, device="cuda"):
+    """Copy float64 site arrays to the GPU as contiguous torch tensors."""
+    import torch
+    return [torch.as_tensor(s, dtype=torch.float64).contiguous().to(device) for s in sites]
+
+
+def workspace_for(plan: Plan, precision: int, device="cuda"):
+    import torch
+    nbytes = plan.info()["workspace_bytes"][precision]
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def contract_grid(plan: Plan, sites, precision="f64", workspace=None, stream=None) -> Result:
+    """Contract with device-resident torch sites (or host numpy arrays)."""
+    import torch
+    if isinstance(precision, str):
+        precision = _PRECS[precision]
+    on_device = all(isinstance(s, torch.Tensor) and s.is_cuda for s in sites)
+    if on_device:
+        for s in sites:
+            if s.dtype != torch.float64 or not s.is_contiguous():
+                raise ValueError("device sites must be contiguous float64 tensors")
+        ptrs = [s.data_ptr() for s in sites]
+        keep = sites
+    else:
+        import numpy as np
+        keep = [np.ascontiguousarray(np.asarray(s, dtype=np.float64)) for s in sites]
+        ptrs = [a.ctypes.data for a in keep]
+    if workspace is None:
+        workspace = workspace_for(plan, precision)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    res = tn_contract_grid(plan, ptrs, on_device, precision, workspace.data_ptr(),
+                           workspace.numel() * workspace.element_size(), stream.cuda_stream)
+    del keep
+    return res

@@ -1,0 +1,124 @@
+// extern "C" entry points declared in include/tn.h.  Every entry point
+// catches everything: no exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "exec.hpp"
+#include "plan.hpp"
+#include "tn.h"
+
+struct tn_plan {
+  tn::Plan p;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+tn_status fail(tn_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tn_last_error(void) { return g_err.c_str(); }
+
+tn_status tn_plan_grid(const tn_grid* grid, int32_t order, int32_t quad_h, int32_t quad_w,
+                       tn_plan** out) {
+  try {
+    if (!grid || !out) return fail(TN_EINVAL, "null argument");
+    *out = nullptr;
+    auto* h = new (std::nothrow) tn_plan;
+    if (!h) return fail(TN_ENOMEM, "out of host memory");
+    std::string err;
+    const tn_status s = tn::build_plan(*grid, order, quad_h, quad_w, h->p, err);
+    if (s != TN_OK) {
+      delete h;
+      return fail(s, err);
+    }
+    *out = h;
+    g_err.clear();
+    return TN_OK;
+  } catch (const std::exception& e) {
+    return fail(TN_EINVAL, e.what());
+  } catch (...) {
+    return fail(TN_EINVAL, "unknown error");
+  }
+}
+
+tn_status tn_plan_stats(const tn_plan* plan, tn_plan_info* out) {
+  try {
+    if (!plan || !out) return fail(TN_EINVAL, "null argument");
+    const tn::Plan& p = plan->p;
+    std::memset(out, 0, sizeof(*out));
+    out->order = p.order;
+    out->transpose = p.transpose;
+    out->quad_h = p.qh;
+    out->quad_w = p.qw;
+    out->n_steps = static_cast<int32_t>(p.steps.size());
+    out->n_units = static_cast<int32_t>(p.units.size());
+    out->n_slots = p.slots;
+    out->peak_entries = p.peak;
+    out->flops = p.flops;
+    out->moved_entries = p.moved;
+    for (int32_t prec = 0; prec < 3; ++prec) {
+      out->workspace_bytes[prec] = static_cast<int64_t>(tn::make_layout(p, prec).total);
+      out->hbm_bytes[prec] = tn::algorithmic_bytes(p, prec);
+    }
+    return TN_OK;
+  } catch (...) {
+    return fail(TN_EINVAL, "tn_plan_stats failed");
+  }
+}
+
+tn_status tn_plan_text(const tn_plan* plan, char* buf, size_t* len) {
+  try {
+    if (!plan || !len) return fail(TN_EINVAL, "null argument");
+    const std::string t = tn::plan_text(plan->p);
+    const size_t need = t.size() + 1;
+    if (!buf || *len < need) {
+      *len = need;
+      return fail(TN_ENOMEM, "text buffer too small");
+    }
+    std::memcpy(buf, t.c_str(), need);
+    *len = need;
+    return TN_OK;
+  } catch (...) {
+    return fail(TN_EINVAL, "tn_plan_text failed");
+  }
+}
+
+void tn_plan_free(tn_plan* plan) { delete plan; }
+
+tn_status tn_contract_grid(const tn_plan* plan, const double* const* sites,
+                           int32_t sites_on_device, int32_t precision, void* workspace,
+                           size_t ws_bytes, void* hip_stream, tn_result* out) {
+  try {
+    if (!plan || !sites || !workspace || !out) return fail(TN_EINVAL, "null argument");
+    if (precision < TN_PREC_F64 || precision > TN_PREC_BF16X3)
+      return fail(TN_EINVAL, "unknown precision");
+    const tn::Plan& p = plan->p;
+    for (int32_t s = 0; s < p.rows * p.cols; ++s)
+      if (!sites[s]) return fail(TN_EINVAL, "null site pointer");
+    std::memset(out, 0, sizeof(*out));
+    std::string err;
+    const tn_status s = tn::contract(p, sites, sites_on_device != 0, precision, workspace,
+                                     ws_bytes, static_cast<hipStream_t>(hip_stream), out, err);
+    if (s != TN_OK) return fail(s, err);
+    g_err.clear();
+    return TN_OK;
+  } catch (const std::exception& e) {
+    return fail(TN_EDEVICE, e.what());
+  } catch (...) {
+    return fail(TN_EDEVICE, "unknown error");
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,252 @@
+// Executor for one lattice contraction on one GPU.
+//
+// Sequence on the caller's stream: (host sites -> workspace copy), one
+// staging launch (fold every site into its step's K x N matrix with an exact
+// power-of-two pre-normalisation), one absorption launch per pairwise step
+// (paper §4: pairwise, sequential contraction), the ring closure for the
+// quadrant order, and a finalize launch that assembles sign, exponent and
+// log|Z|; the 64-byte result is then copied back and the stream synchronised.
+#include "exec.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+namespace tn {
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+inline int32_t elem_bytes(int32_t t) { return t == EL_F64 ? 8 : 4; }
+
+// A colsweep's last column runs in float64 whatever the precision: it shrinks
+// the boundary to the scalar (the "final reduction").
+int32_t step_out_type(const Plan& p, const Step& s, int32_t prec) {
+  if (prec == TN_PREC_F64) return EL_F64;
+  if (p.order == TN_ORDER_COLSWEEP && s.last_col) return EL_F64;
+  return EL_F32;
+}
+
+const char* hip_msg(hipError_t e) { return hipGetErrorString(e); }
+
+}  // namespace
+
+Layout make_layout(const Plan& p, int32_t prec) {
+  Layout L;
+  const size_t nsteps = p.steps.size();
+  L.state = 0;
+  L.state_bytes = align_up(sizeof(DevState) + sizeof(int32_t) * (p.slots + 2 * nsteps));
+  size_t off = L.state_bytes;
+  L.descs = off;
+  off = align_up(off + sizeof(StageDesc) * nsteps);
+  L.raw = off;
+  off = align_up(off + sizeof(double) * static_cast<size_t>(p.total_site_entries));
+  L.s_off.resize(nsteps);
+  L.out_type.resize(nsteps);
+  int64_t staged = 0;
+  for (size_t k = 0; k < nsteps; ++k) {
+    L.s_off[k] = staged;
+    staged += p.steps[k].site_entries;
+    L.out_type[k] = step_out_type(p, p.steps[k], prec);
+  }
+  const size_t ns = static_cast<size_t>(std::max<int64_t>(staged, 1));
+  L.s64 = off; off = align_up(off + 8 * ns);
+  L.s32 = off; off = align_up(off + 4 * ns);
+  L.shi = off; off = align_up(off + 2 * ns);
+  L.slo = off; off = align_up(off + 2 * ns);
+  for (size_t u = 0; u < p.units.size(); ++u) {
+    const Unit& U = p.units[u];
+    size_t mx = 0;
+    for (int32_t k = U.first_step; k < U.first_step + U.n_steps; ++k)
+      mx = std::max(mx, static_cast<size_t>(p.steps[k].out) * elem_bytes(L.out_type[k]));
+    L.buf_bytes[u] = align_up(mx);
+    L.buf[u][0] = off; off += L.buf_bytes[u];
+    L.buf[u][1] = off; off += L.buf_bytes[u];
+  }
+  if (p.has_ring) {
+    const int32_t t = prec == TN_PREC_F64 ? EL_F64 : EL_F32;
+    L.yt = off;
+    L.yt_bytes = align_up(static_cast<size_t>(p.ring.m * p.ring.n) * elem_bytes(t));
+    off += L.yt_bytes;
+    L.n_partials = ring_partials(p.ring.m, p.ring.n);
+    L.partials = off;
+    off = align_up(off + sizeof(double) * static_cast<size_t>(L.n_partials));
+  }
+  L.total = off;
+  return L;
+}
+
+int64_t algorithmic_bytes(const Plan& p, int32_t prec) {
+  const Layout L = make_layout(p, prec);
+  int64_t bytes = 0;
+  for (size_t k = 0; k < p.steps.size(); ++k) {
+    const Step& s = p.steps[k];
+    const int64_t eo = elem_bytes(L.out_type[k]);
+    if (s.kind == STEP_INIT) { bytes += s.out * eo; continue; }
+    const int64_t ei = elem_bytes(L.out_type[k - 1]);
+    bytes += s.pre * s.K * s.post * ei + s.out * eo;
+  }
+  if (p.has_ring) {
+    const int64_t e = prec == TN_PREC_F64 ? 8 : 4;
+    for (const Unit& U : p.units) bytes += U.result * e;
+    bytes += 2 * p.ring.m * p.ring.n * e;
+  }
+  return bytes;
+}
+
+tn_status contract(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
+                   void* ws, size_t ws_bytes, hipStream_t stream, tn_result* out,
+                   std::string& err) {
+  const Layout L = make_layout(p, prec);
+  if (ws_bytes < L.total) {
+    err = "workspace too small: need " + std::to_string(L.total) + " bytes";
+    return TN_ENOMEM;
+  }
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) {
+    err = "workspace must be 256-byte aligned";
+    return TN_EINVAL;
+  }
+  char* base = static_cast<char*>(ws);
+  const int32_t nsites = p.rows * p.cols;
+  hipError_t e;
+#define TN_HIP(call)                                          \
+  do {                                                        \
+    e = (call);                                               \
+    if (e != hipSuccess) {                                    \
+      err = std::string(#call) + ": " + hip_msg(e);           \
+      return TN_EDEVICE;                                      \
+    }                                                         \
+  } while (0)
+
+  // site pointers on the device
+  std::vector<const double*> dsite(nsites);
+  if (on_device) {
+    for (int32_t s = 0; s < nsites; ++s) dsite[s] = sites[s];
+  } else {
+    size_t off = L.raw;
+    for (int32_t s = 0; s < nsites; ++s) {
+      const Step* st = nullptr;
+      for (const Step& x : p.steps)
+        if (x.r * p.cols + x.c == s) { st = &x; break; }
+      const size_t bytes = sizeof(double) * static_cast<size_t>(st->site_entries);
+      TN_HIP(hipMemcpyAsync(base + off, sites[s], bytes, hipMemcpyHostToDevice, stream));
+      dsite[s] = reinterpret_cast<const double*>(base + off);
+      off += bytes;
+    }
+  }
+
+  // staging descriptors
+  const size_t nsteps = p.steps.size();
+  std::vector<StageDesc> descs(nsteps);
+  std::vector<int32_t> cur(p.units.size(), 0);
+  for (size_t k = 0; k < nsteps; ++k) {
+    const Step& s = p.steps[k];
+    StageDesc& d = descs[k];
+    std::memset(&d, 0, sizeof(d));
+    d.src = dsite[s.r * p.cols + s.c];
+    d.entries = s.site_entries;
+    d.s_off = L.s_off[k];
+    d.ndim = s.nperm;
+    // canonical dims / strides of the site
+    int32_t cdims[4];
+    int64_t cstr[4];
+    int32_t nd = 0;
+    const int32_t R = p.rows, C = p.cols;
+    auto hd = [&](int32_t r, int32_t c) { return p.hdim[static_cast<size_t>(r) * (C - 1) + c]; };
+    auto vd = [&](int32_t r, int32_t c) { return p.vdim[static_cast<size_t>(r) * C + c]; };
+    if (s.c > 0) cdims[nd++] = hd(s.r, s.c - 1);
+    if (s.r > 0) cdims[nd++] = vd(s.r - 1, s.c);
+    if (s.c < C - 1) cdims[nd++] = hd(s.r, s.c);
+    if (s.r < R - 1) cdims[nd++] = vd(s.r, s.c);
+    int64_t st = 1;
+    for (int32_t a = nd - 1; a >= 0; --a) { cstr[a] = st; st *= cdims[a]; }
+    for (int32_t a = 0; a < s.nperm; ++a) {
+      d.dims[a] = cdims[s.perm[a]];
+      d.cstride[a] = cstr[s.perm[a]];
+    }
+    if (s.kind == STEP_INIT) {
+      d.init_dst = base + L.buf[s.unit][0];
+      d.init_double = L.out_type[k] == EL_F64;
+    }
+  }
+  TN_HIP(hipMemcpyAsync(base + L.descs, descs.data(), sizeof(StageDesc) * nsteps,
+                        hipMemcpyHostToDevice, stream));
+  // state header
+  DevState hs;
+  std::memset(&hs, 0, sizeof(hs));
+  hs.n_slots = p.slots;
+  hs.n_steps = static_cast<int32_t>(nsteps);
+  TN_HIP(hipMemcpyAsync(base + L.state, &hs, sizeof(hs), hipMemcpyHostToDevice, stream));
+
+  DevState* state = reinterpret_cast<DevState*>(base + L.state);
+  int32_t* slot_exp = reinterpret_cast<int32_t*>(state + 1);
+  StagedArrays sa{reinterpret_cast<double*>(base + L.s64), reinterpret_cast<float*>(base + L.s32),
+                  reinterpret_cast<uint16_t*>(base + L.shi),
+                  reinterpret_cast<uint16_t*>(base + L.slo)};
+  TN_HIP(launch_stage(reinterpret_cast<const StageDesc*>(base + L.descs),
+                      static_cast<int32_t>(nsteps), sa, state, stream));
+
+  const int32_t arith = prec == TN_PREC_F64 ? AR_F64 : (prec == TN_PREC_F32 ? AR_F32 : AR_BF16X3);
+  std::vector<int32_t> final_buf(p.units.size(), 0);
+  for (size_t u = 0; u < p.units.size(); ++u) {
+    const Unit& U = p.units[u];
+    int32_t c = 0;
+    for (int32_t k = U.first_step + 1; k < U.first_step + U.n_steps; ++k) {
+      const Step& s = p.steps[k];
+      AbsorbArgs a;
+      a.in = base + L.buf[u][c];
+      a.out = base + L.buf[u][1 - c];
+      a.in_type = L.out_type[k - 1];
+      a.out_type = L.out_type[k];
+      a.arith = arith;
+      a.pre = s.pre; a.K = s.K; a.N = s.N; a.post = s.post;
+      a.s_off = L.s_off[k];
+      a.scale_slot = s.scale_in >= 0 ? slot_exp + s.scale_in : nullptr;
+      a.max_slot = s.rescale >= 0 ? slot_exp + s.rescale : nullptr;
+      TN_HIP(launch_absorb(a, sa, state, stream));
+      c = 1 - c;
+    }
+    // a rescale on the INIT step of a one-row unit is measured here
+    final_buf[u] = c;
+  }
+
+  if (!p.has_ring) {
+    const double* scalar = reinterpret_cast<const double*>(base + L.buf[0][final_buf[0]]);
+    TN_HIP(launch_finalize(state, scalar, nullptr, nullptr, 0, stream));
+  } else {
+    const Ring& g = p.ring;
+    const int32_t t = prec == TN_PREC_F64 ? EL_F64 : EL_F32;
+    auto unit_ptr = [&](int32_t u) { return base + L.buf[u][final_buf[u]]; };
+    auto unit_slot = [&](int32_t u) -> const int32_t* {
+      const int32_t s = p.units[u].final_slot;
+      return s >= 0 ? slot_exp + s : nullptr;
+    };
+    RingArgs y;
+    y.A = unit_ptr(g.ya); y.B = unit_ptr(g.yb);
+    y.type = t; y.arith = arith;
+    y.m = g.m; y.n = g.n; y.k = g.ky;
+    y.sa = unit_slot(g.ya); y.sb = unit_slot(g.yb);
+    y.c_out = base + L.yt; y.dot_with = nullptr; y.partials = nullptr;
+    TN_HIP(launch_ring(y, stream));
+    RingArgs x = y;
+    x.A = unit_ptr(g.xa); x.B = unit_ptr(g.xb);
+    x.k = g.kx;
+    x.sa = unit_slot(g.xa); x.sb = unit_slot(g.xb);
+    x.c_out = nullptr; x.dot_with = base + L.yt;
+    x.partials = reinterpret_cast<double*>(base + L.partials);
+    TN_HIP(launch_ring(x, stream));
+    TN_HIP(launch_finalize(state, nullptr, nullptr, x.partials, L.n_partials, stream));
+  }
+  TN_HIP(hipMemcpyAsync(out, &state->result, sizeof(tn_result), hipMemcpyDeviceToHost, stream));
+  TN_HIP(hipStreamSynchronize(stream));
+#undef TN_HIP
+  if (out->status != TN_OK) {
+    err = "non-finite value in the inputs or an intermediate";
+    return out->status;
+  }
+  return TN_OK;
+}
+
+}  // namespace tn

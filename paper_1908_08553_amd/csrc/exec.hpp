@@ -1,0 +1,44 @@
+// Executor: turns a plan plus device pointers into kernel launches.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace tn {
+
+// Byte offsets of every region of the caller's workspace for one
+// (plan, precision) pair.  All offsets are 256-byte aligned.
+struct Layout {
+  size_t state = 0, state_bytes = 0;
+  size_t descs = 0;
+  size_t raw = 0;                    // host sites are copied here
+  size_t s64 = 0, s32 = 0, shi = 0, slo = 0;
+  size_t buf[4][2] = {};             // unit boundary ping-pong buffers
+  size_t buf_bytes[4] = {};
+  size_t yt = 0, yt_bytes = 0;       // ring: C^T E
+  size_t partials = 0;
+  int64_t n_partials = 0;
+  size_t total = 0;
+  std::vector<int64_t> s_off;        // staged offset of each step
+  std::vector<int32_t> out_type;     // ElemType of each step's output
+};
+
+Layout make_layout(const Plan& p, int32_t prec);
+
+// Algorithmic HBM bytes of one contraction (boundary in + out per step, sites,
+// ring operands) for the element sizes `prec` uses.
+int64_t algorithmic_bytes(const Plan& p, int32_t prec);
+
+tn_status contract(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
+                   void* ws, size_t ws_bytes, hipStream_t stream, tn_result* out,
+                   std::string& err);
+
+}  // namespace tn

@@ -1,0 +1,400 @@
+// Generic HIP kernels for gfx950: site staging, single-site absorption on the
+// vector ALUs (any K, N, pre, post), the quadrant-ring product with a fused
+// float64 dot, and the final assembly of sign / exponent / log|Z|.
+//
+// Each absorption step computes out[pre][N][post] = sum_k in[pre][k][post] *
+// S[k][N]: the paper's pairwise contraction of the boundary with one site,
+// done by folding both into matrices (paper §6: tensors folded into matrices
+// and multiplied).  The boundary's leg order is chosen by the planner so the
+// shared legs are always adjacent and the contiguous axis ("post") is never
+// permuted, so reads and writes stream.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace tn {
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ inline int32_t exp_of(double m) {
+  if (!(m == m) || m > 1.7976931348623157e308) return kExpBad;
+  if (m == 0.0) return kExpZero;
+  int e;
+  (void)frexp(m, &e);
+  return e;
+}
+
+__device__ inline int32_t shift_of(const int32_t* slot) {
+  if (!slot) return 0;
+  const int32_t e = *slot;
+  return (e == kExpZero || e == kExpBad) ? 0 : e;
+}
+
+// bf16 round-to-nearest-even of a finite float, as its 16 high bits
+__device__ inline uint16_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ inline float bf16_float(uint16_t b) {
+  return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+template <typename T>
+__device__ inline T wave_max(T v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ inline int wave_or(int v) {
+  for (int off = 32; off > 0; off >>= 1) v |= __shfl_xor(v, off);
+  return v;
+}
+
+// block-wide max of |x| and "any non-finite"; result valid in thread 0
+template <typename T>
+__device__ inline void block_max_bad(T& m, int& bad) {
+  __shared__ double sm[kBlock / 64];
+  __shared__ int sb[kBlock / 64];
+  m = wave_max(m);
+  bad = wave_or(bad);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) { sm[w] = static_cast<double>(m); sb[w] = bad; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = sm[0];
+    int bb = sb[0];
+    for (int k = 1; k < static_cast<int>(blockDim.x >> 6); ++k) { mm = fmax(mm, sm[k]); bb |= sb[k]; }
+    m = static_cast<T>(mm);
+    bad = bb;
+  }
+}
+
+// ---------------------------------------------------------------- staging
+__global__ __launch_bounds__(kBlock) void stage_kernel(const StageDesc* __restrict__ descs,
+                                                       StagedArrays st, DevState* state) {
+  const StageDesc d = descs[blockIdx.x];
+  int32_t* slot_exp = reinterpret_cast<int32_t*>(state + 1);
+  int32_t* site_exp = slot_exp + state->n_slots;
+  int32_t* site_bad = site_exp + state->n_steps;
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < state->n_slots; i += blockDim.x) slot_exp[i] = kExpZero;
+    if (threadIdx.x == 0) state->flags = 0;
+  }
+  double m = 0.0;
+  int bad = 0;
+  for (int64_t q = threadIdx.x; q < d.entries; q += blockDim.x) {
+    const double x = d.src[q];
+    bad |= !isfinite(x);
+    m = fmax(m, fabs(x));
+  }
+  block_max_bad(m, bad);
+  __shared__ int32_t sh_e;
+  if (threadIdx.x == 0) {
+    const int32_t e = bad ? 0 : exp_of(m);
+    sh_e = (e == kExpZero) ? 0 : e;
+    site_exp[blockIdx.x] = sh_e;
+    site_bad[blockIdx.x] = bad;
+  }
+  __syncthreads();
+  const int32_t e = sh_e;
+  for (int64_t q = threadIdx.x; q < d.entries; q += blockDim.x) {
+    int64_t rem = q, off = 0;
+    for (int a = d.ndim - 1; a >= 0; --a) {
+      const int64_t i = rem % d.dims[a];
+      rem /= d.dims[a];
+      off += i * d.cstride[a];
+    }
+    const double x = ldexp(d.src[off], -e);
+    const float f = static_cast<float>(x);
+    const uint16_t hi = bf16_bits(f);
+    const uint16_t lo = bf16_bits(f - bf16_float(hi));
+    st.s64[d.s_off + q] = x;
+    st.s32[d.s_off + q] = f;
+    st.shi[d.s_off + q] = hi;
+    st.slo[d.s_off + q] = lo;
+    if (d.init_dst) {
+      if (d.init_double) static_cast<double*>(d.init_dst)[q] = x;
+      else static_cast<float*>(d.init_dst)[q] = f;
+    }
+  }
+}
+
+// -------------------------------------------------------------- absorption
+// One thread per (pre, post) fiber; N processed in chunks of 16 accumulators.
+template <typename Tin, typename Tc, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void absorb_generic(
+    const Tin* __restrict__ in, Tc* __restrict__ out, const Tc* __restrict__ S,
+    const uint16_t* __restrict__ shi, const uint16_t* __restrict__ slo, int64_t pre, int32_t K,
+    int32_t N, int64_t post, const int32_t* scale_slot, int32_t* max_slot,
+    int32_t* flags) {
+  const int64_t f = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nf = pre * post;
+  const int32_t shift = shift_of(scale_slot);
+  Tc mx = 0;
+  int bad = 0;
+  if (f < nf) {
+    const int64_t p = f / post, q = f - p * post;
+    const Tin* src = in + p * K * post + q;
+    Tc* dst = out + p * N * post + q;
+    for (int32_t n0 = 0; n0 < N; n0 += 16) {
+      const int32_t nn = min(16, N - n0);
+      Tc acc[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j] = 0;
+      for (int32_t k = 0; k < K; ++k) {
+        const Tc x = static_cast<Tc>(ldexp(static_cast<Tc>(src[k * post]), -shift));
+        if constexpr (SPLIT) {
+          const uint16_t xh_b = bf16_bits(static_cast<float>(x));
+          const float xh = bf16_float(xh_b);
+          const float xl = bf16_float(bf16_bits(static_cast<float>(x) - xh));
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            if (j < nn) {
+              const float sh = bf16_float(shi[k * N + n0 + j]);
+              const float sl = bf16_float(slo[k * N + n0 + j]);
+              float a = acc[j];
+              a = fmaf(xl, sh, a);
+              a = fmaf(xh, sl, a);
+              a = fmaf(xh, sh, a);
+              acc[j] = a;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (j < nn) acc[j] = fma(x, S[k * N + n0 + j], acc[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if (j < nn) {
+          dst[(n0 + j) * post] = acc[j];
+          bad |= !isfinite(acc[j]);
+          mx = fmax(mx, fabs(acc[j]));
+        }
+      }
+    }
+  }
+  if (max_slot) {
+    block_max_bad(mx, bad);
+    if (threadIdx.x == 0) {
+      const int32_t e = bad ? kExpBad : exp_of(static_cast<double>(mx));
+      if (e != kExpZero) atomicMax(max_slot, e);
+      if (bad) atomicOr(flags, 1);
+    }
+  }
+}
+
+// ------------------------------------------------------------------- ring
+// 64x64 output tile per block, 256 threads, 4x4 outputs per thread.
+constexpr int kRT = 64, kRK = 16;
+
+template <typename T, bool SPLIT>
+__global__ __launch_bounds__(kBlock) void ring_generic(
+    const T* __restrict__ A, const T* __restrict__ B, int64_t m, int64_t n, int64_t k,
+    const int32_t* sa, const int32_t* sb, T* __restrict__ C, const T* __restrict__ dotw,
+    double* __restrict__ partials) {
+  __shared__ T As[kRK][kRT];
+  __shared__ T Bs[kRK][kRT];
+  const int64_t m0 = static_cast<int64_t>(blockIdx.y) * kRT;
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * kRT;
+  const int32_t ea = shift_of(sa), eb = shift_of(sb);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+  for (int64_t k0 = 0; k0 < k; k0 += kRK) {
+    for (int e = threadIdx.x; e < kRK * kRT; e += blockDim.x) {
+      const int kk = e / kRT, ii = e % kRT;
+      const int64_t kg = k0 + kk;
+      As[kk][ii] = (kg < k && m0 + ii < m) ? static_cast<T>(ldexp(A[kg * m + m0 + ii], -ea)) : T(0);
+      Bs[kk][ii] = (kg < k && n0 + ii < n) ? static_cast<T>(ldexp(B[kg * n + n0 + ii], -eb)) : T(0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kRK; ++kk) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const T a = As[kk][ty * 4 + i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const T b = Bs[kk][tx * 4 + j];
+          if constexpr (SPLIT) {
+            const float ah = bf16_float(bf16_bits(a)), al = bf16_float(bf16_bits(a - ah));
+            const float bh = bf16_float(bf16_bits(b)), bl = bf16_float(bf16_bits(b - bh));
+            float s = acc[i][j];
+            s = fmaf(al, bh, s);
+            s = fmaf(ah, bl, s);
+            s = fmaf(ah, bh, s);
+            acc[i][j] = s;
+          } else {
+            acc[i][j] = fma(a, b, acc[i][j]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t gi = m0 + ty * 4 + i;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t gj = n0 + tx * 4 + j;
+      if (gi < m && gj < n) {
+        if (dotw) part += static_cast<double>(acc[i][j]) * static_cast<double>(dotw[gi * n + gj]);
+        else C[gi * n + gj] = acc[i][j];
+      }
+    }
+  }
+  if (dotw) {
+    // fixed-order block reduction (deterministic)
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+      if (static_cast<int>(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+  }
+}
+
+// --------------------------------------------------------------- finalize
+__global__ __launch_bounds__(kBlock) void finalize_kernel(DevState* state, const double* scalar,
+                                                          const double* partials, int64_t np) {
+  __shared__ double red[kBlock];
+  double s = 0.0;
+  if (partials) {
+    for (int64_t i = threadIdx.x; i < np; i += blockDim.x) s += partials[i];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (static_cast<int>(threadIdx.x) < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double mval = partials ? red[0] : *scalar;
+  const int32_t* slot_exp = reinterpret_cast<const int32_t*>(state + 1);
+  const int32_t* site_exp = slot_exp + state->n_slots;
+  const int32_t* site_bad = site_exp + state->n_steps;
+  int64_t E = 0;
+  int bad = state->flags & 1;
+  for (int i = 0; i < state->n_slots; ++i) {
+    const int32_t e = slot_exp[i];
+    if (e == kExpBad) bad = 1;
+    else if (e != kExpZero) E += e;
+  }
+  for (int i = 0; i < state->n_steps; ++i) {
+    E += site_exp[i];
+    bad |= site_bad[i];
+  }
+  if (!isfinite(mval)) bad = 1;
+  tn_result r;
+  r.status = bad ? TN_ENONFINITE : TN_OK;
+  if (bad || mval == 0.0) {
+    r.sign = 0;
+    r.mantissa = 0.0;
+    r.exp2_sum = 0;
+    r.log_abs = bad ? __builtin_nan("") : -INFINITY;
+    r.value = bad ? __builtin_nan("") : 0.0;
+  } else {
+    int em;
+    const double f = frexp(mval, &em);
+    r.sign = f > 0 ? 1 : -1;
+    r.mantissa = f;
+    r.exp2_sum = E + em;
+    r.log_abs = static_cast<double>(r.exp2_sum) * 0.69314718055994530942 + log(fabs(f));
+    const int64_t ex = r.exp2_sum;
+    r.value = (ex > 2000) ? r.sign * INFINITY
+                          : (ex < -2000 ? 0.0 * r.sign : ldexp(f, static_cast<int>(ex)));
+  }
+  state->result = r;
+}
+
+}  // namespace
+
+hipError_t launch_stage(const StageDesc* descs, int32_t n_steps, StagedArrays st, DevState* state,
+                        hipStream_t stream) {
+  if (n_steps <= 0) return hipSuccess;
+  hipLaunchKernelGGL(stage_kernel, dim3(n_steps), dim3(kBlock), 0, stream, descs, st, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_absorb(const AbsorbArgs& a, const StagedArrays& st, DevState* state,
+                         hipStream_t stream) {
+  const int64_t nf = a.pre * a.post;
+  const int64_t blocks = (nf + kBlock - 1) / kBlock;
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > INT_MAX || a.K > INT_MAX || a.N > INT_MAX) return hipErrorInvalidValue;
+  int32_t* flags = &state->flags;
+  const int32_t K = static_cast<int32_t>(a.K), N = static_cast<int32_t>(a.N);
+  dim3 g(static_cast<uint32_t>(blocks)), b(kBlock);
+  if (a.out_type == EL_F64) {
+    if (a.in_type == EL_F64)
+      hipLaunchKernelGGL((absorb_generic<double, double, false>), g, b, 0, stream,
+                         static_cast<const double*>(a.in), static_cast<double*>(a.out),
+                         st.s64 + a.s_off, st.shi + a.s_off, st.slo + a.s_off, a.pre, K, N,
+                         a.post, a.scale_slot, a.max_slot, flags);
+    else
+      hipLaunchKernelGGL((absorb_generic<float, double, false>), g, b, 0, stream,
+                         static_cast<const float*>(a.in), static_cast<double*>(a.out),
+                         st.s64 + a.s_off, st.shi + a.s_off, st.slo + a.s_off, a.pre, K, N,
+                         a.post, a.scale_slot, a.max_slot, flags);
+  } else if (a.arith == AR_BF16X3) {
+    hipLaunchKernelGGL((absorb_generic<float, float, true>), g, b, 0, stream,
+                       static_cast<const float*>(a.in), static_cast<float*>(a.out),
+                       st.s32 + a.s_off, st.shi + a.s_off, st.slo + a.s_off, a.pre, K, N, a.post,
+                       a.scale_slot, a.max_slot, flags);
+  } else {
+    hipLaunchKernelGGL((absorb_generic<float, float, false>), g, b, 0, stream,
+                       static_cast<const float*>(a.in), static_cast<float*>(a.out),
+                       st.s32 + a.s_off, st.shi + a.s_off, st.slo + a.s_off, a.pre, K, N, a.post,
+                       a.scale_slot, a.max_slot, flags);
+  }
+  return hipGetLastError();
+}
+
+int64_t ring_partials(int64_t m, int64_t n) {
+  return ((m + kRT - 1) / kRT) * ((n + kRT - 1) / kRT);
+}
+
+hipError_t launch_ring(const RingArgs& a, hipStream_t stream) {
+  const int64_t gx = (a.n + kRT - 1) / kRT, gy = (a.m + kRT - 1) / kRT;
+  if (gx > INT_MAX || gy > 65535) return hipErrorInvalidValue;
+  dim3 g(static_cast<uint32_t>(gx), static_cast<uint32_t>(gy)), b(kBlock);
+  if (a.type == EL_F64) {
+    hipLaunchKernelGGL((ring_generic<double, false>), g, b, 0, stream,
+                       static_cast<const double*>(a.A), static_cast<const double*>(a.B), a.m, a.n,
+                       a.k, a.sa, a.sb, static_cast<double*>(a.c_out),
+                       static_cast<const double*>(a.dot_with), a.partials);
+  } else if (a.arith == AR_BF16X3) {
+    hipLaunchKernelGGL((ring_generic<float, true>), g, b, 0, stream,
+                       static_cast<const float*>(a.A), static_cast<const float*>(a.B), a.m, a.n,
+                       a.k, a.sa, a.sb, static_cast<float*>(a.c_out),
+                       static_cast<const float*>(a.dot_with), a.partials);
+  } else {
+    hipLaunchKernelGGL((ring_generic<float, false>), g, b, 0, stream,
+                       static_cast<const float*>(a.A), static_cast<const float*>(a.B), a.m, a.n,
+                       a.k, a.sa, a.sb, static_cast<float*>(a.c_out),
+                       static_cast<const float*>(a.dot_with), a.partials);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(DevState* state, const double* scalar, const float*,
+                           const double* partials, int64_t n_partials, hipStream_t stream) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kBlock), 0, stream, state, scalar, partials,
+                     n_partials);
+  return hipGetLastError();
+}
+
+}  // namespace tn

@@ -1,0 +1,68 @@
+// Host-side launchers for the HIP kernels (defined in kernels.hip).
+// Every launcher checks nothing itself: the executor validates shapes and
+// buffer sizes against the plan before calling.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+#include "device.hpp"
+
+namespace tn {
+
+enum ElemType : int32_t { EL_F32 = 0, EL_F64 = 1 };
+enum Arith : int32_t { AR_F64 = 0, AR_F32 = 1, AR_BF16X3 = 2 };
+
+struct StagedArrays {
+  double* s64;
+  float* s32;
+  uint16_t* shi;   // bf16 bits of the high part
+  uint16_t* slo;   // bf16 bits of the low part
+};
+
+hipError_t launch_stage(const StageDesc* descs, int32_t n_steps, StagedArrays st,
+                        DevState* state, hipStream_t stream);
+
+// out[pre][N][post] = sum_k (2^-shift * in[pre][k][post]) * S[k][n]
+struct AbsorbArgs {
+  const void* in;
+  void* out;
+  int32_t in_type, out_type;   // ElemType
+  int32_t arith;               // Arith: F64 needs out F64; F32/BF16X3 compute in float
+                               // unless out_type is F64 (then double)
+  int64_t pre, K, N, post;
+  int64_t s_off;               // staged offset of S (K x N)
+  const int32_t* scale_slot;   // nullable
+  int32_t* max_slot;           // nullable
+};
+
+hipError_t launch_absorb(const AbsorbArgs& a, const StagedArrays& st, DevState* state,
+                         hipStream_t stream);
+
+// Ring: C = 2^-(sa+sb) * A^T B with A [k][m], B [k][n].  If dot_with != nullptr
+// the tile results are multiplied elementwise with dot_with [m][n] and summed
+// in float64 into partials[tile]; otherwise C is stored to c_out [m][n].
+struct RingArgs {
+  const void* A;
+  const void* B;
+  int32_t type;                // ElemType of A, B, c_out, dot_with
+  int32_t arith;
+  int64_t m, n, k;
+  const int32_t* sa;
+  const int32_t* sb;
+  void* c_out;
+  const void* dot_with;
+  double* partials;
+};
+
+// Number of float64 partials a fused-dot ring launch writes.
+int64_t ring_partials(int64_t m, int64_t n);
+hipError_t launch_ring(const RingArgs& a, hipStream_t stream);
+
+// Writes state->result from the final scalar (or the sum of `n_partials`
+// partials), the site exponents and the rescale slots.
+hipError_t launch_finalize(DevState* state, const double* scalar, const float* scalar_f,
+                           const double* partials, int64_t n_partials, hipStream_t stream);
+
+}  // namespace tn

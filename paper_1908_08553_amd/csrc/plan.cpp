@@ -1,0 +1,356 @@
+// Contraction planner: column sweep, quadrant ring and the minimal-bottleneck
+// heuristic (paper §4, Fig. 2).  See plan.hpp for the step model.
+//
+// Readings where the paper is silent or garbled:
+//  * Dimension rule: the printed d(B) = d(A1) d(A2) / d(x) counts the shared
+//    legs once; both operands carry them, so the planner tracks legs and the
+//    result is d(A1) d(A2) / d(x)^2.
+//  * The row scheme runs sequentially as a sweep: the boundary absorbs one
+//    site at a time, columns left to right, rows top to bottom, in a frame.
+//    The absorbed site's shared legs (local up, local left) are replaced in
+//    place by its new legs (local right, then local down).
+//  * Quadrant split rows [0,h) / [h,R), columns [0,w) / [w,C), default
+//    h = ceil(R/2), w = ceil(C/2).  Each quadrant is swept from its outer
+//    lattice corner; legs that leave a quadrant stay on its tensor.
+//  * Heuristic key: (bottleneck entries, total flops, candidate index) over
+//    sweep, transposed sweep, then quadrant splits (h, w) in lexicographic
+//    order.
+//  * Exact power-of-two rescale points after every local column except the
+//    last column of a sweep order (which ends in the scalar).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstdio>
+#include <sstream>
+
+namespace tn {
+namespace {
+
+struct Overflow {};
+
+inline int64_t mul(int64_t a, int64_t b) {
+  int64_t r;
+  if (__builtin_mul_overflow(a, b, &r)) throw Overflow{};
+  return r;
+}
+inline int64_t add(int64_t a, int64_t b) {
+  int64_t r;
+  if (__builtin_add_overflow(a, b, &r)) throw Overflow{};
+  return r;
+}
+
+// local legs L, U, R, Dn of each frame, as canonical legs
+const int32_t kFrameLegs[5][4] = {
+    {LEG_LEFT, LEG_UP, LEG_RIGHT, LEG_DOWN},   // ID
+    {LEG_UP, LEG_LEFT, LEG_DOWN, LEG_RIGHT},   // T   (transpose)
+    {LEG_RIGHT, LEG_UP, LEG_LEFT, LEG_DOWN},   // MH  (mirror left-right)
+    {LEG_RIGHT, LEG_DOWN, LEG_LEFT, LEG_UP},   // MHV (mirror both)
+    {LEG_LEFT, LEG_DOWN, LEG_RIGHT, LEG_UP},   // MV  (mirror top-bottom)
+};
+const char* kFrameName[5] = {"ID", "T", "MH", "MHV", "MV"};
+const char* kOrderName[3] = {"COLSWEEP", "QUADRANT", "HEURISTIC"};
+
+struct Lattice {
+  int32_t R, C;
+  const std::vector<int32_t>* h;
+  const std::vector<int32_t>* v;
+  int32_t nh() const { return R * (C - 1); }
+  // bond ids: h(r,c) -> r*(C-1)+c ; v(r,c) -> nh + r*C + c
+  int32_t hid(int32_t r, int32_t c) const { return r * (C - 1) + c; }
+  int32_t vid(int32_t r, int32_t c) const { return nh() + r * C + c; }
+  int64_t dim(int32_t b) const { return b < nh() ? (*h)[b] : (*v)[b - nh()]; }
+  bool has(int32_t r, int32_t c, int32_t leg) const {
+    switch (leg) {
+      case LEG_LEFT: return c > 0;
+      case LEG_UP: return r > 0;
+      case LEG_RIGHT: return c < C - 1;
+      default: return r < R - 1;
+    }
+  }
+  int32_t bond(int32_t r, int32_t c, int32_t leg) const {
+    switch (leg) {
+      case LEG_LEFT: return hid(r, c - 1);
+      case LEG_UP: return vid(r - 1, c);
+      case LEG_RIGHT: return hid(r, c);
+      default: return vid(r, c);
+    }
+  }
+  // canonical axis index of `leg` at (r,c): count of present legs before it
+  int32_t axis(int32_t r, int32_t c, int32_t leg) const {
+    int32_t a = 0;
+    for (int32_t l = 0; l < leg; ++l) a += has(r, c, l) ? 1 : 0;
+    return a;
+  }
+  void site_of(int32_t frame, int32_t i, int32_t j, int32_t& r, int32_t& c) const {
+    switch (frame) {
+      case FRAME_ID: r = i; c = j; break;
+      case FRAME_T: r = j; c = i; break;
+      case FRAME_MH: r = i; c = C - 1 - j; break;
+      case FRAME_MHV: r = R - 1 - i; c = C - 1 - j; break;
+      default: r = R - 1 - i; c = j; break;
+    }
+  }
+};
+
+// Sweep local rows [0,nh) x cols [0,nw) of `frame`; appends steps, returns the
+// final boundary legs.
+std::vector<int32_t> sweep(const Lattice& L, int32_t unit, int32_t frame, int32_t nh,
+                           int32_t nw, bool rescale_last, int32_t& slot,
+                           std::vector<Step>& steps) {
+  std::vector<int32_t> bnd;
+  const int32_t* fl = kFrameLegs[frame];
+  for (int32_t j = 0; j < nw; ++j) {
+    for (int32_t i = 0; i < nh; ++i) {
+      int32_t r, c;
+      L.site_of(frame, i, j, r, c);
+      Step s;
+      s.unit = unit; s.r = r; s.c = c; s.col = j; s.last_col = (j == nw - 1);
+      s.site_entries = 1;
+      for (int32_t leg = 0; leg < 4; ++leg)
+        if (L.has(r, c, leg)) s.site_entries = mul(s.site_entries, L.dim(L.bond(r, c, leg)));
+      // shared legs sit at local L / U, new legs at local R then Dn
+      std::vector<int32_t> shared_legs, new_legs;
+      for (int32_t loc : {0, 1})
+        if (L.has(r, c, fl[loc])) shared_legs.push_back(fl[loc]);
+      for (int32_t loc : {2, 3})
+        if (L.has(r, c, fl[loc])) new_legs.push_back(fl[loc]);
+      if (i == 0 && j == 0) {
+        s.kind = STEP_INIT;
+        int64_t n = 1;
+        for (int32_t leg : new_legs) {
+          s.perm[s.nperm++] = L.axis(r, c, leg);
+          n = mul(n, L.dim(L.bond(r, c, leg)));
+          bnd.push_back(L.bond(r, c, leg));
+        }
+        s.pre = s.K = s.post = 1;
+        s.N = n;
+        s.out = n;
+        s.flops = 0;
+        steps.push_back(s);
+        if (nh == 1 && (j < nw - 1 || rescale_last)) steps.back().rescale = slot++;
+        continue;
+      }
+      // locate the shared bonds in the boundary; they must be adjacent
+      size_t k0 = bnd.size();
+      for (int32_t leg : shared_legs) {
+        auto it = std::find(bnd.begin(), bnd.end(), L.bond(r, c, leg));
+        k0 = std::min(k0, static_cast<size_t>(it - bnd.begin()));
+      }
+      const size_t nk = shared_legs.size();
+      int64_t pre = 1, post = 1, K = 1, N = 1;
+      for (size_t a = 0; a < k0; ++a) pre = mul(pre, L.dim(bnd[a]));
+      for (size_t a = k0 + nk; a < bnd.size(); ++a) post = mul(post, L.dim(bnd[a]));
+      for (size_t a = k0; a < k0 + nk; ++a) {
+        const int32_t b = bnd[a];
+        int32_t leg = -1;
+        for (int32_t l : shared_legs)
+          if (L.bond(r, c, l) == b) leg = l;
+        if (leg < 0) throw std::runtime_error("shared legs are not adjacent");
+        s.perm[s.nperm++] = L.axis(r, c, leg);
+        K = mul(K, L.dim(b));
+      }
+      std::vector<int32_t> nb(bnd.begin(), bnd.begin() + k0);
+      for (int32_t leg : new_legs) {
+        s.perm[s.nperm++] = L.axis(r, c, leg);
+        N = mul(N, L.dim(L.bond(r, c, leg)));
+        nb.push_back(L.bond(r, c, leg));
+      }
+      nb.insert(nb.end(), bnd.begin() + k0 + nk, bnd.end());
+      bnd.swap(nb);
+      s.kind = STEP_ABSORB;
+      s.pre = pre; s.K = K; s.N = N; s.post = post;
+      s.out = mul(mul(pre, N), post);
+      s.flops = mul(mul(s.out, K), 2);
+      steps.push_back(s);
+      if (i == nh - 1 && (j < nw - 1 || rescale_last)) steps.back().rescale = slot++;
+    }
+  }
+  return bnd;
+}
+
+void finish(Plan& p) {
+  p.peak = 0; p.flops = 0; p.moved = 0; p.total_site_entries = 0;
+  for (size_t k = 0; k < p.steps.size(); ++k) {
+    Step& s = p.steps[k];
+    p.peak = std::max(p.peak, s.out);
+    p.flops = add(p.flops, s.flops);
+    p.total_site_entries = add(p.total_site_entries, s.site_entries);
+    if (s.kind == STEP_ABSORB) {
+      p.moved = add(p.moved, add(mul(mul(s.pre, s.K), s.post), s.out));
+      const Step& prev = p.steps[k - 1];
+      if (prev.unit == s.unit && prev.rescale >= 0) s.scale_in = prev.rescale;
+    }
+  }
+  for (size_t u = 0; u < p.units.size(); ++u) {
+    Unit& U = p.units[u];
+    U.final_slot = p.steps[U.first_step + U.n_steps - 1].rescale;
+  }
+  if (p.has_ring) {
+    const int64_t mn = mul(p.ring.m, p.ring.n);
+    p.peak = std::max(p.peak, mn);
+    p.flops = add(p.flops, p.ring.flops);
+    for (const Unit& U : p.units) p.moved = add(p.moved, U.result);
+    p.moved = add(p.moved, mul(mn, 2));
+  }
+}
+
+void plan_colsweep(const Lattice& L, int32_t transpose, int32_t requested, Plan& p) {
+  p.requested = requested;
+  p.order = TN_ORDER_COLSWEEP;
+  p.transpose = transpose;
+  p.qh = p.qw = 0;
+  p.has_ring = false;
+  p.units.clear();
+  p.steps.clear();
+  const int32_t frame = transpose ? FRAME_T : FRAME_ID;
+  const int32_t nh = transpose ? L.C : L.R, nw = transpose ? L.R : L.C;
+  int32_t slot = 0;
+  sweep(L, 0, frame, nh, nw, false, slot, p.steps);
+  Unit U;
+  U.frame = frame; U.rows = nh; U.cols = nw; U.result = 1;
+  U.first_step = 0; U.n_steps = static_cast<int32_t>(p.steps.size());
+  p.units.push_back(U);
+  p.slots = slot;
+  finish(p);
+}
+
+void plan_quadrant(const Lattice& L, int32_t h, int32_t w, int32_t requested, Plan& p) {
+  p.requested = requested;
+  p.order = TN_ORDER_QUADRANT;
+  p.transpose = 0;
+  p.qh = h; p.qw = w;
+  p.units.clear();
+  p.steps.clear();
+  const int32_t R = L.R, C = L.C;
+  const int32_t frames[4] = {FRAME_ID, FRAME_MH, FRAME_MHV, FRAME_MV};
+  const int32_t nhs[4] = {h, h, R - h, R - h};
+  const int32_t nws[4] = {w, C - w, C - w, w};
+  int32_t slot = 0;
+  for (int32_t u = 0; u < 4; ++u) {
+    Unit U;
+    U.frame = frames[u]; U.rows = nhs[u]; U.cols = nws[u];
+    U.first_step = static_cast<int32_t>(p.steps.size());
+    std::vector<int32_t> legs = sweep(L, u, frames[u], nhs[u], nws[u], true, slot, p.steps);
+    U.n_steps = static_cast<int32_t>(p.steps.size()) - U.first_step;
+    U.result = 1;
+    for (int32_t b : legs) U.result = mul(U.result, L.dim(b));
+    p.units.push_back(U);
+  }
+  Ring& g = p.ring;
+  g.xa = 0; g.xb = 1; g.ya = 3; g.yb = 2;
+  g.kx = 1; g.ky = 1; g.m = 1; g.n = 1;
+  for (int32_t r = 0; r < h; ++r) g.kx = mul(g.kx, L.dim(L.hid(r, w - 1)));
+  for (int32_t r = h; r < R; ++r) g.ky = mul(g.ky, L.dim(L.hid(r, w - 1)));
+  for (int32_t c = 0; c < w; ++c) g.m = mul(g.m, L.dim(L.vid(h - 1, c)));
+  for (int32_t c = w; c < C; ++c) g.n = mul(g.n, L.dim(L.vid(h - 1, c)));
+  const int64_t mn = mul(g.m, g.n);
+  g.flops = add(add(mul(mul(mn, g.kx), 2), mul(mul(mn, g.ky), 2)), mul(mn, 2));
+  p.has_ring = true;
+  p.slots = slot;
+  finish(p);
+}
+
+}  // namespace
+
+tn_status build_plan(const tn_grid& grid, int32_t order, int32_t quad_h, int32_t quad_w,
+                     Plan& out, std::string& err) {
+  const int32_t R = grid.rows, C = grid.cols;
+  if (R < 1 || C < 1) { err = "rows and cols must be >= 1"; return TN_EINVAL; }
+  if (static_cast<int64_t>(R) * C > (1 << 20)) { err = "lattice too large"; return TN_EINVAL; }
+  Plan p;
+  p.rows = R; p.cols = C;
+  p.hdim.resize(static_cast<size_t>(R) * (C - 1));
+  p.vdim.resize(static_cast<size_t>(R - 1) * C);
+  for (size_t k = 0; k < p.hdim.size(); ++k) p.hdim[k] = grid.hdim ? grid.hdim[k] : grid.D;
+  for (size_t k = 0; k < p.vdim.size(); ++k) p.vdim[k] = grid.vdim ? grid.vdim[k] : grid.D;
+  if ((!grid.hdim || !grid.vdim) && grid.D < 1 && (!p.hdim.empty() || !p.vdim.empty())) {
+    err = "D must be >= 1"; return TN_EINVAL;
+  }
+  for (int32_t d : p.hdim) if (d < 1) { err = "bond dimension < 1"; return TN_EINVAL; }
+  for (int32_t d : p.vdim) if (d < 1) { err = "bond dimension < 1"; return TN_EINVAL; }
+  Lattice L{R, C, &p.hdim, &p.vdim};
+  try {
+    if (order == TN_ORDER_COLSWEEP) {
+      plan_colsweep(L, 0, TN_ORDER_COLSWEEP, p);
+    } else if (order == TN_ORDER_QUADRANT) {
+      if (R < 2 || C < 2) { err = "QUADRANT needs >= 2 rows and >= 2 columns"; return TN_EINVAL; }
+      const int32_t h = quad_h ? quad_h : (R + 1) / 2;
+      const int32_t w = quad_w ? quad_w : (C + 1) / 2;
+      if (h < 1 || h > R - 1 || w < 1 || w > C - 1) { err = "quadrant split out of range"; return TN_EINVAL; }
+      plan_quadrant(L, h, w, TN_ORDER_QUADRANT, p);
+    } else if (order == TN_ORDER_HEURISTIC) {
+      bool have = false;
+      Plan best;
+      auto consider = [&](Plan& cand) {
+        if (!have || cand.peak < best.peak || (cand.peak == best.peak && cand.flops < best.flops)) {
+          best = cand;   // earlier candidates win exact ties
+          have = true;
+        }
+      };
+      for (int32_t t = 0; t < 2; ++t) {
+        Plan cand = p;
+        try { plan_colsweep(L, t, TN_ORDER_HEURISTIC, cand); consider(cand); } catch (Overflow&) {}
+      }
+      if (R >= 2 && C >= 2) {
+        for (int32_t h = 1; h < R; ++h)
+          for (int32_t w = 1; w < C; ++w) {
+            Plan cand = p;
+            try { plan_quadrant(L, h, w, TN_ORDER_HEURISTIC, cand); consider(cand); } catch (Overflow&) {}
+          }
+      }
+      if (!have) throw Overflow{};
+      p = best;
+    } else {
+      err = "unknown order";
+      return TN_EINVAL;
+    }
+  } catch (Overflow&) {
+    err = "plan integers overflow int64";
+    return TN_EOVERFLOW;
+  }
+  out = std::move(p);
+  return TN_OK;
+}
+
+namespace {
+void ints(std::ostringstream& os, const std::vector<int32_t>& v) {
+  if (v.empty()) { os << "-"; return; }
+  for (size_t k = 0; k < v.size(); ++k) os << (k ? "," : "") << v[k];
+}
+}  // namespace
+
+std::string plan_text(const Plan& p) {
+  std::ostringstream os;
+  os << "tnplan v1 rows=" << p.rows << " cols=" << p.cols
+     << " requested=" << kOrderName[p.requested] << " order=" << kOrderName[p.order]
+     << " transpose=" << p.transpose << " quad=" << p.qh << "," << p.qw << "\n";
+  os << "hdim "; ints(os, p.hdim); os << "\n";
+  os << "vdim "; ints(os, p.vdim); os << "\n";
+  for (size_t u = 0; u < p.units.size(); ++u) {
+    const Unit& U = p.units[u];
+    os << "unit " << u << " frame=" << kFrameName[U.frame] << " rows=" << U.rows
+       << " cols=" << U.cols << " result=" << U.result << "\n";
+  }
+  for (size_t k = 0; k < p.steps.size(); ++k) {
+    const Step& s = p.steps[k];
+    os << "step " << k << " unit=" << s.unit << " site=" << s.r << "," << s.c
+       << " kind=" << (s.kind == STEP_INIT ? "INIT" : "ABSORB") << " pre=" << s.pre
+       << " K=" << s.K << " N=" << s.N << " post=" << s.post << " perm=";
+    if (s.nperm == 0) os << "-";
+    for (int32_t a = 0; a < s.nperm; ++a) os << (a ? "." : "") << s.perm[a];
+    os << " out=" << s.out << " flops=" << s.flops << " rescale=";
+    if (s.rescale >= 0) os << s.rescale; else os << "-";
+    os << "\n";
+  }
+  if (p.has_ring) {
+    const Ring& g = p.ring;
+    os << "ring xa=" << g.xa << " xb=" << g.xb << " ya=" << g.ya << " yb=" << g.yb
+       << " m=" << g.m << " n=" << g.n << " kx=" << g.kx << " ky=" << g.ky
+       << " flops=" << g.flops << "\n";
+  }
+  os << "totals steps=" << p.steps.size() << " slots=" << p.slots << " peak=" << p.peak
+     << " flops=" << p.flops << " moved=" << p.moved << "\n";
+  return os.str();
+}
+
+}  // namespace tn

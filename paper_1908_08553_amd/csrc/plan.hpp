@@ -1,0 +1,75 @@
+// Contraction planner for the planar square lattice (host only, integers only).
+//
+// Paper §4: a planar network is contracted by pairwise, sequential
+// contractions; each intermediate has a "dimension" (entry count) and the
+// largest one, the bottleneck, fixes memory and operation count.  Two orders
+// are described -- along rows from one edge to the other, and quadrants
+// contracted from the edges to the middle, leaving a ring of four tensors --
+// and the heuristic keeps the order with the smallest bottleneck.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tn.h"
+
+namespace tn {
+
+enum : int32_t { LEG_LEFT = 0, LEG_UP = 1, LEG_RIGHT = 2, LEG_DOWN = 3 };
+enum : int32_t { FRAME_ID = 0, FRAME_T = 1, FRAME_MH = 2, FRAME_MHV = 3, FRAME_MV = 4 };
+enum : int32_t { STEP_INIT = 0, STEP_ABSORB = 1 };
+
+// One pairwise step: out[pre][N][post] = sum_k in[pre][k][post] * S[k][n], where
+// S is the site tensor folded to (K legs, N legs) by the axis permutation perm.
+// An INIT step copies the folded site into the unit's boundary (pre=K=post=1).
+struct Step {
+  int32_t unit = 0, r = 0, c = 0, kind = STEP_INIT;
+  int64_t pre = 1, K = 1, N = 1, post = 1, out = 1, flops = 0;
+  int32_t nperm = 0;
+  int32_t perm[4] = {0, 0, 0, 0};
+  int32_t rescale = -1;    // exponent slot measured after this step
+  int32_t scale_in = -1;   // slot whose exponent scales this step's input
+  int32_t col = 0;         // local column within the unit's sweep
+  int32_t last_col = 0;    // 1 when the step is in the unit's last column
+  int64_t site_entries = 1;
+};
+
+struct Unit {
+  int32_t frame = FRAME_ID;
+  int32_t rows = 0, cols = 0;   // local (swept) extent
+  int64_t result = 1;           // entries of the unit's final tensor
+  int32_t first_step = 0, n_steps = 0;
+  int32_t final_slot = -1;      // rescale slot of the last step (-1: none)
+};
+
+// Closing the quadrant ring: X = A^T B with A = unit xa as [kx][m], B = unit
+// xb as [kx][n]; Yt = C^T E with C = unit ya as [ky][m], E = unit yb as
+// [ky][n]; Z = sum over (i,j) of X[i][j] * Yt[i][j].
+struct Ring {
+  int32_t xa = 0, xb = 1, ya = 3, yb = 2;
+  int64_t m = 1, n = 1, kx = 1, ky = 1, flops = 0;
+};
+
+struct Plan {
+  int32_t rows = 0, cols = 0;
+  std::vector<int32_t> hdim, vdim;
+  int32_t requested = TN_ORDER_COLSWEEP, order = TN_ORDER_COLSWEEP;
+  int32_t transpose = 0, qh = 0, qw = 0;
+  std::vector<Unit> units;
+  std::vector<Step> steps;
+  bool has_ring = false;
+  Ring ring;
+  int32_t slots = 0;
+  int64_t peak = 0, flops = 0, moved = 0;
+  int64_t total_site_entries = 0;
+};
+
+// Builds a plan.  Returns TN_OK, TN_EINVAL or TN_EOVERFLOW (message in err).
+tn_status build_plan(const tn_grid& grid, int32_t order, int32_t quad_h,
+                     int32_t quad_w, Plan& out, std::string& err);
+
+// Canonical text: identical bytes for identical plans.
+std::string plan_text(const Plan& p);
+
+}  // namespace tn

@@ -1,0 +1,85 @@
+"""The C++ planner behind the C ABI emits byte-identical canonical plan text
+to the oracle's independent planner, and its statistics match the plan."""
+import numpy as np
+import pytest
+
+import paper_1908_08553_amd as tn
+from oracle import plan as P
+
+ORDERS = [P.COLSWEEP, P.QUADRANT, P.HEURISTIC]
+
+
+def both(rows, cols, D=2, hdim=None, vdim=None, order=P.COLSWEEP, qh=0, qw=0):
+    ref = P.plan_text(P.plan_grid(rows, cols, D, hdim, vdim, order, qh, qw))
+    got = tn.tn_plan_text(tn.tn_plan_grid(rows, cols, D, hdim, vdim, order, qh, qw))
+    return got, ref
+
+
+@pytest.mark.parametrize("rows", range(1, 17))
+@pytest.mark.parametrize("cols", [1, 2, 3, 5, 8, 12, 16])
+def test_uniform_plans_bit_exact(rows, cols):
+    for D in (1, 2, 3, 4, 5):
+        for order in ORDERS:
+            if order == P.QUADRANT and (rows < 2 or cols < 2):
+                continue
+            if order == P.HEURISTIC and rows * cols > 100 and D > 2:
+                continue
+            got, ref = both(rows, cols, D, order=order)
+            assert got == ref
+
+
+def test_nonuniform_plans_bit_exact():
+    rng = np.random.default_rng(0)
+    for _ in range(60):
+        rows, cols = (int(x) for x in rng.integers(1, 7, size=2))
+        h = rng.integers(1, 5, size=(rows, max(cols - 1, 0)))
+        v = rng.integers(1, 5, size=(max(rows - 1, 0), cols))
+        for order in ORDERS:
+            if order == P.QUADRANT and (rows < 2 or cols < 2):
+                continue
+            got, ref = both(rows, cols, 0, h, v, order)
+            assert got == ref
+
+
+def test_every_quadrant_split_bit_exact():
+    for h in range(1, 7):
+        for w in range(1, 5):
+            got, ref = both(7, 5, 3, order=P.QUADRANT, qh=h, qw=w)
+            assert got == ref
+
+
+def test_stats_match_oracle_plan():
+    for (L, D, order) in [(10, 4, P.COLSWEEP), (12, 4, P.COLSWEEP), (12, 4, P.QUADRANT),
+                          (10, 4, P.HEURISTIC), (13, 4, P.HEURISTIC)]:
+        ref = P.plan_grid(L, L, D, order=order)
+        info = tn.tn_plan_stats(tn.tn_plan_grid(L, L, D, order=order))
+        assert info["peak_entries"] == ref.peak
+        assert info["flops"] == ref.flops
+        assert info["moved_entries"] == ref.moved
+        assert info["n_steps"] == len(ref.steps)
+        assert info["order"] == ref.order
+    info = tn.tn_plan_stats(tn.tn_plan_grid(12, 12, 4))
+    assert info["peak_entries"] == 4 ** 13 and info["flops"] == 226112132128
+
+
+def test_errors():
+    with pytest.raises(tn.TnError) as e:
+        tn.tn_plan_grid(0, 3, 2)
+    assert e.value.status == tn.TN_EINVAL
+    with pytest.raises(tn.TnError) as e:
+        tn.tn_plan_grid(3, 3, 0)
+    assert e.value.status == tn.TN_EINVAL
+    with pytest.raises(tn.TnError) as e:
+        tn.tn_plan_grid(1, 5, 2, order=P.QUADRANT)
+    assert e.value.status == tn.TN_EINVAL
+    with pytest.raises(tn.TnError) as e:
+        tn.tn_plan_grid(4, 4, 2, order=P.QUADRANT, quad_h=4)
+    assert e.value.status == tn.TN_EINVAL
+    with pytest.raises(tn.TnError) as e:
+        tn.tn_plan_grid(40, 40, 64)
+    assert e.value.status == tn.TN_EOVERFLOW
+    with pytest.raises(tn.TnError) as e:
+        tn.tn_plan_grid(3, 3, 2, order=7)
+    assert e.value.status == tn.TN_EINVAL
+    with pytest.raises(tn.TnError):
+        tn.tn_plan_grid(3, 3, 2, hdim=[[2, 0], [2, 2], [2, 2]])
