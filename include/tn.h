@@ -148,6 +148,28 @@ tn_status tn_contract_grid(const tn_plan* plan, const double* const* sites,
                            void* workspace, size_t ws_bytes, void* hip_stream,
                            tn_result* out);
 
+/* ------------------------------------------------------------ profiling
+ * Kernel timing for roofline accounting.  While enabled, every kernel launch
+ * the library issues is bracketed by HIP events on the stream it is launched
+ * on; after each contraction the elapsed times are added to per-kernel
+ * totals together with the kernel's algorithmic bytes and flops (boundary in
+ * + out + site for an absorption step; operands + result for a ring
+ * product).  Process-wide, guarded by a mutex; costs two event records per
+ * launch, so leave it off outside measurements.                            */
+typedef struct {
+  char    name[48];        /* kernel variant, e.g. "absorb_mfma_f32"          */
+  int64_t launches;
+  double  total_ms;        /* sum of event-measured durations                 */
+  double  bytes;           /* sum of algorithmic HBM bytes                    */
+  double  flops;           /* sum of algorithmic flops                        */
+} tn_kernel_stat;
+
+/* Start (clear and enable) or stop recording.                               */
+tn_status tn_profile_enable(int32_t on);
+/* Copy up to `cap` per-kernel totals into `out`; *n receives the number of
+ * kernels recorded (may exceed cap).                                        */
+tn_status tn_profile_read(tn_kernel_stat* out, int32_t cap, int32_t* n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,12 +36,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [HIPCC, *COMMON]
-        if src.endswith(".hip"):
-            cmd += ["-x", "hip", *DEVICE_FLAGS]
-        else:
-            cmd += ["-D__HIP_PLATFORM_AMD__"]
-        cmd += ["-c", src, "-o", obj]
+        cmd = [HIPCC, *COMMON, "-x", "hip", *DEVICE_FLAGS, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

@@ -121,4 +121,23 @@ tn_status tn_contract_grid(const tn_plan* plan, const double* const* sites,
   }
 }
 
+tn_status tn_profile_enable(int32_t on) {
+  try {
+    tn::profile_enable(on != 0);
+    return TN_OK;
+  } catch (...) {
+    return fail(TN_EINVAL, "tn_profile_enable failed");
+  }
+}
+
+tn_status tn_profile_read(tn_kernel_stat* out, int32_t cap, int32_t* n) {
+  try {
+    if (!n || (cap > 0 && !out)) return fail(TN_EINVAL, "null argument");
+    *n = tn::profile_read(out, cap);
+    return TN_OK;
+  } catch (...) {
+    return fail(TN_EINVAL, "tn_profile_read failed");
+  }
+}
+
 }  // extern "C"

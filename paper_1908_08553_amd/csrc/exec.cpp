@@ -12,6 +12,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 namespace tn {
 namespace {
@@ -31,7 +33,80 @@ int32_t step_out_type(const Plan& p, const Step& s, int32_t prec) {
 
 const char* hip_msg(hipError_t e) { return hipGetErrorString(e); }
 
+struct KStat { int64_t launches = 0; double ms = 0, bytes = 0, flops = 0; };
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::map<std::string, KStat> g_prof;
+
 }  // namespace
+
+void profile_enable(bool on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.clear();
+  g_prof_on = on;
+}
+
+bool profile_on() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  return g_prof_on;
+}
+
+int32_t profile_read(tn_kernel_stat* out, int32_t cap) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  int32_t k = 0;
+  for (const auto& kv : g_prof) {
+    if (out && k < cap) {
+      tn_kernel_stat& o = out[k];
+      std::memset(&o, 0, sizeof(o));
+      std::strncpy(o.name, kv.first.c_str(), sizeof(o.name) - 1);
+      o.launches = kv.second.launches;
+      o.total_ms = kv.second.ms;
+      o.bytes = kv.second.bytes;
+      o.flops = kv.second.flops;
+    }
+    ++k;
+  }
+  return k;
+}
+
+LaunchTimer::LaunchTimer(hipStream_t s) : stream_(s), on_(profile_on()) {}
+
+LaunchTimer::~LaunchTimer() {
+  for (Rec& r : recs_) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  if (pending_) (void)hipEventDestroy(pending_);
+}
+
+void LaunchTimer::before() {
+  if (!on_) return;
+  if (hipEventCreate(&pending_) != hipSuccess) { pending_ = nullptr; return; }
+  (void)hipEventRecord(pending_, stream_);
+}
+
+void LaunchTimer::after(const char* name, double bytes, double flops) {
+  if (!on_ || !pending_) return;
+  Rec r{pending_, nullptr, name, bytes, flops};
+  pending_ = nullptr;
+  if (hipEventCreate(&r.b) != hipSuccess) { (void)hipEventDestroy(r.a); return; }
+  (void)hipEventRecord(r.b, stream_);
+  recs_.push_back(r);
+}
+
+void LaunchTimer::flush() {
+  if (!on_) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (Rec& r : recs_) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+    KStat& k = g_prof[r.name];
+    k.launches += 1;
+    k.ms += ms;
+    k.bytes += r.bytes;
+    k.flops += r.flops;
+  }
+}
 
 Layout make_layout(const Plan& p, int32_t prec) {
   Layout L;
@@ -185,8 +260,11 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
   StagedArrays sa{reinterpret_cast<double*>(base + L.s64), reinterpret_cast<float*>(base + L.s32),
                   reinterpret_cast<uint16_t*>(base + L.shi),
                   reinterpret_cast<uint16_t*>(base + L.slo)};
+  LaunchTimer timer(stream);
+  timer.before();
   TN_HIP(launch_stage(reinterpret_cast<const StageDesc*>(base + L.descs),
                       static_cast<int32_t>(nsteps), sa, state, stream));
+  timer.after("stage", 8.0 * 2 * static_cast<double>(p.total_site_entries), 0.0);
 
   const int32_t arith = prec == TN_PREC_F64 ? AR_F64 : (prec == TN_PREC_F32 ? AR_F32 : AR_BF16X3);
   std::vector<int32_t> final_buf(p.units.size(), 0);
@@ -205,7 +283,15 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
       a.s_off = L.s_off[k];
       a.scale_slot = s.scale_in >= 0 ? slot_exp + s.scale_in : nullptr;
       a.max_slot = s.rescale >= 0 ? slot_exp + s.rescale : nullptr;
-      TN_HIP(launch_absorb(a, sa, state, stream));
+      const char* kname = "";
+      timer.before();
+      TN_HIP(launch_absorb(a, sa, state, stream, &kname));
+      const double sb = (a.out_type == EL_F64 || prec == TN_PREC_F64) ? 8.0 : (prec == TN_PREC_BF16X3 ? 4.0 : 4.0);
+      timer.after(kname,
+                  static_cast<double>(s.pre * s.K * s.post) * elem_bytes(a.in_type) +
+                      static_cast<double>(s.out) * elem_bytes(a.out_type) +
+                      static_cast<double>(s.K * s.N) * sb,
+                  static_cast<double>(s.flops));
       c = 1 - c;
     }
     // a rescale on the INIT step of a one-row unit is measured here
@@ -214,7 +300,9 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
 
   if (!p.has_ring) {
     const double* scalar = reinterpret_cast<const double*>(base + L.buf[0][final_buf[0]]);
+    timer.before();
     TN_HIP(launch_finalize(state, scalar, nullptr, nullptr, 0, stream));
+    timer.after("finalize", 0.0, 0.0);
   } else {
     const Ring& g = p.ring;
     const int32_t t = prec == TN_PREC_F64 ? EL_F64 : EL_F32;
@@ -229,18 +317,29 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
     y.m = g.m; y.n = g.n; y.k = g.ky;
     y.sa = unit_slot(g.ya); y.sb = unit_slot(g.yb);
     y.c_out = base + L.yt; y.dot_with = nullptr; y.partials = nullptr;
-    TN_HIP(launch_ring(y, stream));
+    const char* kname = "";
+    const double es = (t == EL_F64) ? 8.0 : 4.0;
+    timer.before();
+    TN_HIP(launch_ring(y, stream, &kname));
+    timer.after(kname, es * static_cast<double>(g.ky * (g.m + g.n) + g.m * g.n),
+                2.0 * static_cast<double>(g.m * g.n * g.ky));
     RingArgs x = y;
     x.A = unit_ptr(g.xa); x.B = unit_ptr(g.xb);
     x.k = g.kx;
     x.sa = unit_slot(g.xa); x.sb = unit_slot(g.xb);
     x.c_out = nullptr; x.dot_with = base + L.yt;
     x.partials = reinterpret_cast<double*>(base + L.partials);
-    TN_HIP(launch_ring(x, stream));
+    timer.before();
+    TN_HIP(launch_ring(x, stream, &kname));
+    timer.after(kname, es * static_cast<double>(g.kx * (g.m + g.n) + g.m * g.n),
+                2.0 * static_cast<double>(g.m * g.n * g.kx) + 2.0 * static_cast<double>(g.m * g.n));
+    timer.before();
     TN_HIP(launch_finalize(state, nullptr, nullptr, x.partials, L.n_partials, stream));
+    timer.after("finalize", 0.0, 0.0);
   }
   TN_HIP(hipMemcpyAsync(out, &state->result, sizeof(tn_result), hipMemcpyDeviceToHost, stream));
   TN_HIP(hipStreamSynchronize(stream));
+  timer.flush();
 #undef TN_HIP
   if (out->status != TN_OK) {
     err = "non-finite value in the inputs or an intermediate";

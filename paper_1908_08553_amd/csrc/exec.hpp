@@ -37,6 +37,28 @@ Layout make_layout(const Plan& p, int32_t prec);
 // ring operands) for the element sizes `prec` uses.
 int64_t algorithmic_bytes(const Plan& p, int32_t prec);
 
+// Launch timing for roofline accounting (see tn_profile_enable in tn.h).
+void profile_enable(bool on);
+int32_t profile_read(tn_kernel_stat* out, int32_t cap);
+bool profile_on();
+
+// Records HIP events around launches on one stream and folds the elapsed
+// times into the process-wide totals once the stream has been synchronised.
+class LaunchTimer {
+ public:
+  explicit LaunchTimer(hipStream_t s);
+  ~LaunchTimer();
+  void before();
+  void after(const char* name, double bytes, double flops);
+  void flush();   // call after the stream is synchronised
+ private:
+  struct Rec { hipEvent_t a, b; const char* name; double bytes, flops; };
+  hipStream_t stream_;
+  bool on_;
+  std::vector<Rec> recs_;
+  hipEvent_t pending_ = nullptr;
+};
+
 tn_status contract(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                    void* ws, size_t ws_bytes, hipStream_t stream, tn_result* out,
                    std::string& err);

@@ -330,7 +330,7 @@ hipError_t launch_stage(const StageDesc* descs, int32_t n_steps, StagedArrays st
 }
 
 hipError_t launch_absorb(const AbsorbArgs& a, const StagedArrays& st, DevState* state,
-                         hipStream_t stream) {
+                         hipStream_t stream, const char** kname) {
   const int64_t nf = a.pre * a.post;
   const int64_t blocks = (nf + kBlock - 1) / kBlock;
   if (blocks <= 0) return hipSuccess;
@@ -339,6 +339,7 @@ hipError_t launch_absorb(const AbsorbArgs& a, const StagedArrays& st, DevState* 
   const int32_t K = static_cast<int32_t>(a.K), N = static_cast<int32_t>(a.N);
   dim3 g(static_cast<uint32_t>(blocks)), b(kBlock);
   if (a.out_type == EL_F64) {
+    *kname = a.in_type == EL_F64 ? "absorb_valu_f64" : "absorb_valu_f32_to_f64";
     if (a.in_type == EL_F64)
       hipLaunchKernelGGL((absorb_generic<double, double, false>), g, b, 0, stream,
                          static_cast<const double*>(a.in), static_cast<double*>(a.out),
@@ -350,11 +351,13 @@ hipError_t launch_absorb(const AbsorbArgs& a, const StagedArrays& st, DevState* 
                          st.s64 + a.s_off, st.shi + a.s_off, st.slo + a.s_off, a.pre, K, N,
                          a.post, a.scale_slot, a.max_slot, flags);
   } else if (a.arith == AR_BF16X3) {
+    *kname = "absorb_valu_bf16x3";
     hipLaunchKernelGGL((absorb_generic<float, float, true>), g, b, 0, stream,
                        static_cast<const float*>(a.in), static_cast<float*>(a.out),
                        st.s32 + a.s_off, st.shi + a.s_off, st.slo + a.s_off, a.pre, K, N, a.post,
                        a.scale_slot, a.max_slot, flags);
   } else {
+    *kname = "absorb_valu_f32";
     hipLaunchKernelGGL((absorb_generic<float, float, false>), g, b, 0, stream,
                        static_cast<const float*>(a.in), static_cast<float*>(a.out),
                        st.s32 + a.s_off, st.shi + a.s_off, st.slo + a.s_off, a.pre, K, N, a.post,
@@ -367,10 +370,11 @@ int64_t ring_partials(int64_t m, int64_t n) {
   return ((m + kRT - 1) / kRT) * ((n + kRT - 1) / kRT);
 }
 
-hipError_t launch_ring(const RingArgs& a, hipStream_t stream) {
+hipError_t launch_ring(const RingArgs& a, hipStream_t stream, const char** kname) {
   const int64_t gx = (a.n + kRT - 1) / kRT, gy = (a.m + kRT - 1) / kRT;
   if (gx > INT_MAX || gy > 65535) return hipErrorInvalidValue;
   dim3 g(static_cast<uint32_t>(gx), static_cast<uint32_t>(gy)), b(kBlock);
+  *kname = a.type == EL_F64 ? "ring_valu_f64" : (a.arith == AR_BF16X3 ? "ring_valu_bf16x3" : "ring_valu_f32");
   if (a.type == EL_F64) {
     hipLaunchKernelGGL((ring_generic<double, false>), g, b, 0, stream,
                        static_cast<const double*>(a.A), static_cast<const double*>(a.B), a.m, a.n,

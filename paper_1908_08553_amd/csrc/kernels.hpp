@@ -37,8 +37,9 @@ struct AbsorbArgs {
   int32_t* max_slot;           // nullable
 };
 
+// *kname receives the name of the kernel variant launched.
 hipError_t launch_absorb(const AbsorbArgs& a, const StagedArrays& st, DevState* state,
-                         hipStream_t stream);
+                         hipStream_t stream, const char** kname);
 
 // Ring: C = 2^-(sa+sb) * A^T B with A [k][m], B [k][n].  If dot_with != nullptr
 // the tile results are multiplied elementwise with dot_with [m][n] and summed
@@ -58,7 +59,7 @@ struct RingArgs {
 
 // Number of float64 partials a fused-dot ring launch writes.
 int64_t ring_partials(int64_t m, int64_t n);
-hipError_t launch_ring(const RingArgs& a, hipStream_t stream);
+hipError_t launch_ring(const RingArgs& a, hipStream_t stream, const char** kname);
 
 // Writes state->result from the final scalar (or the sum of `n_partials`
 // partials), the site exponents and the rescale slots.
