@@ -100,6 +100,26 @@ def roofline(ks, prec):
             "share_of_gpu_time": dom["total_ms"] / sum(k["total_ms"] for k in ks)}
 
 
+def copy_calibration(torch, mib=256, reps=20):
+    """A plain device-to-device copy of `mib` MiB (torch's copy kernel): the
+    achievable HBM rate, and the reference dispatch for scaling rocprofv3's
+    FETCH_SIZE / WRITE_SIZE counters."""
+    n = mib * (1 << 20) // 4
+    x = torch.rand(n, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"bytes_per_launch": 2 * n * 4, "avg_ms": ms, "gbs": 2 * n * 4 / (ms * 1e-3) / 1e9}
+
+
 def cpu_baseline():
     """The FP64 oracle, unchanged, on the first two columns (24 steps) of the
     same 12x12 D=4 column sweep; GFLOP/s from the plan's flops."""
@@ -128,6 +148,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-legs", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also time a plain 256 MiB device copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -138,6 +160,7 @@ def main():
     import paper_1908_08553_amd as tn
     torch.cuda.set_device(0)
 
+    calib = copy_calibration(torch) if args.calibrate else None
     head = run_leg(tn, torch, 12, 12, 4, "uniform", 0, tn.TN_ORDER_COLSWEEP, "f32",
                    args.steps, args.warmup, profile=True)
     log(f"headline: {head['ms']:.3f} ms/contraction, {head['gflops']:.1f} GFLOP/s")
@@ -154,7 +177,7 @@ def main():
         for name, r, c, D, kind, order, prec in spec:
             leg = run_leg(tn, torch, r, c, D, kind, 0, order, prec, max(3, args.steps // 4),
                           1, profile=True)
-            leg["roofline"] = roofline(leg.pop("kernels"), prec)
+            leg["roofline"] = roofline(leg["kernels"], prec)
             legs[name] = leg
             log(f"{name}: {leg['ms']:.3f} ms, {leg['gflops']:.1f} GFLOP/s, log|Z|={leg['log_abs']:.10f}")
         ref = legs["sweep12_f64"]["log_abs"]
@@ -186,6 +209,8 @@ def main():
         "kernels": head_kernels,
         "legs": legs,
     }
+    if calib:
+        line["copy_calibration"] = calib
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

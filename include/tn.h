@@ -148,6 +148,15 @@ tn_status tn_contract_grid(const tn_plan* plan, const double* const* sites,
                            void* workspace, size_t ws_bytes, void* hip_stream,
                            tn_result* out);
 
+/* Library-wide options (process-wide; not for concurrent change during a
+ * contraction).
+ *   TN_OPT_KERNEL_IMPL : 0 = matrix-core (MFMA) kernels for absorption steps
+ *                        and ring products wherever the shape allows,
+ *                        vector-ALU kernels elsewhere;
+ *                        1 = vector-ALU kernels only (reference path).      */
+#define TN_OPT_KERNEL_IMPL 0
+tn_status tn_set_option(int32_t option, int64_t value);
+
 /* ------------------------------------------------------------ profiling
  * Kernel timing for roofline accounting.  While enabled, every kernel launch
  * the library issues is bracketed by HIP events on the stream it is launched

@@ -12,6 +12,7 @@ from ._native import (  # noqa: F401
     TN_ORDER_COLSWEEP, TN_ORDER_QUADRANT, TN_ORDER_HEURISTIC,
     TN_PREC_F64, TN_PREC_F32, TN_PREC_BF16X3,
     TnError, Plan, Result, lib, library_path,
-    tn_plan_grid, tn_plan_stats, tn_plan_text, tn_contract_grid,
+    tn_plan_grid, tn_plan_stats, tn_plan_text, tn_contract_grid, tn_set_option,
+    TN_OPT_KERNEL_IMPL,
     plan_grid, contract_grid, device_sites, workspace_for,
 )

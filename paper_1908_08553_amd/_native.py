@@ -62,6 +62,10 @@ lib.tn_plan_text.restype = C.c_int32
 lib.tn_plan_text.argtypes = [_P, C.c_char_p, C.POINTER(C.c_size_t)]
 lib.tn_plan_free.restype = None
 lib.tn_plan_free.argtypes = [_P]
+lib.tn_set_option.restype = C.c_int32
+lib.tn_set_option.argtypes = [C.c_int32, C.c_int64]
+lib.tn_profile_enable.restype = C.c_int32
+lib.tn_profile_enable.argtypes = [C.c_int32]
 lib.tn_contract_grid.restype = C.c_int32
 lib.tn_contract_grid.argtypes = [_P, C.POINTER(C.c_void_p), C.c_int32, C.c_int32, _P,
                                  C.c_size_t, _P, C.POINTER(tn_result)]
@@ -170,6 +174,13 @@ def tn_contract_grid(plan: Plan, site_ptrs: Sequence[int], sites_on_device: bool
         return Result.from_c(out)
     _check(status)
     return Result.from_c(out)
+
+
+TN_OPT_KERNEL_IMPL = 0
+
+
+def tn_set_option(option: int, value: int) -> None:
+    _check(lib.tn_set_option(option, value))
 
 
 # ------------------------------------------------------------ conveniences

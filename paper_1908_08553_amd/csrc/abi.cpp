@@ -8,6 +8,7 @@
 #include <string>
 
 #include "exec.hpp"
+#include "kernels.hpp"
 #include "plan.hpp"
 #include "tn.h"
 
@@ -119,6 +120,15 @@ tn_status tn_contract_grid(const tn_plan* plan, const double* const* sites,
   } catch (...) {
     return fail(TN_EDEVICE, "unknown error");
   }
+}
+
+tn_status tn_set_option(int32_t option, int64_t value) {
+  if (option == TN_OPT_KERNEL_IMPL) {
+    if (value < 0 || value > 1) return fail(TN_EINVAL, "TN_OPT_KERNEL_IMPL must be 0 or 1");
+    tn::set_absorb_policy(static_cast<int32_t>(value));
+    return TN_OK;
+  }
+  return fail(TN_EINVAL, "unknown option");
 }
 
 tn_status tn_profile_enable(int32_t on) {

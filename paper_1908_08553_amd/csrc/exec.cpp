@@ -319,8 +319,9 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
     y.c_out = base + L.yt; y.dot_with = nullptr; y.partials = nullptr;
     const char* kname = "";
     const double es = (t == EL_F64) ? 8.0 : 4.0;
+    int64_t n_part = 0;
     timer.before();
-    TN_HIP(launch_ring(y, stream, &kname));
+    TN_HIP(launch_ring(y, stream, &kname, &n_part));
     timer.after(kname, es * static_cast<double>(g.ky * (g.m + g.n) + g.m * g.n),
                 2.0 * static_cast<double>(g.m * g.n * g.ky));
     RingArgs x = y;
@@ -330,11 +331,11 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
     x.c_out = nullptr; x.dot_with = base + L.yt;
     x.partials = reinterpret_cast<double*>(base + L.partials);
     timer.before();
-    TN_HIP(launch_ring(x, stream, &kname));
+    TN_HIP(launch_ring(x, stream, &kname, &n_part));
     timer.after(kname, es * static_cast<double>(g.kx * (g.m + g.n) + g.m * g.n),
                 2.0 * static_cast<double>(g.m * g.n * g.kx) + 2.0 * static_cast<double>(g.m * g.n));
     timer.before();
-    TN_HIP(launch_finalize(state, nullptr, nullptr, x.partials, L.n_partials, stream));
+    TN_HIP(launch_finalize(state, nullptr, nullptr, x.partials, n_part, stream));
     timer.after("finalize", 0.0, 0.0);
   }
   TN_HIP(hipMemcpyAsync(out, &state->result, sizeof(tn_result), hipMemcpyDeviceToHost, stream));

@@ -329,8 +329,17 @@ hipError_t launch_stage(const StageDesc* descs, int32_t n_steps, StagedArrays st
   return hipGetLastError();
 }
 
+namespace {
+int32_t g_absorb_policy = 0;
+}
+
+void set_absorb_policy(int32_t policy) { g_absorb_policy = policy; }
+int32_t absorb_policy() { return g_absorb_policy; }
+
 hipError_t launch_absorb(const AbsorbArgs& a, const StagedArrays& st, DevState* state,
                          hipStream_t stream, const char** kname) {
+  if (g_absorb_policy == 0 && absorb_mfma_supported(a))
+    return launch_absorb_mfma(a, st, state, stream, kname);
   const int64_t nf = a.pre * a.post;
   const int64_t blocks = (nf + kBlock - 1) / kBlock;
   if (blocks <= 0) return hipSuccess;
@@ -367,10 +376,17 @@ hipError_t launch_absorb(const AbsorbArgs& a, const StagedArrays& st, DevState* 
 }
 
 int64_t ring_partials(int64_t m, int64_t n) {
+  // the vector-ALU kernel's 64 x 64 tiles give the larger count
   return ((m + kRT - 1) / kRT) * ((n + kRT - 1) / kRT);
 }
 
-hipError_t launch_ring(const RingArgs& a, hipStream_t stream, const char** kname) {
+hipError_t launch_ring(const RingArgs& a, hipStream_t stream, const char** kname,
+                       int64_t* n_partials) {
+  if (g_absorb_policy == 0 && ring_mfma_supported(a)) {
+    *n_partials = ring_mfma_partials(a.m, a.n);
+    return launch_ring_mfma(a, stream, kname);
+  }
+  *n_partials = ((a.m + kRT - 1) / kRT) * ((a.n + kRT - 1) / kRT);
   const int64_t gx = (a.n + kRT - 1) / kRT, gy = (a.m + kRT - 1) / kRT;
   if (gx > INT_MAX || gy > 65535) return hipErrorInvalidValue;
   dim3 g(static_cast<uint32_t>(gx), static_cast<uint32_t>(gy)), b(kBlock);

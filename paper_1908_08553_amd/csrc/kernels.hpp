@@ -37,6 +37,16 @@ struct AbsorbArgs {
   int32_t* max_slot;           // nullable
 };
 
+// MFMA absorption (absorb_mfma.hip): K, N <= 16 and post % 16 == 0 or post == 1.
+bool absorb_mfma_supported(const AbsorbArgs& a);
+hipError_t launch_absorb_mfma(const AbsorbArgs& a, const StagedArrays& st, DevState* state,
+                              hipStream_t stream, const char** kname);
+
+// Kernel policy: 0 = matrix-core kernels where the shape allows, 1 = vector-ALU
+// kernels only (absorption and ring products).
+void set_absorb_policy(int32_t policy);
+int32_t absorb_policy();
+
 // *kname receives the name of the kernel variant launched.
 hipError_t launch_absorb(const AbsorbArgs& a, const StagedArrays& st, DevState* state,
                          hipStream_t stream, const char** kname);
@@ -57,9 +67,16 @@ struct RingArgs {
   double* partials;
 };
 
-// Number of float64 partials a fused-dot ring launch writes.
+// Upper bound on the float64 partials a fused-dot ring launch writes.
 int64_t ring_partials(int64_t m, int64_t n);
-hipError_t launch_ring(const RingArgs& a, hipStream_t stream, const char** kname);
+// *n_partials receives the number of partials this launch writes (fused dot).
+hipError_t launch_ring(const RingArgs& a, hipStream_t stream, const char** kname,
+                       int64_t* n_partials);
+
+// MFMA ring products (ring_mfma.hip): m % 4 == 0 and n % 4 == 0.
+bool ring_mfma_supported(const RingArgs& a);
+int64_t ring_mfma_partials(int64_t m, int64_t n);
+hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** kname);
 
 // Writes state->result from the final scalar (or the sum of `n_partials`
 // partials), the site exponents and the rescale slots.

@@ -19,12 +19,16 @@ pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
-@pytest.fixture(scope="module")
-def tn():
+@pytest.fixture(scope="module", params=["mfma", "valu"])
+def tn(request):
+    """The library, with absorption on the matrix cores where the step shape
+    allows ("mfma") or forced onto the vector-ALU kernels ("valu")."""
     import torch
     assert torch.cuda.is_available()
     import paper_1908_08553_amd as tn
-    return tn
+    tn.tn_set_option(tn.TN_OPT_KERNEL_IMPL, 0 if request.param == "mfma" else 1)
+    yield tn
+    tn.tn_set_option(tn.TN_OPT_KERNEL_IMPL, 0)
 
 
 def ising_gold():
