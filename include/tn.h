@@ -52,10 +52,14 @@ typedef int32_t tn_status;
  *              products and an elementwise dot.
  *   HEURISTIC: the candidate (sweep, transposed sweep, every quadrant split)
  *              with the smallest bottleneck tensor; ties broken by total flops,
- *              then by enumeration order (§4, last paragraph).                 */
-#define TN_ORDER_COLSWEEP  0
-#define TN_ORDER_QUADRANT  1
-#define TN_ORDER_HEURISTIC 2
+ *              then by enumeration order (§4, last paragraph).
+ *   SWEEP_AUTO: the column sweep in the orientation with the smaller bottleneck
+ *              (boundary along the shorter side); ties: fewer flops, then
+ *              untransposed.  Planned order is COLSWEEP.                      */
+#define TN_ORDER_COLSWEEP   0
+#define TN_ORDER_QUADRANT   1
+#define TN_ORDER_HEURISTIC  2
+#define TN_ORDER_SWEEP_AUTO 3
 
 /* Arithmetic of the contraction.
  *   F64    : every step in float64.
@@ -89,7 +93,7 @@ typedef struct {
 } tn_result;
 
 typedef struct {
-  int32_t order;           /* order actually planned (never HEURISTIC)           */
+  int32_t order;           /* order actually planned (COLSWEEP or QUADRANT)      */
   int32_t transpose;       /* COLSWEEP: 1 if the sweep runs along rows           */
   int32_t quad_h, quad_w;  /* QUADRANT split (rows [0,h), cols [0,w))            */
   int32_t n_steps;         /* INIT + ABSORB steps over all units                 */
@@ -148,13 +152,62 @@ tn_status tn_contract_grid(const tn_plan* plan, const double* const* sites,
                            void* workspace, size_t ws_bytes, void* hip_stream,
                            tn_result* out);
 
+/* ------------------------------------------------------------ batching
+ * Many independent lattices contracted by one persistent launch (the paper's
+ * observable evaluations need one full contraction per local quantity, §5).
+ * Every plan must be a column-sweep plan (TN_ORDER_COLSWEEP, transposed or
+ * not).  The batch copies the plans; the caller may free them after create.
+ *
+ * One launch contracts the whole batch: workgroup b sweeps the b-th costliest
+ * lattice with all of its waves, so the dispatcher starts the largest first.
+ * Staging and the batch kernel are captured once into a hipGraph at create
+ * time and replayed by every tn_batch_run.                                 */
+typedef struct tn_batch tn_batch;
+
+typedef struct {
+  int32_t threads;         /* workgroup size: 256, 512 or 1024 (0 = default)    */
+  int32_t reserved;        /* must be 0                                        */
+} tn_batch_config;
+
+/* Workspace bytes a batch of these plans needs in `precision`.              */
+tn_status tn_batch_workspace(const tn_plan* const* plans, int32_t n, int32_t precision,
+                             size_t* bytes);
+
+/* Build device tables in `workspace` (>= tn_batch_workspace bytes, 256-byte
+ * aligned, owned by the caller and reserved for this batch until destroy)
+ * and capture the launch graph.  cfg may be NULL (defaults).  Uses the
+ * current HIP device.  Errors: TN_EINVAL (non-sweep plan, bad config),
+ * TN_ENOMEM (workspace), TN_EDEVICE.                                        */
+tn_status tn_batch_create(const tn_plan* const* plans, int32_t n, int32_t precision,
+                          const tn_batch_config* cfg, void* workspace, size_t ws_bytes,
+                          tn_batch** out);
+
+/* Contract every lattice: sites[i] is an array of rows*cols DEVICE pointers
+ * to lattice i's float64 sites (canonical legs), borrowed for the call.
+ * Writes outs[0..n-1]; blocks until done.  Returns TN_ENONFINITE if any
+ * lattice hit a non-finite value (its outs[i].status says so; the others are
+ * valid).                                                                  */
+tn_status tn_batch_run(tn_batch* batch, const double* const* const* sites, void* hip_stream,
+                       tn_result* outs);
+
+tn_status tn_batch_destroy(tn_batch* batch);
+
+/* One-shot form: create with the process-wide default configuration
+ * (TN_OPT_BATCH_THREADS), run once, destroy.                               */
+tn_status tn_contract_batch(const tn_plan* const* plans, const double* const* const* sites,
+                            int32_t n, int32_t precision, void* workspace, size_t ws_bytes,
+                            void* hip_stream, tn_result* outs);
+
 /* Library-wide options (process-wide; not for concurrent change during a
  * contraction).
  *   TN_OPT_KERNEL_IMPL : 0 = matrix-core (MFMA) kernels for absorption steps
  *                        and ring products wherever the shape allows,
  *                        vector-ALU kernels elsewhere;
- *                        1 = vector-ALU kernels only (reference path).      */
+ *                        1 = vector-ALU kernels only (reference path).
+ *   TN_OPT_BATCH_THREADS : batch workgroup size used when a tn_batch_config is
+ *                        NULL or zero (and by tn_contract_batch).            */
 #define TN_OPT_KERNEL_IMPL 0
+#define TN_OPT_BATCH_THREADS 1
 tn_status tn_set_option(int32_t option, int64_t value);
 
 /* ------------------------------------------------------------ profiling

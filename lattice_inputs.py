@@ -166,3 +166,19 @@ def make(kind: str, rows: int, cols: int, D: int = 2, seed: int = 0,
             return ising_d4(rows, cols, K)
         raise ValueError("ising networks exist for D in {2, 4}")
     raise ValueError(f"unknown input kind {kind!r}")
+
+
+def batch_mix(n: int, base_seed: int, sides=(4, 8), dims=(2, 3, 4)):
+    """A mixed batch of independent lattices: a master
+    ``default_rng(base_seed)`` draws Lh and Lw independently and uniformly
+    from ``sides`` (inclusive) and D uniformly from ``dims``; lattice i's
+    entries are i.i.d. uniform[0, 1) from ``default_rng(base_seed + 1 + i)``.
+    Returns a list of (rows, cols, D, sites)."""
+    master = np.random.default_rng(base_seed)
+    out = []
+    for i in range(n):
+        r = int(master.integers(sides[0], sides[1] + 1))
+        c = int(master.integers(sides[0], sides[1] + 1))
+        D = int(master.choice(dims))
+        out.append((r, c, D, uniform(r, c, D, base_seed + 1 + i)))
+    return out

@@ -44,8 +44,9 @@ import numpy as np
 LEFT, UP, RIGHT, DOWN = 0, 1, 2, 3
 INT64_MAX = (1 << 63) - 1
 
-COLSWEEP, QUADRANT, HEURISTIC = 0, 1, 2
-ORDER_NAMES = {COLSWEEP: "COLSWEEP", QUADRANT: "QUADRANT", HEURISTIC: "HEURISTIC"}
+COLSWEEP, QUADRANT, HEURISTIC, SWEEP_AUTO = 0, 1, 2, 3
+ORDER_NAMES = {COLSWEEP: "COLSWEEP", QUADRANT: "QUADRANT", HEURISTIC: "HEURISTIC",
+               SWEEP_AUTO: "SWEEP_AUTO"}
 
 # frame name -> (local L, U, R, Dn as canonical legs)
 FRAME_LEGS = {
@@ -332,6 +333,19 @@ def plan_grid(rows: int, cols: int, D: int = 2, hdim=None, vdim=None,
         return plan_colsweep(rows, cols, hdim, vdim, 0)
     if order == QUADRANT:
         return plan_quadrant(rows, cols, hdim, vdim, quad_h, quad_w)
+    if order == SWEEP_AUTO:
+        # the sweep orientation with the smaller bottleneck (then fewer flops,
+        # then untransposed): the boundary runs along the shorter side
+        cands = []
+        for t in (0, 1):
+            try:
+                cands.append(plan_colsweep(rows, cols, hdim, vdim, t, SWEEP_AUTO))
+            except PlanOverflow:
+                pass
+        if not cands:
+            raise PlanOverflow()
+        best = min(range(len(cands)), key=lambda k: (cands[k].peak, cands[k].flops, k))
+        return cands[best]
     if order == HEURISTIC:
         cands = []
         for t in (0, 1):

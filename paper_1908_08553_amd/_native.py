@@ -25,10 +25,10 @@ lib = C.CDLL(library_path)
 TN_OK, TN_PENDING = 0, 1
 TN_EINVAL, TN_ENOMEM, TN_EBUSY, TN_EDEVICE = -1, -2, -3, -4
 TN_ENOTFOUND, TN_ENONFINITE, TN_EOVERFLOW = -5, -6, -7
-TN_ORDER_COLSWEEP, TN_ORDER_QUADRANT, TN_ORDER_HEURISTIC = 0, 1, 2
+TN_ORDER_COLSWEEP, TN_ORDER_QUADRANT, TN_ORDER_HEURISTIC, TN_ORDER_SWEEP_AUTO = 0, 1, 2, 3
 TN_PREC_F64, TN_PREC_F32, TN_PREC_BF16X3 = 0, 1, 2
 
-_ORDERS = {"colsweep": 0, "quadrant": 1, "heuristic": 2}
+_ORDERS = {"colsweep": 0, "quadrant": 1, "heuristic": 2, "sweep_auto": 3}
 _PRECS = {"f64": 0, "f32": 1, "bf16x3": 2}
 
 
@@ -66,6 +66,22 @@ lib.tn_set_option.restype = C.c_int32
 lib.tn_set_option.argtypes = [C.c_int32, C.c_int64]
 lib.tn_profile_enable.restype = C.c_int32
 lib.tn_profile_enable.argtypes = [C.c_int32]
+class tn_batch_config(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("reserved", C.c_int32)]
+
+
+lib.tn_batch_workspace.restype = C.c_int32
+lib.tn_batch_workspace.argtypes = [C.POINTER(_P), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+lib.tn_batch_create.restype = C.c_int32
+lib.tn_batch_create.argtypes = [C.POINTER(_P), C.c_int32, C.c_int32, C.POINTER(tn_batch_config),
+                                _P, C.c_size_t, C.POINTER(_P)]
+lib.tn_batch_run.restype = C.c_int32
+lib.tn_batch_run.argtypes = [_P, C.POINTER(C.POINTER(C.c_void_p)), _P, C.POINTER(tn_result)]
+lib.tn_batch_destroy.restype = C.c_int32
+lib.tn_batch_destroy.argtypes = [_P]
+lib.tn_contract_batch.restype = C.c_int32
+lib.tn_contract_batch.argtypes = [C.POINTER(_P), C.POINTER(C.POINTER(C.c_void_p)), C.c_int32,
+                                  C.c_int32, _P, C.c_size_t, _P, C.POINTER(tn_result)]
 lib.tn_contract_grid.restype = C.c_int32
 lib.tn_contract_grid.argtypes = [_P, C.POINTER(C.c_void_p), C.c_int32, C.c_int32, _P,
                                  C.c_size_t, _P, C.POINTER(tn_result)]
@@ -177,6 +193,7 @@ def tn_contract_grid(plan: Plan, site_ptrs: Sequence[int], sites_on_device: bool
 
 
 TN_OPT_KERNEL_IMPL = 0
+TN_OPT_BATCH_THREADS = 1
 
 
 def tn_set_option(option: int, value: int) -> None:
@@ -224,3 +241,84 @@ def contract_grid(plan: Plan, sites, precision="f64", workspace=None, stream=Non
                            workspace.numel() * workspace.element_size(), stream.cuda_stream)
     del keep
     return res
+
+
+# ------------------------------------------------------------------ batches
+
+def _plan_array(plans):
+    return (C.c_void_p * len(plans))(*[p.handle.value for p in plans])
+
+
+def _site_table(site_lists):
+    rows = [(C.c_void_p * len(sl))(*[t.data_ptr() for t in sl]) for sl in site_lists]
+    table = (C.POINTER(C.c_void_p) * len(rows))(*[C.cast(r, C.POINTER(C.c_void_p)) for r in rows])
+    return table, rows
+
+
+def tn_batch_workspace(plans, precision) -> int:
+    if isinstance(precision, str):
+        precision = _PRECS[precision]
+    n = C.c_size_t(0)
+    _check(lib.tn_batch_workspace(_plan_array(plans), len(plans), precision, C.byref(n)))
+    return n.value
+
+
+class Batch:
+    """A tn_batch: device tables + captured launch graph for a fixed list of
+    column-sweep plans.  `threads` of 0 uses the library default (see
+    tn_set_option)."""
+
+    def __init__(self, plans, precision="f32", threads=0, device="cuda"):
+        import torch
+        if isinstance(precision, str):
+            precision = _PRECS[precision]
+        self.plans = list(plans)
+        self.precision = precision
+        nbytes = tn_batch_workspace(self.plans, precision)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        cfg = tn_batch_config(threads, 0)
+        h = C.c_void_p()
+        _check(lib.tn_batch_create(_plan_array(self.plans), len(self.plans), precision,
+                                   C.byref(cfg), C.c_void_p(self.workspace.data_ptr()),
+                                   self.workspace.numel(), C.byref(h)))
+        self._h = h
+
+    def run(self, site_lists, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        table, keep = _site_table(site_lists)
+        outs = (tn_result * len(self.plans))()
+        status = lib.tn_batch_run(self._h, table, C.c_void_p(stream.cuda_stream), outs)
+        if status not in (TN_OK, TN_ENONFINITE):
+            _check(status)
+        del keep
+        return [Result.from_c(o) for o in outs]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.tn_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def tn_contract_batch(plans, site_lists, precision="f32", workspace=None, stream=None):
+    import torch
+    if isinstance(precision, str):
+        precision = _PRECS[precision]
+    if workspace is None:
+        workspace = torch.empty(max(tn_batch_workspace(plans, precision), 256),
+                                dtype=torch.uint8, device="cuda")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    table, keep = _site_table(site_lists)
+    outs = (tn_result * len(plans))()
+    status = lib.tn_contract_batch(_plan_array(plans), table, len(plans), precision,
+                                   C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                   C.c_void_p(stream.cuda_stream), outs)
+    if status not in (TN_OK, TN_ENONFINITE):
+        _check(status)
+    del keep
+    return [Result.from_c(o) for o in outs]

@@ -1,0 +1,101 @@
+"""Autotuner for the batched persistent launch.
+
+The batched kernel's launch-shape knob is the workgroup size: how many waves
+sweep one lattice together (more waves finish a large lattice sooner; fewer
+leave room for more lattices per compute unit).  ``tune_batch`` times every candidate on the caller's own batch
+(replaying the captured graph), checks that every candidate returns
+bit-identical results, and caches the fastest under a signature of the
+workload (device name, precision, sorted lattice shapes and plan costs) in a
+JSON file: $TN_TUNE_CACHE, else ``tune_cache.json`` beside this module.
+``tuned_batch`` builds a Batch with the cached choice (library defaults when
+the workload has not been tuned).
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+from . import _native as N
+
+CANDIDATES: List[int] = [256, 512, 1024]
+
+
+def cache_path() -> str:
+    return os.environ.get("TN_TUNE_CACHE",
+                          os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                       "tune_cache.json"))
+
+
+def signature(plans: Sequence[N.Plan], precision) -> str:
+    import torch
+    if isinstance(precision, str):
+        precision = N._PRECS[precision]
+    shapes = sorted((p.info()["peak_entries"], p.info()["flops"], p.info()["n_steps"])
+                    for p in plans)
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    h = hashlib.sha1(json.dumps([dev, precision, shapes]).encode()).hexdigest()
+    return f"batch:{precision}:{len(plans)}:{h[:16]}"
+
+
+def _load() -> Dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(d: Dict) -> None:
+    path = cache_path()
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tuned_config(plans, precision) -> Optional[int]:
+    e = _load().get(signature(plans, precision))
+    return e["threads"] if e else None
+
+
+def tune_batch(plans, site_lists, precision="f32", candidates=CANDIDATES, reps=5,
+               warmup=1, save=True) -> Dict:
+    """Time each workgroup-size candidate; returns
+    {"best": threads, "ms": {threads: median ms}, "signature": ...}."""
+    import torch
+    timings = {}
+    ref = None
+    for threads in candidates:
+        b = N.Batch(plans, precision, threads)
+        for _ in range(warmup):
+            res = b.run(site_lists)
+        if ref is None:
+            ref = [(r.mantissa, r.exp2_sum) for r in res]
+        elif [(r.mantissa, r.exp2_sum) for r in res] != ref:
+            raise RuntimeError(f"workgroup size {threads} changed the results")
+        ms = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            z = torch.cuda.Event(enable_timing=True)
+            a.record()
+            b.run(site_lists)
+            z.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(z))
+        ms.sort()
+        timings[threads] = ms[len(ms) // 2]
+        b.close()
+    best = min(timings, key=timings.get)
+    sig = signature(plans, precision)
+    if save:
+        d = _load()
+        d[sig] = {"threads": best, "ms": timings[best]}
+        _save(d)
+    return {"best": best, "ms": timings, "signature": sig}
+
+
+def tuned_batch(plans, precision="f32") -> N.Batch:
+    threads = tuned_config(plans, precision)
+    return N.Batch(plans, precision, threads or 0)

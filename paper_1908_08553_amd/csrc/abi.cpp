@@ -6,7 +6,9 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <vector>
 
+#include "batch.hpp"
 #include "exec.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -16,9 +18,14 @@ struct tn_plan {
   tn::Plan p;
 };
 
+struct tn_batch {
+  tn::BatchImpl* impl;
+};
+
 namespace {
 
 thread_local std::string g_err;
+int32_t g_batch_threads = 512;
 
 tn_status fail(tn_status s, const std::string& msg) {
   g_err = msg;
@@ -122,7 +129,98 @@ tn_status tn_contract_grid(const tn_plan* plan, const double* const* sites,
   }
 }
 
+namespace {
+tn_status collect(const tn_plan* const* plans, int32_t n, std::vector<const tn::Plan*>& v) {
+  if (!plans || n < 1) return fail(TN_EINVAL, "empty or null plan list");
+  v.resize(n);
+  for (int32_t i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(TN_EINVAL, "null plan");
+    v[i] = &plans[i]->p;
+  }
+  return TN_OK;
+}
+}  // namespace
+
+tn_status tn_batch_workspace(const tn_plan* const* plans, int32_t n, int32_t precision,
+                             size_t* bytes) {
+  try {
+    if (!bytes) return fail(TN_EINVAL, "null argument");
+    if (precision < TN_PREC_F64 || precision > TN_PREC_BF16X3) return fail(TN_EINVAL, "unknown precision");
+    std::vector<const tn::Plan*> v;
+    if (collect(plans, n, v) != TN_OK) return TN_EINVAL;
+    std::string err;
+    const tn_status s = tn::batch_workspace(v.data(), n, precision, bytes, err);
+    return s == TN_OK ? s : fail(s, err);
+  } catch (...) {
+    return fail(TN_EINVAL, "tn_batch_workspace failed");
+  }
+}
+
+tn_status tn_batch_create(const tn_plan* const* plans, int32_t n, int32_t precision,
+                          const tn_batch_config* cfg, void* workspace, size_t ws_bytes,
+                          tn_batch** out) {
+  try {
+    if (!out || !workspace) return fail(TN_EINVAL, "null argument");
+    *out = nullptr;
+    if (precision < TN_PREC_F64 || precision > TN_PREC_BF16X3) return fail(TN_EINVAL, "unknown precision");
+    std::vector<const tn::Plan*> v;
+    if (collect(plans, n, v) != TN_OK) return TN_EINVAL;
+    if (cfg && cfg->reserved != 0) return fail(TN_EINVAL, "tn_batch_config.reserved must be 0");
+    const int32_t threads = (cfg && cfg->threads) ? cfg->threads : g_batch_threads;
+    std::string err;
+    tn::BatchImpl* impl = nullptr;
+    const tn_status s = tn::batch_create(v.data(), n, precision, threads, workspace, ws_bytes,
+                                         &impl, err);
+    if (s != TN_OK) return fail(s, err);
+    *out = new tn_batch{impl};
+    return TN_OK;
+  } catch (const std::exception& e) {
+    return fail(TN_EDEVICE, e.what());
+  } catch (...) {
+    return fail(TN_EDEVICE, "tn_batch_create failed");
+  }
+}
+
+tn_status tn_batch_run(tn_batch* batch, const double* const* const* sites, void* hip_stream,
+                       tn_result* outs) {
+  try {
+    if (!batch || !sites || !outs) return fail(TN_EINVAL, "null argument");
+    std::string err;
+    const tn_status s = tn::batch_run(batch->impl, sites, static_cast<hipStream_t>(hip_stream),
+                                      outs, err);
+    return s == TN_OK ? s : fail(s, err);
+  } catch (...) {
+    return fail(TN_EDEVICE, "tn_batch_run failed");
+  }
+}
+
+tn_status tn_batch_destroy(tn_batch* batch) {
+  if (!batch) return TN_OK;
+  tn::batch_destroy(batch->impl);
+  delete batch;
+  return TN_OK;
+}
+
+tn_status tn_contract_batch(const tn_plan* const* plans, const double* const* const* sites,
+                            int32_t n, int32_t precision, void* workspace, size_t ws_bytes,
+                            void* hip_stream, tn_result* outs) {
+  tn_batch* b = nullptr;
+  tn_status s = tn_batch_create(plans, n, precision, nullptr, workspace, ws_bytes, &b);
+  if (s != TN_OK) return s;
+  s = tn_batch_run(b, sites, hip_stream, outs);
+  const std::string keep = g_err;
+  tn_batch_destroy(b);
+  g_err = keep;
+  return s;
+}
+
 tn_status tn_set_option(int32_t option, int64_t value) {
+  if (option == TN_OPT_BATCH_THREADS) {
+    if (value != 256 && value != 512 && value != 1024)
+      return fail(TN_EINVAL, "TN_OPT_BATCH_THREADS must be 256, 512 or 1024");
+    g_batch_threads = static_cast<int32_t>(value);
+    return TN_OK;
+  }
   if (option == TN_OPT_KERNEL_IMPL) {
     if (value < 0 || value > 1) return fail(TN_EINVAL, "TN_OPT_KERNEL_IMPL must be 0 or 1");
     tn::set_absorb_policy(static_cast<int32_t>(value));

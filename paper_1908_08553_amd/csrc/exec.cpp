@@ -171,6 +171,40 @@ int64_t algorithmic_bytes(const Plan& p, int32_t prec) {
   return bytes;
 }
 
+void fill_stage_descs(const Plan& p, const Layout& L, int64_t s_base,
+                      const double* const* dsite, char* const* init_dst, StageDesc* descs) {
+  const int32_t R = p.rows, C = p.cols;
+  auto hd = [&](int32_t r, int32_t c) { return p.hdim[static_cast<size_t>(r) * (C - 1) + c]; };
+  auto vd = [&](int32_t r, int32_t c) { return p.vdim[static_cast<size_t>(r) * C + c]; };
+  for (size_t k = 0; k < p.steps.size(); ++k) {
+    const Step& s = p.steps[k];
+    StageDesc& d = descs[k];
+    std::memset(&d, 0, sizeof(d));
+    d.src = dsite[s.r * C + s.c];
+    d.entries = s.site_entries;
+    d.s_off = s_base + L.s_off[k];
+    d.ndim = s.nperm;
+    // canonical dims / strides of the site
+    int32_t cdims[4];
+    int64_t cstr[4];
+    int32_t nd = 0;
+    if (s.c > 0) cdims[nd++] = hd(s.r, s.c - 1);
+    if (s.r > 0) cdims[nd++] = vd(s.r - 1, s.c);
+    if (s.c < C - 1) cdims[nd++] = hd(s.r, s.c);
+    if (s.r < R - 1) cdims[nd++] = vd(s.r, s.c);
+    int64_t st = 1;
+    for (int32_t a = nd - 1; a >= 0; --a) { cstr[a] = st; st *= cdims[a]; }
+    for (int32_t a = 0; a < s.nperm; ++a) {
+      d.dims[a] = cdims[s.perm[a]];
+      d.cstride[a] = cstr[s.perm[a]];
+    }
+    if (s.kind == STEP_INIT) {
+      d.init_dst = init_dst[s.unit];
+      d.init_double = L.out_type[k] == EL_F64;
+    }
+  }
+}
+
 tn_status contract(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                    void* ws, size_t ws_bytes, hipStream_t stream, tn_result* out,
                    std::string& err) {
@@ -215,37 +249,9 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
   // staging descriptors
   const size_t nsteps = p.steps.size();
   std::vector<StageDesc> descs(nsteps);
-  std::vector<int32_t> cur(p.units.size(), 0);
-  for (size_t k = 0; k < nsteps; ++k) {
-    const Step& s = p.steps[k];
-    StageDesc& d = descs[k];
-    std::memset(&d, 0, sizeof(d));
-    d.src = dsite[s.r * p.cols + s.c];
-    d.entries = s.site_entries;
-    d.s_off = L.s_off[k];
-    d.ndim = s.nperm;
-    // canonical dims / strides of the site
-    int32_t cdims[4];
-    int64_t cstr[4];
-    int32_t nd = 0;
-    const int32_t R = p.rows, C = p.cols;
-    auto hd = [&](int32_t r, int32_t c) { return p.hdim[static_cast<size_t>(r) * (C - 1) + c]; };
-    auto vd = [&](int32_t r, int32_t c) { return p.vdim[static_cast<size_t>(r) * C + c]; };
-    if (s.c > 0) cdims[nd++] = hd(s.r, s.c - 1);
-    if (s.r > 0) cdims[nd++] = vd(s.r - 1, s.c);
-    if (s.c < C - 1) cdims[nd++] = hd(s.r, s.c);
-    if (s.r < R - 1) cdims[nd++] = vd(s.r, s.c);
-    int64_t st = 1;
-    for (int32_t a = nd - 1; a >= 0; --a) { cstr[a] = st; st *= cdims[a]; }
-    for (int32_t a = 0; a < s.nperm; ++a) {
-      d.dims[a] = cdims[s.perm[a]];
-      d.cstride[a] = cstr[s.perm[a]];
-    }
-    if (s.kind == STEP_INIT) {
-      d.init_dst = base + L.buf[s.unit][0];
-      d.init_double = L.out_type[k] == EL_F64;
-    }
-  }
+  char* init_dst[4];
+  for (size_t u = 0; u < p.units.size(); ++u) init_dst[u] = base + L.buf[u][0];
+  fill_stage_descs(p, L, 0, dsite.data(), init_dst, descs.data());
   TN_HIP(hipMemcpyAsync(base + L.descs, descs.data(), sizeof(StageDesc) * nsteps,
                         hipMemcpyHostToDevice, stream));
   // state header
@@ -262,8 +268,15 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
                   reinterpret_cast<uint16_t*>(base + L.slo)};
   LaunchTimer timer(stream);
   timer.before();
+  StageTargets tg;
+  tg.slot_exp = slot_exp;
+  tg.n_slots = p.slots;
+  tg.site_exp = slot_exp + p.slots;
+  tg.site_bad = tg.site_exp + nsteps;
+  tg.flags = &state->flags;
+  tg.counter = nullptr;
   TN_HIP(launch_stage(reinterpret_cast<const StageDesc*>(base + L.descs),
-                      static_cast<int32_t>(nsteps), sa, state, stream));
+                      static_cast<int32_t>(nsteps), sa, tg, stream));
   timer.after("stage", 8.0 * 2 * static_cast<double>(p.total_site_entries), 0.0);
 
   const int32_t arith = prec == TN_PREC_F64 ? AR_F64 : (prec == TN_PREC_F32 ? AR_F32 : AR_BF16X3);

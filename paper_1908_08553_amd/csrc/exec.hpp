@@ -59,6 +59,12 @@ class LaunchTimer {
   hipEvent_t pending_ = nullptr;
 };
 
+// Staging descriptors for every step of p: site pointers from dsite (indexed by
+// lattice site), staged offsets s_base + L.s_off[k], INIT steps written to
+// init_dst[unit] in the element type of that step.
+void fill_stage_descs(const Plan& p, const Layout& L, int64_t s_base,
+                      const double* const* dsite, char* const* init_dst, StageDesc* descs);
+
 tn_status contract(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                    void* ws, size_t ws_bytes, hipStream_t stream, tn_result* out,
                    std::string& err);

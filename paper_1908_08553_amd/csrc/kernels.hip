@@ -13,6 +13,7 @@
 #include <climits>
 #include <cmath>
 
+#include "absorb_device.hpp"
 #include "kernels.hpp"
 
 namespace tn {
@@ -75,14 +76,16 @@ __device__ inline void block_max_bad(T& m, int& bad) {
 
 // ---------------------------------------------------------------- staging
 __global__ __launch_bounds__(kBlock) void stage_kernel(const StageDesc* __restrict__ descs,
-                                                       StagedArrays st, DevState* state) {
+                                                       StagedArrays st, StageTargets tg) {
   const StageDesc d = descs[blockIdx.x];
-  int32_t* slot_exp = reinterpret_cast<int32_t*>(state + 1);
-  int32_t* site_exp = slot_exp + state->n_slots;
-  int32_t* site_bad = site_exp + state->n_steps;
+  int32_t* site_exp = tg.site_exp;
+  int32_t* site_bad = tg.site_bad;
   if (blockIdx.x == 0) {
-    for (int i = threadIdx.x; i < state->n_slots; i += blockDim.x) slot_exp[i] = kExpZero;
-    if (threadIdx.x == 0) state->flags = 0;
+    for (int i = threadIdx.x; i < tg.n_slots; i += blockDim.x) tg.slot_exp[i] = kExpZero;
+    if (threadIdx.x == 0) {
+      if (tg.flags) *tg.flags = 0;
+      if (tg.counter) *tg.counter = 0;
+    }
   }
   double m = 0.0;
   int bad = 0;
@@ -297,35 +300,16 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(DevState* state, const
     E += site_exp[i];
     bad |= site_bad[i];
   }
-  if (!isfinite(mval)) bad = 1;
-  tn_result r;
-  r.status = bad ? TN_ENONFINITE : TN_OK;
-  if (bad || mval == 0.0) {
-    r.sign = 0;
-    r.mantissa = 0.0;
-    r.exp2_sum = 0;
-    r.log_abs = bad ? __builtin_nan("") : -INFINITY;
-    r.value = bad ? __builtin_nan("") : 0.0;
-  } else {
-    int em;
-    const double f = frexp(mval, &em);
-    r.sign = f > 0 ? 1 : -1;
-    r.mantissa = f;
-    r.exp2_sum = E + em;
-    r.log_abs = static_cast<double>(r.exp2_sum) * 0.69314718055994530942 + log(fabs(f));
-    const int64_t ex = r.exp2_sum;
-    r.value = (ex > 2000) ? r.sign * INFINITY
-                          : (ex < -2000 ? 0.0 * r.sign : ldexp(f, static_cast<int>(ex)));
-  }
+  const tn_result r = dev::assemble_result(mval, E, bad);
   state->result = r;
 }
 
 }  // namespace
 
-hipError_t launch_stage(const StageDesc* descs, int32_t n_steps, StagedArrays st, DevState* state,
+hipError_t launch_stage(const StageDesc* descs, int32_t n_steps, StagedArrays st, StageTargets t,
                         hipStream_t stream) {
   if (n_steps <= 0) return hipSuccess;
-  hipLaunchKernelGGL(stage_kernel, dim3(n_steps), dim3(kBlock), 0, stream, descs, st, state);
+  hipLaunchKernelGGL(stage_kernel, dim3(n_steps), dim3(kBlock), 0, stream, descs, st, t);
   return hipGetLastError();
 }
 

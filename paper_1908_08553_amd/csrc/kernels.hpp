@@ -21,8 +21,19 @@ struct StagedArrays {
   uint16_t* slo;   // bf16 bits of the low part
 };
 
+// Where the staging launch writes its bookkeeping.  Block 0 also resets the
+// rescale slots to "zero", clears *flags and *counter (each nullable).
+struct StageTargets {
+  int32_t* site_exp;    // [n_steps] exponent divided out of each staged site
+  int32_t* site_bad;    // [n_steps] 1 if the site held a non-finite entry
+  int32_t* slot_exp;    // [n_slots] or nullptr
+  int32_t n_slots;
+  int32_t* flags;       // nullable
+  int32_t* counter;     // nullable (work counter of the batched kernel)
+};
+
 hipError_t launch_stage(const StageDesc* descs, int32_t n_steps, StagedArrays st,
-                        DevState* state, hipStream_t stream);
+                        StageTargets t, hipStream_t stream);
 
 // out[pre][N][post] = sum_k (2^-shift * in[pre][k][post]) * S[k][n]
 struct AbsorbArgs {

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <stdexcept>
 #include <sstream>
 
 namespace tn {
@@ -48,7 +49,7 @@ const int32_t kFrameLegs[5][4] = {
     {LEG_LEFT, LEG_DOWN, LEG_RIGHT, LEG_UP},   // MV  (mirror top-bottom)
 };
 const char* kFrameName[5] = {"ID", "T", "MH", "MHV", "MV"};
-const char* kOrderName[3] = {"COLSWEEP", "QUADRANT", "HEURISTIC"};
+const char* kOrderName[4] = {"COLSWEEP", "QUADRANT", "HEURISTIC", "SWEEP_AUTO"};
 
 struct Lattice {
   int32_t R, C;
@@ -278,6 +279,21 @@ tn_status build_plan(const tn_grid& grid, int32_t order, int32_t quad_h, int32_t
       const int32_t w = quad_w ? quad_w : (C + 1) / 2;
       if (h < 1 || h > R - 1 || w < 1 || w > C - 1) { err = "quadrant split out of range"; return TN_EINVAL; }
       plan_quadrant(L, h, w, TN_ORDER_QUADRANT, p);
+    } else if (order == TN_ORDER_SWEEP_AUTO) {
+      bool have = false;
+      Plan best;
+      for (int32_t t = 0; t < 2; ++t) {
+        Plan cand = p;
+        try {
+          plan_colsweep(L, t, TN_ORDER_SWEEP_AUTO, cand);
+          if (!have || cand.peak < best.peak || (cand.peak == best.peak && cand.flops < best.flops)) {
+            best = cand;
+            have = true;
+          }
+        } catch (Overflow&) {}
+      }
+      if (!have) throw Overflow{};
+      p = best;
     } else if (order == TN_ORDER_HEURISTIC) {
       bool have = false;
       Plan best;

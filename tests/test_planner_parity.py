@@ -6,7 +6,7 @@ import pytest
 import paper_1908_08553_amd as tn
 from oracle import plan as P
 
-ORDERS = [P.COLSWEEP, P.QUADRANT, P.HEURISTIC]
+ORDERS = [P.COLSWEEP, P.QUADRANT, P.HEURISTIC, P.SWEEP_AUTO]
 
 
 def both(rows, cols, D=2, hdim=None, vdim=None, order=P.COLSWEEP, qh=0, qw=0):
@@ -83,3 +83,12 @@ def test_errors():
     assert e.value.status == tn.TN_EINVAL
     with pytest.raises(tn.TnError):
         tn.tn_plan_grid(3, 3, 2, hdim=[[2, 0], [2, 2], [2, 2]])
+
+
+def test_batch_workspace_host_only():
+    plans = [tn.tn_plan_grid(r, c, 3, order=tn.TN_ORDER_SWEEP_AUTO) for r, c in [(4, 5), (6, 3)]]
+    n = tn.tn_batch_workspace(plans, "f32")
+    assert n > 0
+    with pytest.raises(tn.TnError) as e:
+        tn.tn_batch_workspace([tn.tn_plan_grid(4, 4, 2, order=tn.TN_ORDER_QUADRANT)], "f32")
+    assert e.value.status == tn.TN_EINVAL
