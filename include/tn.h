@@ -198,6 +198,52 @@ tn_status tn_contract_batch(const tn_plan* const* plans, const double* const* co
                             int32_t n, int32_t precision, void* workspace, size_t ws_bytes,
                             void* hip_stream, tn_result* outs);
 
+/* ------------------------------------------------------------ serving
+ * A request loop that admits contractions of different sizes and precisions
+ * as they arrive.  A scheduler thread admits queued requests first-come-
+ * first-served as soon as a slot (a HIP stream of the server's own) and a
+ * contiguous region of the arena large enough for the request's whole
+ * workspace are free; the request's contraction is then enqueued on its
+ * stream and its boundary tensors stay in the arena until the result is
+ * written.  Kernels of different requests interleave on the device, so small
+ * requests complete while large ones are still running.  The arena is device
+ * memory owned by the caller, 256-byte aligned, reserved for the server until
+ * tn_server_destroy; the library allocates no device memory for requests.  */
+typedef struct {
+  int64_t submitted, completed;   /* since create                              */
+  int64_t queued, active;         /* waiting for admission / on the device     */
+  int64_t arena_bytes, arena_in_use, peak_arena_in_use;
+  int64_t peak_active;            /* most requests on the device at once       */
+} tn_server_info;
+
+/* max_slots: requests on the device at once (1..64); queue_depth: requests
+ * waiting for admission before tn_submit returns TN_EBUSY.  Uses the current
+ * HIP device.                                                              */
+tn_status tn_server_create(void* arena, size_t arena_bytes, int32_t max_slots,
+                           int32_t queue_depth, tn_server** out);
+
+/* Queue one contraction of `grid` in `order` and `precision`.  host_sites are
+ * rows*cols HOST pointers to canonical float64 sites; they are copied before
+ * tn_submit returns.  Errors: TN_EINVAL, TN_EOVERFLOW, TN_ENOMEM (footprint
+ * larger than the whole arena), TN_EBUSY (queue full).                     */
+tn_status tn_submit(tn_server* server, const tn_grid* grid, int32_t order, int32_t precision,
+                    const double* const* host_sites, uint64_t* ticket);
+
+/* TN_PENDING while queued or running; on completion writes *out, retires the
+ * ticket and returns TN_OK (or the request's error: TN_ENONFINITE,
+ * TN_EDEVICE).  TN_ENOTFOUND for unknown or retired tickets.               */
+tn_status tn_poll(tn_server* server, uint64_t ticket, tn_result* out);
+
+/* As tn_poll; also returns steady-clock times in ns: times_ns[0] submit,
+ * [1] admission, [2] completion seen by the scheduler.                     */
+tn_status tn_poll_ex(tn_server* server, uint64_t ticket, tn_result* out, int64_t* times_ns);
+
+tn_status tn_server_stats(tn_server* server, tn_server_info* out);
+
+/* Finishes every queued and running request, then releases the server's
+ * streams and thread.  Unpolled results are dropped.                       */
+tn_status tn_server_destroy(tn_server* server);
+
 /* Library-wide options (process-wide; not for concurrent change during a
  * contraction).
  *   TN_OPT_KERNEL_IMPL : 0 = matrix-core (MFMA) kernels for absorption steps

@@ -322,3 +322,92 @@ def tn_contract_batch(plans, site_lists, precision="f32", workspace=None, stream
         _check(status)
     del keep
     return [Result.from_c(o) for o in outs]
+
+
+# ------------------------------------------------------------------ serving
+
+class tn_server_info(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("queued", C.c_int64),
+                ("active", C.c_int64), ("arena_bytes", C.c_int64), ("arena_in_use", C.c_int64),
+                ("peak_arena_in_use", C.c_int64), ("peak_active", C.c_int64)]
+
+
+lib.tn_server_create.restype = C.c_int32
+lib.tn_server_create.argtypes = [_P, C.c_size_t, C.c_int32, C.c_int32, C.POINTER(_P)]
+lib.tn_submit.restype = C.c_int32
+lib.tn_submit.argtypes = [_P, C.POINTER(tn_grid), C.c_int32, C.c_int32,
+                          C.POINTER(C.c_void_p), C.POINTER(C.c_uint64)]
+lib.tn_poll_ex.restype = C.c_int32
+lib.tn_poll_ex.argtypes = [_P, C.c_uint64, C.POINTER(tn_result), C.POINTER(C.c_int64)]
+lib.tn_poll.restype = C.c_int32
+lib.tn_poll.argtypes = [_P, C.c_uint64, C.POINTER(tn_result)]
+lib.tn_server_stats.restype = C.c_int32
+lib.tn_server_stats.argtypes = [_P, C.POINTER(tn_server_info)]
+lib.tn_server_destroy.restype = C.c_int32
+lib.tn_server_destroy.argtypes = [_P]
+
+
+class Server:
+    """A tn_server over a torch-allocated arena of `arena_bytes` bytes."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 4, queue_depth: int = 4096,
+                 device="cuda"):
+        import torch
+        self.arena = torch.empty(max(int(arena_bytes), 256), dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        _check(lib.tn_server_create(C.c_void_p(self.arena.data_ptr()), self.arena.numel(),
+                                    max_slots, queue_depth, C.byref(h)))
+        self._h = h
+
+    def submit(self, rows, cols, sites, D=2, hdim=None, vdim=None, order=TN_ORDER_HEURISTIC,
+               precision="f64") -> int:
+        import numpy as np
+        if isinstance(order, str):
+            order = _ORDERS[order]
+        if isinstance(precision, str):
+            precision = _PRECS[precision]
+        h = _int_array(hdim)
+        v = _int_array(vdim)
+        g = tn_grid(rows, cols, D,
+                    C.cast(h, C.POINTER(C.c_int32)) if h is not None else None,
+                    C.cast(v, C.POINTER(C.c_int32)) if v is not None else None)
+        keep = [np.ascontiguousarray(np.asarray(s, dtype=np.float64)) for s in sites]
+        ptrs = (C.c_void_p * len(keep))(*[a.ctypes.data for a in keep])
+        t = C.c_uint64(0)
+        _check(lib.tn_submit(self._h, C.byref(g), order, precision, ptrs, C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """(status, Result or None, (t_submit, t_admit, t_done) ns)."""
+        out = tn_result()
+        times = (C.c_int64 * 3)()
+        st = lib.tn_poll_ex(self._h, ticket, C.byref(out), times)
+        if st == TN_PENDING:
+            return st, None, None
+        if st not in (TN_OK, TN_ENONFINITE):
+            _check(st)
+        return st, Result.from_c(out), tuple(times)
+
+    def wait(self, ticket: int, timeout: float = 120.0):
+        import time
+        t0 = time.monotonic()
+        while True:
+            st, res, times = self.poll(ticket)
+            if st != TN_PENDING:
+                return res, times
+            if time.monotonic() - t0 > timeout:
+                raise TimeoutError(f"ticket {ticket} still pending after {timeout} s")
+            time.sleep(50e-6)
+
+    def stats(self) -> dict:
+        i = tn_server_info()
+        _check(lib.tn_server_stats(self._h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in tn_server_info._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.tn_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -10,6 +10,7 @@
 
 #include "batch.hpp"
 #include "exec.hpp"
+#include "server.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
 #include "tn.h"
@@ -20,6 +21,10 @@ struct tn_plan {
 
 struct tn_batch {
   tn::BatchImpl* impl;
+};
+
+struct tn_server {
+  tn::ServerImpl* impl;
 };
 
 namespace {
@@ -212,6 +217,66 @@ tn_status tn_contract_batch(const tn_plan* const* plans, const double* const* co
   tn_batch_destroy(b);
   g_err = keep;
   return s;
+}
+
+tn_status tn_server_create(void* arena, size_t arena_bytes, int32_t max_slots,
+                           int32_t queue_depth, tn_server** out) {
+  try {
+    if (!out) return fail(TN_EINVAL, "null argument");
+    *out = nullptr;
+    std::string err;
+    tn::ServerImpl* impl = nullptr;
+    const tn_status s = tn::server_create(arena, arena_bytes, max_slots, queue_depth, &impl, err);
+    if (s != TN_OK) return fail(s, err);
+    *out = new tn_server{impl};
+    return TN_OK;
+  } catch (...) {
+    return fail(TN_EDEVICE, "tn_server_create failed");
+  }
+}
+
+tn_status tn_submit(tn_server* server, const tn_grid* grid, int32_t order, int32_t precision,
+                    const double* const* host_sites, uint64_t* ticket) {
+  try {
+    if (!server || !grid) return fail(TN_EINVAL, "null argument");
+    std::string err;
+    const tn_status s = tn::server_submit(server->impl, *grid, order, precision, host_sites,
+                                          ticket, err);
+    return s == TN_OK ? s : fail(s, err);
+  } catch (...) {
+    return fail(TN_EINVAL, "tn_submit failed");
+  }
+}
+
+tn_status tn_poll_ex(tn_server* server, uint64_t ticket, tn_result* out, int64_t* times_ns) {
+  try {
+    if (!server) return fail(TN_EINVAL, "null argument");
+    std::string err;
+    const tn_status s = tn::server_poll(server->impl, ticket, out, times_ns, err);
+    return (s == TN_OK || s == TN_PENDING) ? s : fail(s, err);
+  } catch (...) {
+    return fail(TN_EINVAL, "tn_poll failed");
+  }
+}
+
+tn_status tn_poll(tn_server* server, uint64_t ticket, tn_result* out) {
+  return tn_poll_ex(server, ticket, out, nullptr);
+}
+
+tn_status tn_server_stats(tn_server* server, tn_server_info* out) {
+  if (!server || !out) return fail(TN_EINVAL, "null argument");
+  tn::server_info(server->impl, out);
+  return TN_OK;
+}
+
+tn_status tn_server_destroy(tn_server* server) {
+  if (!server) return TN_OK;
+  try {
+    tn::server_destroy(server->impl);
+  } catch (...) {
+  }
+  delete server;
+  return TN_OK;
 }
 
 tn_status tn_set_option(int32_t option, int64_t value) {

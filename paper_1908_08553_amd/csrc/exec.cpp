@@ -69,7 +69,7 @@ int32_t profile_read(tn_kernel_stat* out, int32_t cap) {
   return k;
 }
 
-LaunchTimer::LaunchTimer(hipStream_t s) : stream_(s), on_(profile_on()) {}
+LaunchTimer::LaunchTimer(hipStream_t s, bool allow) : stream_(s), on_(allow && profile_on()) {}
 
 LaunchTimer::~LaunchTimer() {
   for (Rec& r : recs_) {
@@ -205,9 +205,9 @@ void fill_stage_descs(const Plan& p, const Layout& L, int64_t s_base,
   }
 }
 
-tn_status contract(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
-                   void* ws, size_t ws_bytes, hipStream_t stream, tn_result* out,
-                   std::string& err) {
+tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
+                  void* ws, size_t ws_bytes, hipStream_t stream, HostKeep& keep,
+                  LaunchTimer& timer, std::string& err) {
   const Layout L = make_layout(p, prec);
   if (ws_bytes < L.total) {
     err = "workspace too small: need " + std::to_string(L.total) + " bytes";
@@ -248,14 +248,15 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
 
   // staging descriptors
   const size_t nsteps = p.steps.size();
-  std::vector<StageDesc> descs(nsteps);
+  std::vector<StageDesc>& descs = keep.descs;
+  descs.assign(nsteps, StageDesc{});
   char* init_dst[4];
   for (size_t u = 0; u < p.units.size(); ++u) init_dst[u] = base + L.buf[u][0];
   fill_stage_descs(p, L, 0, dsite.data(), init_dst, descs.data());
   TN_HIP(hipMemcpyAsync(base + L.descs, descs.data(), sizeof(StageDesc) * nsteps,
                         hipMemcpyHostToDevice, stream));
   // state header
-  DevState hs;
+  DevState& hs = keep.hs;
   std::memset(&hs, 0, sizeof(hs));
   hs.n_slots = p.slots;
   hs.n_steps = static_cast<int32_t>(nsteps);
@@ -266,7 +267,6 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
   StagedArrays sa{reinterpret_cast<double*>(base + L.s64), reinterpret_cast<float*>(base + L.s32),
                   reinterpret_cast<uint16_t*>(base + L.shi),
                   reinterpret_cast<uint16_t*>(base + L.slo)};
-  LaunchTimer timer(stream);
   timer.before();
   StageTargets tg;
   tg.slot_exp = slot_exp;
@@ -351,10 +351,27 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
     TN_HIP(launch_finalize(state, nullptr, nullptr, x.partials, n_part, stream));
     timer.after("finalize", 0.0, 0.0);
   }
-  TN_HIP(hipMemcpyAsync(out, &state->result, sizeof(tn_result), hipMemcpyDeviceToHost, stream));
-  TN_HIP(hipStreamSynchronize(stream));
-  timer.flush();
 #undef TN_HIP
+  return TN_OK;
+}
+
+tn_status contract(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
+                   void* ws, size_t ws_bytes, hipStream_t stream, tn_result* out,
+                   std::string& err) {
+  HostKeep keep;
+  LaunchTimer timer(stream);
+  const tn_status s = enqueue(p, sites, on_device, prec, ws, ws_bytes, stream, keep, timer, err);
+  if (s != TN_OK) return s;
+  const Layout L = make_layout(p, prec);
+  const DevState* state = reinterpret_cast<const DevState*>(static_cast<char*>(ws) + L.state);
+  hipError_t e = hipMemcpyAsync(out, &state->result, sizeof(tn_result), hipMemcpyDeviceToHost,
+                                stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    err = std::string("result copy: ") + hip_msg(e);
+    return TN_EDEVICE;
+  }
+  timer.flush();
   if (out->status != TN_OK) {
     err = "non-finite value in the inputs or an intermediate";
     return out->status;

@@ -46,7 +46,7 @@ bool profile_on();
 // times into the process-wide totals once the stream has been synchronised.
 class LaunchTimer {
  public:
-  explicit LaunchTimer(hipStream_t s);
+  explicit LaunchTimer(hipStream_t s, bool allow = true);
   ~LaunchTimer();
   void before();
   void after(const char* name, double bytes, double flops);
@@ -64,6 +64,19 @@ class LaunchTimer {
 // init_dst[unit] in the element type of that step.
 void fill_stage_descs(const Plan& p, const Layout& L, int64_t s_base,
                       const double* const* dsite, char* const* init_dst, StageDesc* descs);
+
+// Host-side sources of the asynchronous copies an enqueue issues; they must
+// outlive the stream work.
+struct HostKeep {
+  std::vector<StageDesc> descs;
+  DevState hs;
+};
+
+// Issue every copy and launch of one contraction on `stream` without waiting;
+// the result record lands in the workspace's DevState (offset Layout.state).
+tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
+                  void* ws, size_t ws_bytes, hipStream_t stream, HostKeep& keep,
+                  LaunchTimer& timer, std::string& err);
 
 tn_status contract(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                    void* ws, size_t ws_bytes, hipStream_t stream, tn_result* out,
