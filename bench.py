@@ -1,13 +1,17 @@
-"""Benchmark: exact 12x12 D=4 lattice contraction on one MI355X.
+"""Benchmark: exact 12x12 D=4 planar-lattice contraction on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-legs]
+                    [--no-batch] [--no-serve] [--calibrate]
 
-One step = one full contraction through the C ABI (staging, every pairwise
-absorption with its per-column rescale, the final float64 reduction and the
-result copy) of a 12x12, D=4 network with i.i.d. uniform[0,1) entries
-(seed 0) already resident in HBM.  `value` is the plan's algorithmic flops
-per second.  Prints ONE JSON line; the extra legs (other orders and
-precisions, the 10x10 FP64 configuration) ride along under "legs".
+One step = one full contraction through the C ABI -- site staging, every
+pairwise absorption with its per-column exact rescale, the quadrant ring
+products with the float64 closing dot, and the result copy -- of a 12x12,
+D=4 network with i.i.d. uniform[0,1) entries (seed 0) already resident in
+HBM, in the order the paper's heuristic picks (smallest bottleneck: the
+quadrant split for even L), FP32 arithmetic.  `value` is the plan's
+algorithmic flops per second.  Prints ONE JSON line; the other orders and
+precisions, the 10x10 FP64 configuration, the 512-lattice batch and the
+served Poisson stream ride along under "legs".
 """
 from __future__ import annotations
 
@@ -23,6 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# dense peaks; split BF16x3 issues three bf16 products per algorithmic one
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0 / 3.0}
 
 
@@ -30,7 +35,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_stats(tn):
+def kernel_stats():
     import ctypes as C
     from paper_1908_08553_amd._native import lib
 
@@ -44,6 +49,11 @@ def kernel_stats(tn):
     return [{"name": arr[i].name.decode(), "launches": arr[i].launches,
              "total_ms": arr[i].total_ms, "bytes": arr[i].bytes, "flops": arr[i].flops}
             for i in range(min(n.value, 64))]
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))]
 
 
 def run_leg(tn, torch, rows, cols, D, kind, seed, order, prec, steps, warmup, profile=False):
@@ -61,6 +71,7 @@ def run_leg(tn, torch, rows, cols, D, kind, seed, order, prec, steps, warmup, pr
     if profile:
         tn.lib.tn_profile_enable(1)
     lat = []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         a = time.perf_counter()
@@ -68,13 +79,12 @@ def run_leg(tn, torch, rows, cols, D, kind, seed, order, prec, steps, warmup, pr
         lat.append(time.perf_counter() - a)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ks = kernel_stats(tn) if profile else None
+    ks = kernel_stats() if profile else None
     if profile:
         tn.lib.tn_profile_enable(0)
-    lat.sort()
     return {"rows": rows, "cols": cols, "D": D, "inputs": kind, "order": info["order"],
             "quad": list(info["quad"]), "precision": prec, "ms": 1e3 * dt / steps,
-            "p50_ms": 1e3 * lat[len(lat) // 2], "p99_ms": 1e3 * lat[min(len(lat) - 1, int(0.99 * len(lat)))],
+            "p50_ms": 1e3 * pct(lat, 0.5), "p99_ms": 1e3 * pct(lat, 0.99),
             "gflops": info["flops"] / (dt / steps) / 1e9,
             "contractions_per_s": steps / dt, "flops": info["flops"],
             "peak_entries": info["peak_entries"], "hbm_bytes": info["hbm_bytes"][pidx],
@@ -82,22 +92,23 @@ def run_leg(tn, torch, rows, cols, D, kind, seed, order, prec, steps, warmup, pr
 
 
 def roofline(ks, prec):
+    """Dominant kernel (most GPU time) of a profiled leg against its bound."""
     if not ks:
         return None
     dom = max(ks, key=lambda k: k["total_ms"])
     avg_ms = dom["total_ms"] / dom["launches"]
-    if dom["name"].startswith("ring_mfma") or dom["name"].startswith("ring_valu"):
+    share = dom["total_ms"] / sum(k["total_ms"] for k in ks)
+    if dom["name"].startswith("ring_"):
         ach = dom["flops"] / dom["launches"] / (avg_ms * 1e-3) / 1e12
-        peak = PEAK_TFLOPS[prec]
+        dt = "f64" if dom["name"].endswith("f64") else prec
+        peak = PEAK_TFLOPS[dt]
         return {"kernel": dom["name"], "bound": "mfma", "achieved": ach, "peak": peak,
                 "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
-                "launches": dom["launches"], "avg_ms": avg_ms,
-                "share_of_gpu_time": dom["total_ms"] / sum(k["total_ms"] for k in ks)}
+                "launches": dom["launches"], "avg_ms": avg_ms, "share_of_gpu_time": share}
     ach = dom["bytes"] / dom["launches"] / (avg_ms * 1e-3) / 1e9
     return {"kernel": dom["name"], "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None,
-            "launches": dom["launches"], "avg_ms": avg_ms,
-            "share_of_gpu_time": dom["total_ms"] / sum(k["total_ms"] for k in ks)}
+            "launches": dom["launches"], "avg_ms": avg_ms, "share_of_gpu_time": share}
 
 
 def copy_calibration(torch, mib=256, reps=20):
@@ -120,9 +131,109 @@ def copy_calibration(torch, mib=256, reps=20):
     return {"bytes_per_launch": 2 * n * 4, "avg_ms": ms, "gbs": 2 * n * 4 / (ms * 1e-3) / 1e9}
 
 
+def batch_leg(tn, torch, n=512, seed=2024, reps=20):
+    """512 independent lattices (Lh, Lw ~ U{4..8}, D ~ U{2,3,4}, uniform[0,1))
+    in one graph-replayed launch, FP32; workgroup size from the autotuner."""
+    import lattice_inputs as li
+    from paper_1908_08553_amd import autotune
+    mix = li.batch_mix(n, seed)
+    plans = [tn.tn_plan_grid(r, c, D, order=tn.TN_ORDER_SWEEP_AUTO) for r, c, D, _ in mix]
+    sites = [tn.device_sites(s) for _, _, _, s in mix]
+    flops = sum(p.info()["flops"] for p in plans)
+    tuned = autotune.tune_batch(plans, sites, "f32", reps=5)
+    b = autotune.tuned_batch(plans, "f32")
+    b.run(sites)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = b.run(sites)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    b.close()
+    # the same lattices one tn_contract_grid call at a time
+    ws = torch.empty(max(max(p.info()["workspace_bytes"][1] for p in plans), 256),
+                     dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single = [tn.contract_grid(p, s, "f32", ws) for p, s in zip(plans, sites)]
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t0
+    same = all((a.mantissa, a.exp2_sum) == (c.mantissa, c.exp2_sum) for a, c in zip(res, single))
+    return {"lattices": n, "precision": "f32", "ms": 1e3 * dt,
+            "contractions_per_s": n / dt, "gflops": flops / dt / 1e9,
+            "flops_per_batch": flops, "tuned_threads": tuned["best"],
+            "tuning_ms": {str(k): v for k, v in tuned["ms"].items()},
+            "sequential_ms": 1e3 * dt_seq, "sequential_contractions_per_s": n / dt_seq,
+            "speedup_vs_sequential": dt_seq / dt, "bitwise_equal_to_single": same,
+            "all_finite": all(r.status == 0 for r in res)}
+
+
+def served_leg(tn, torch, n=240, seed=5):
+    """Poisson stream: L ~ U{4..13} square Ising lattices, D ~ U{2,4} (D=4 is
+    the two-replica network), tag ~ U{FP64, BF16x3}, beta*J ~ U[0.1, 0.8],
+    heuristic order.  First the plain FP64 GPU path runs every request back
+    to back (saturation rate mu); then the server takes the stream at arrival
+    rates 0.5 mu and 0.9 mu.  Accuracy: |d log Z| against the FP64 path."""
+    import numpy as np
+    import lattice_inputs as li
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(n):
+        L = int(rng.integers(4, 14))
+        D = int(rng.choice([2, 4]))
+        tag = str(rng.choice(["f64", "bf16x3"]))
+        K = float(rng.uniform(0.1, 0.8))
+        sites = li.ising(L, L, K) if D == 2 else li.ising_d4(L, L, K)
+        reqs.append((L, D, tag, sites))
+    plans = [tn.tn_plan_grid(L, L, D, order=tn.TN_ORDER_HEURISTIC) for L, D, _, _ in reqs]
+    ws = torch.empty(max(p.info()["workspace_bytes"][0] for p in plans), dtype=torch.uint8,
+                     device="cuda")
+    tn.contract_grid(plans[0], reqs[0][3], "f64", ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref = [tn.contract_grid(p, r[3], "f64", ws) for p, r in zip(plans, reqs)]
+    t_serial = time.perf_counter() - t0
+    del ws
+    mu = n / t_serial
+    out = {"requests": n, "fp64_serial_s": t_serial, "fp64_serial_contractions_per_s": mu,
+           "mean_flops": sum(p.info()["flops"] for p in plans) / n}
+    srv = tn.Server(24 << 30, max_slots=4, queue_depth=n + 8)
+    for frac in (0.5, 0.9):
+        lam = frac * mu
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n))
+        pending = {}
+        done = {}
+        start = time.perf_counter()
+        i = 0
+        while len(done) < n:
+            now = time.perf_counter() - start
+            while i < n and arrivals[i] <= now:
+                L, D, tag, sites = reqs[i]
+                pending[srv.submit(L, L, sites, D=D, precision=tag)] = i
+                i += 1
+            for t in list(pending):
+                st, res, times = srv.poll(t)
+                if st != tn.TN_PENDING:
+                    done[pending.pop(t)] = (res, times)
+            time.sleep(100e-6)
+        lat = [(done[k][1][2] - done[k][1][0]) * 1e-6 for k in range(n)]
+        span = (max(done[k][1][2] for k in range(n)) - min(done[k][1][0] for k in range(n))) * 1e-9
+        err = {"f64": 0.0, "bf16x3": 0.0}
+        for k in range(n):
+            d = abs(done[k][0].log_abs - ref[k].log_abs)
+            err[reqs[k][2]] = max(err[reqs[k][2]], d / max(1.0, abs(ref[k].log_abs)))
+        out[f"rate_{frac}"] = {"arrival_per_s": lam, "p50_ms": pct(lat, 0.5),
+                               "p99_ms": pct(lat, 0.99), "max_ms": max(lat),
+                               "contractions_per_s": n / span,
+                               "max_rel_dlogz_vs_fp64": err,
+                               "peak_active": srv.stats()["peak_active"]}
+    srv.close()
+    return out
+
+
 def cpu_baseline():
-    """The FP64 oracle, unchanged, on the first two columns (24 steps) of the
-    same 12x12 D=4 column sweep; GFLOP/s from the plan's flops."""
+    """The FP64 oracle, unchanged, contracting the whole headline network
+    (12x12, D=4, uniform seed 0, the heuristic's quadrant plan)."""
     import lattice_inputs as li
     from oracle import contract as OC
     from oracle import plan as OP
@@ -132,13 +243,14 @@ def cpu_baseline():
     except Exception:  # pragma: no cover
         threads = os.cpu_count()
     sites = li.uniform(12, 12, 4, 0)
-    plan = OP.plan_grid(12, 12, 4)
+    plan = OP.plan_grid(12, 12, 4, order=OP.HEURISTIC)
     t = time.perf_counter()
-    flops = OC.run_prefix(sites, plan, 24)
+    r = OC.contract(sites, plan)
     dt = time.perf_counter() - t
-    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"first 24 of 144 steps (columns 0-1, {flops:.3e} flops) of the 12x12 D=4 "
-                      f"column sweep, FP64 numpy/OpenBLAS, {dt:.1f} s"}
+    return {"value": plan.flops / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"one complete 12x12 D=4 contraction (quadrant plan, {plan.flops:.3e} "
+                      f"flops), FP64 numpy/OpenBLAS, {dt:.1f} s",
+            "log_abs": r.log_abs}
 
 
 def main():
@@ -148,6 +260,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-legs", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--calibrate", action="store_true",
                     help="also time a plain 256 MiB device copy")
     args = ap.parse_args()
@@ -161,32 +275,39 @@ def main():
     torch.cuda.set_device(0)
 
     calib = copy_calibration(torch) if args.calibrate else None
-    head = run_leg(tn, torch, 12, 12, 4, "uniform", 0, tn.TN_ORDER_COLSWEEP, "f32",
+    head = run_leg(tn, torch, 12, 12, 4, "uniform", 0, tn.TN_ORDER_HEURISTIC, "f32",
                    args.steps, args.warmup, profile=True)
     log(f"headline: {head['ms']:.3f} ms/contraction, {head['gflops']:.1f} GFLOP/s")
     legs = {}
     if not args.no_legs:
-        spec = [("sweep12_bf16x3", 12, 12, 4, "uniform", 0, "f32"),
+        spec = [("sweep12_f32", 12, 12, 4, "uniform", 0, "f32"),
+                ("sweep12_bf16x3", 12, 12, 4, "uniform", 0, "bf16x3"),
                 ("sweep12_f64", 12, 12, 4, "uniform", 0, "f64"),
-                ("quad12_f32", 12, 12, 4, "uniform", 1, "f32"),
                 ("quad12_bf16x3", 12, 12, 4, "uniform", 1, "bf16x3"),
                 ("quad12_f64", 12, 12, 4, "uniform", 1, "f64"),
+                ("ising12_d4_quad_f32", 12, 12, 4, "ising", 1, "f32"),
                 ("sweep10_f64_normal", 10, 10, 4, "normal", 0, "f64"),
                 ("quad10_f64_normal", 10, 10, 4, "normal", 1, "f64")]
-        spec[0] = ("sweep12_bf16x3", 12, 12, 4, "uniform", 0, "bf16x3")
         for name, r, c, D, kind, order, prec in spec:
             leg = run_leg(tn, torch, r, c, D, kind, 0, order, prec, max(3, args.steps // 4),
                           1, profile=True)
             leg["roofline"] = roofline(leg["kernels"], prec)
             legs[name] = leg
-            log(f"{name}: {leg['ms']:.3f} ms, {leg['gflops']:.1f} GFLOP/s, log|Z|={leg['log_abs']:.10f}")
-        ref = legs["sweep12_f64"]["log_abs"]
-        for name, leg in legs.items():
-            if leg["rows"] == 12:
-                leg["dlogz_vs_gpu_f64_sweep"] = abs(leg["log_abs"] - ref)
+            log(f"{name}: {leg['ms']:.3f} ms, {leg['gflops']:.1f} GFLOP/s, "
+                f"log|Z|={leg['log_abs']:.10f}")
+        ref = legs["quad12_f64"]["log_abs"]
+        for name, leg in list(legs.items()) + [("headline", head)]:
+            if leg["rows"] == 12 and leg["inputs"] == "uniform":
+                leg["dlogz_vs_gpu_f64"] = abs(leg["log_abs"] - ref)
+        if not args.no_batch:
+            legs["batch512_f32"] = batch_leg(tn, torch)
+            log(f"batch: {legs['batch512_f32']['contractions_per_s']:.0f} contractions/s")
+        if not args.no_serve:
+            legs["served"] = served_leg(tn, torch)
+            log(f"served: {json.dumps(legs['served'])}")
     head_kernels = head.pop("kernels")
     line = {
-        "metric": "exact contraction GFLOP/s (12x12 D=4 column sweep)",
+        "metric": "exact contraction GFLOP/s (12x12 D=4, paper's heuristic order)",
         "value": head["gflops"],
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -198,10 +319,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic: 12x12 lattice, D=4, i.i.d. uniform[0,1) site tensors, seed 0",
-        "config": {"workload": "12x12 square lattice, bond dim 4, column sweep, FP32 boundary "
-                               "with FP64 rescale exponents and FP64 last column",
-                   "rows": 12, "cols": 12, "D": 4, "order": "COLSWEEP", "precision": "f32",
-                   "parallelism": "single GPU"},
+        "config": {"workload": "12x12 square-lattice network, bond dimension 4, minimal-bottleneck "
+                               "(quadrant) order, FP32 products with exact FP64-exponent rescaling "
+                               "and an FP64 closing dot",
+                   "rows": 12, "cols": 12, "D": 4, "order": "HEURISTIC -> QUADRANT 6,6",
+                   "precision": "f32", "parallelism": "single GPU"},
         "contractions_per_s": head["contractions_per_s"],
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "log_abs": head["log_abs"],
