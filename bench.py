@@ -197,7 +197,8 @@ def served_leg(tn, torch, n=240, seed=5):
     mu = n / t_serial
     out = {"requests": n, "fp64_serial_s": t_serial, "fp64_serial_contractions_per_s": mu,
            "mean_flops": sum(p.info()["flops"] for p in plans) / n}
-    srv = tn.Server(24 << 30, max_slots=4, queue_depth=n + 8)
+    # one slot per hardware queue left beside the caller's stream
+    srv = tn.Server(24 << 30, max_slots=3, queue_depth=n + 8)
     for frac in (0.5, 0.9):
         lam = frac * mu
         arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n))

@@ -218,7 +218,10 @@ typedef struct {
 
 /* max_slots: requests on the device at once (1..64); queue_depth: requests
  * waiting for admission before tn_submit returns TN_EBUSY.  Uses the current
- * HIP device.                                                              */
+ * HIP device.  Each slot is a HIP stream; the runtime maps streams onto a
+ * limited number of hardware queues per process (GPU_MAX_HW_QUEUES, 4 by
+ * default), and streams sharing a queue run their kernels in order, so slots
+ * beyond the free hardware queues add admission capacity but no overlap.   */
 tn_status tn_server_create(void* arena, size_t arena_bytes, int32_t max_slots,
                            int32_t queue_depth, tn_server** out);
 

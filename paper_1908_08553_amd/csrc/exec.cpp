@@ -280,36 +280,68 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
   timer.after("stage", 8.0 * 2 * static_cast<double>(p.total_site_entries), 0.0);
 
   const int32_t arith = prec == TN_PREC_F64 ? AR_F64 : (prec == TN_PREC_F32 ? AR_F32 : AR_BF16X3);
-  std::vector<int32_t> final_buf(p.units.size(), 0);
-  for (size_t u = 0; u < p.units.size(); ++u) {
-    const Unit& U = p.units[u];
-    int32_t c = 0;
-    for (int32_t k = U.first_step + 1; k < U.first_step + U.n_steps; ++k) {
-      const Step& s = p.steps[k];
-      AbsorbArgs a;
-      a.in = base + L.buf[u][c];
-      a.out = base + L.buf[u][1 - c];
-      a.in_type = L.out_type[k - 1];
-      a.out_type = L.out_type[k];
-      a.arith = arith;
-      a.pre = s.pre; a.K = s.K; a.N = s.N; a.post = s.post;
-      a.s_off = L.s_off[k];
-      a.scale_slot = s.scale_in >= 0 ? slot_exp + s.scale_in : nullptr;
-      a.max_slot = s.rescale >= 0 ? slot_exp + s.rescale : nullptr;
-      const char* kname = "";
-      timer.before();
-      TN_HIP(launch_absorb(a, sa, state, stream, &kname));
-      const double sb = (a.out_type == EL_F64 || prec == TN_PREC_F64) ? 8.0 : (prec == TN_PREC_BF16X3 ? 4.0 : 4.0);
-      timer.after(kname,
-                  static_cast<double>(s.pre * s.K * s.post) * elem_bytes(a.in_type) +
-                      static_cast<double>(s.out) * elem_bytes(a.out_type) +
-                      static_cast<double>(s.K * s.N) * sb,
-                  static_cast<double>(s.flops));
-      c = 1 - c;
+  // Steps of different units are independent: walk step index t across the
+  // units and launch same-kind steps of several units together.
+  const size_t nu = p.units.size();
+  std::vector<int32_t> final_buf(nu, 0), cur(nu, 0);
+  int32_t max_steps = 0;
+  for (const Unit& U : p.units) max_steps = std::max(max_steps, U.n_steps);
+  auto args_of = [&](size_t u, int32_t k) {
+    const Step& s = p.steps[k];
+    AbsorbArgs a;
+    a.in = base + L.buf[u][cur[u]];
+    a.out = base + L.buf[u][1 - cur[u]];
+    a.in_type = L.out_type[k - 1];
+    a.out_type = L.out_type[k];
+    a.arith = arith;
+    a.pre = s.pre; a.K = s.K; a.N = s.N; a.post = s.post;
+    a.s_off = L.s_off[k];
+    a.scale_slot = s.scale_in >= 0 ? slot_exp + s.scale_in : nullptr;
+    a.max_slot = s.rescale >= 0 ? slot_exp + s.rescale : nullptr;
+    return a;
+  };
+  auto step_bytes = [&](const AbsorbArgs& a, const Step& s) {
+    const double sb = a.out_type == EL_F64 ? 8.0 : (prec == TN_PREC_F64 ? 8.0 : 4.0);
+    return static_cast<double>(s.pre * s.K * s.post) * elem_bytes(a.in_type) +
+           static_cast<double>(s.out) * elem_bytes(a.out_type) +
+           static_cast<double>(s.K * s.N) * sb;
+  };
+  for (int32_t t = 1; t < max_steps; ++t) {
+    AbsorbArgs group[4];
+    const Step* gsteps[4];
+    size_t gunit[4];
+    int32_t n = 0;
+    for (size_t u = 0; u < nu; ++u) {
+      const Unit& U = p.units[u];
+      if (t >= U.n_steps) continue;
+      const int32_t k = U.first_step + t;
+      group[n] = args_of(u, k);
+      gsteps[n] = &p.steps[k];
+      gunit[n] = u;
+      ++n;
     }
-    // a rescale on the INIT step of a one-row unit is measured here
-    final_buf[u] = c;
+    const char* kname = "";
+    if (n > 1 && absorb_policy() == 0 && absorb_group_supported(group, n)) {
+      double bytes = 0.0, flops = 0.0;
+      for (int32_t i = 0; i < n; ++i) {
+        bytes += step_bytes(group[i], *gsteps[i]);
+        flops += static_cast<double>(gsteps[i]->flops);
+      }
+      timer.before();
+      TN_HIP(launch_absorb_group(group, n, sa, state, stream, &kname));
+      timer.after(kname, bytes, flops);
+    } else {
+      for (int32_t i = 0; i < n; ++i) {
+        timer.before();
+        TN_HIP(launch_absorb(group[i], sa, state, stream, &kname));
+        timer.after(kname, step_bytes(group[i], *gsteps[i]), static_cast<double>(gsteps[i]->flops));
+      }
+    }
+    for (int32_t i = 0; i < n; ++i) cur[gunit[i]] = 1 - cur[gunit[i]];
   }
+  // a rescale on the INIT step of a one-row unit needs no measurement: its
+  // slot stays "zero" and scales by 2^0
+  for (size_t u = 0; u < nu; ++u) final_buf[u] = cur[u];
 
   if (!p.has_ring) {
     const double* scalar = reinterpret_cast<const double*>(base + L.buf[0][final_buf[0]]);

@@ -53,6 +53,12 @@ bool absorb_mfma_supported(const AbsorbArgs& a);
 hipError_t launch_absorb_mfma(const AbsorbArgs& a, const StagedArrays& st, DevState* state,
                               hipStream_t stream, const char** kname);
 
+// Several independent steps of one kind (same element types, all wide or all
+// narrow) in a single launch; n in 2..4.
+bool absorb_group_supported(const AbsorbArgs* a, int32_t n);
+hipError_t launch_absorb_group(const AbsorbArgs* a, int32_t n, const StagedArrays& st,
+                               DevState* state, hipStream_t stream, const char** kname);
+
 // Kernel policy: 0 = matrix-core kernels where the shape allows, 1 = vector-ALU
 // kernels only (absorption and ring products).
 void set_absorb_policy(int32_t policy);

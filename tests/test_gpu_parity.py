@@ -184,3 +184,39 @@ def test_deterministic_bitwise(tn):
         a = gpu(tn, s, 8, 8, P.QUADRANT, prec)
         b = gpu(tn, s, 8, 8, P.QUADRANT, prec)
         assert (a.mantissa, a.exp2_sum) == (b.mantissa, b.exp2_sum)
+
+
+# ------------------------------------------ configuration 3 (12x12, D=4)
+
+@pytest.fixture(scope="module")
+def cfg3_uniform():
+    s = li.uniform(12, 12, 4, 0)
+    return s, oracle(s, 12, 12, P.QUADRANT)      # the oracle's fastest exact plan
+
+
+@pytest.mark.parametrize("order", [P.COLSWEEP, P.HEURISTIC])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "f64"])
+def test_cfg3_uniform_12x12_d4(tn, cfg3_uniform, order, prec):
+    s, ref = cfg3_uniform
+    got = gpu(tn, s, 12, 12, order, prec)
+    print(f"  12x12 D=4 {prec} order={order}: log|Z| {got.log_abs!r} oracle {ref.log_abs!r}")
+    if prec == "f64":
+        close_f64(got, ref)
+    else:
+        close_log(got, ref.log_abs)
+
+
+@pytest.mark.parametrize("D", [2, 4])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_cfg3_ising_12x12(tn, D, prec):
+    tm = ising_gold()[(12, 12, 0.44)] * (1 if D == 2 else 2)
+    sites = li.ising(12, 12, 0.44) if D == 2 else li.ising_d4(12, 12, 0.44)
+    for order in (P.COLSWEEP, P.HEURISTIC):
+        close_log(gpu(tn, sites, 12, 12, order, prec), tm)
+
+
+def test_cfg3_ising_13x13_d4_f64(tn):
+    # the largest served size: 13x13 two-replica network, FP64 sweep (peak 4^14)
+    tm = 2 * ising_gold()[(13, 13, 0.44)]
+    got = gpu(tn, li.ising_d4(13, 13, 0.44), 13, 13, P.HEURISTIC, "f64")
+    assert got.sign == 1 and abs(got.log_abs - tm) <= 1e-12 * tm

@@ -74,7 +74,10 @@ def test_alone_equals_in_the_mix_bitwise(tn):
 
 
 def test_small_requests_overtake_a_running_large_one(tn):
-    srv = tn.Server(16 * GiB, max_slots=4)
+    # three slots: with 4 hardware queues per process (GPU_MAX_HW_QUEUES) and
+    # the caller's own stream, more slot streams would share a queue with the
+    # large request and wait behind its kernels
+    srv = tn.Server(16 * GiB, max_slots=3)
     big_sites, big_want = ising_request(13, 4, 0.44)
     big = srv.submit(13, 13, big_sites, D=4, precision="f64")
     small = []
