@@ -148,6 +148,18 @@ Layout make_layout(const Plan& p, int32_t prec) {
     L.n_partials = ring_partials(p.ring.m, p.ring.n);
     L.partials = off;
     off = align_up(off + sizeof(double) * static_cast<size_t>(L.n_partials));
+    const Ring& g = p.ring;
+    L.split_ring = prec == TN_PREC_BF16X3 && g.m % 4 == 0 && g.n % 4 == 0;
+    if (L.split_ring) {
+      // unit u as [k][rows]: rows = m for TL/BL, n for TR/BR; k = kx (top) / ky (bottom)
+      const int64_t rows[4] = {g.m, g.n, g.n, g.m};
+      const int64_t kk[4] = {g.kx, g.kx, g.ky, g.ky};
+      for (int u = 0; u < 4; ++u) {
+        const size_t bytes = align_up(static_cast<size_t>(rows[u] * split_k_padded(kk[u])) * 2);
+        L.split[u][0] = off; off += bytes;
+        L.split[u][1] = off; off += bytes;
+      }
+    }
   }
   L.total = off;
   return L;
@@ -356,15 +368,48 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
       const int32_t s = p.units[u].final_slot;
       return s >= 0 ? slot_exp + s : nullptr;
     };
+    int64_t n_part = 0;
+    const char* kname = "";
+    const double es = (t == EL_F64) ? 8.0 : 4.0;
+    double* partials = reinterpret_cast<double*>(base + L.partials);
+    if (L.split_ring && absorb_policy() == 0) {
+      // BF16x3: split + transpose each quadrant tensor once, then NT GEMMs
+      const int64_t rows[4] = {g.m, g.n, g.n, g.m};
+      const int64_t kk[4] = {g.kx, g.kx, g.ky, g.ky};
+      uint16_t* hs[4];
+      uint16_t* ls[4];
+      for (int u = 0; u < 4; ++u) {
+        hs[u] = reinterpret_cast<uint16_t*>(base + L.split[u][0]);
+        ls[u] = reinterpret_cast<uint16_t*>(base + L.split[u][1]);
+        timer.before();
+        TN_HIP(launch_split_transpose(reinterpret_cast<const float*>(unit_ptr(u)), kk[u], rows[u],
+                                      unit_slot(u), hs[u], ls[u], stream));
+        timer.after("split_transpose",
+                    4.0 * static_cast<double>(kk[u] * rows[u]) +
+                        4.0 * static_cast<double>(rows[u] * split_k_padded(kk[u])),
+                    0.0);
+      }
+      // Yt = BL BR^T (BL = unit ya, BR = unit yb), then X = TL TR^T fused with the dot
+      timer.before();
+      TN_HIP(launch_ring_bf16x3_nt(hs[g.ya], ls[g.ya], hs[g.yb], ls[g.yb], g.m, g.n,
+                                   split_k_padded(g.ky), reinterpret_cast<float*>(base + L.yt),
+                                   nullptr, nullptr, stream));
+      timer.after("ring_mfma_bf16x3", es * static_cast<double>(g.ky * (g.m + g.n) + g.m * g.n),
+                  2.0 * static_cast<double>(g.m * g.n * g.ky));
+      timer.before();
+      TN_HIP(launch_ring_bf16x3_nt(hs[g.xa], ls[g.xa], hs[g.xb], ls[g.xb], g.m, g.n,
+                                   split_k_padded(g.kx), nullptr,
+                                   reinterpret_cast<const float*>(base + L.yt), partials, stream));
+      timer.after("ring_mfma_bf16x3", es * static_cast<double>(g.kx * (g.m + g.n) + g.m * g.n),
+                  2.0 * static_cast<double>(g.m * g.n * g.kx) + 2.0 * static_cast<double>(g.m * g.n));
+      n_part = ring_mfma_partials(g.m, g.n);
+    } else {
     RingArgs y;
     y.A = unit_ptr(g.ya); y.B = unit_ptr(g.yb);
     y.type = t; y.arith = arith;
     y.m = g.m; y.n = g.n; y.k = g.ky;
     y.sa = unit_slot(g.ya); y.sb = unit_slot(g.yb);
     y.c_out = base + L.yt; y.dot_with = nullptr; y.partials = nullptr;
-    const char* kname = "";
-    const double es = (t == EL_F64) ? 8.0 : 4.0;
-    int64_t n_part = 0;
     timer.before();
     TN_HIP(launch_ring(y, stream, &kname, &n_part));
     timer.after(kname, es * static_cast<double>(g.ky * (g.m + g.n) + g.m * g.n),
@@ -374,13 +419,14 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
     x.k = g.kx;
     x.sa = unit_slot(g.xa); x.sb = unit_slot(g.xb);
     x.c_out = nullptr; x.dot_with = base + L.yt;
-    x.partials = reinterpret_cast<double*>(base + L.partials);
+    x.partials = partials;
     timer.before();
     TN_HIP(launch_ring(x, stream, &kname, &n_part));
     timer.after(kname, es * static_cast<double>(g.kx * (g.m + g.n) + g.m * g.n),
                 2.0 * static_cast<double>(g.m * g.n * g.kx) + 2.0 * static_cast<double>(g.m * g.n));
+    }
     timer.before();
-    TN_HIP(launch_finalize(state, nullptr, nullptr, x.partials, n_part, stream));
+    TN_HIP(launch_finalize(state, nullptr, nullptr, partials, n_part, stream));
     timer.after("finalize", 0.0, 0.0);
   }
 #undef TN_HIP

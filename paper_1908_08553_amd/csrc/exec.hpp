@@ -26,6 +26,8 @@ struct Layout {
   size_t yt = 0, yt_bytes = 0;       // ring: C^T E
   size_t partials = 0;
   int64_t n_partials = 0;
+  bool split_ring = false;           // BF16x3 ring from pre-split operands
+  size_t split[4][2] = {};           // unit tensor -> (hi, lo) [rows][kp] bf16
   size_t total = 0;
   std::vector<int64_t> s_off;        // staged offset of each step
   std::vector<int32_t> out_type;     // ElemType of each step's output

@@ -367,7 +367,7 @@ int64_t ring_partials(int64_t m, int64_t n) {
 hipError_t launch_ring(const RingArgs& a, hipStream_t stream, const char** kname,
                        int64_t* n_partials) {
   if (g_absorb_policy == 0 && ring_mfma_supported(a)) {
-    *n_partials = ring_mfma_partials(a.m, a.n);
+    *n_partials = ring_mfma_partials_for(a);
     return launch_ring_mfma(a, stream, kname);
   }
   *n_partials = ((a.m + kRT - 1) / kRT) * ((a.n + kRT - 1) / kRT);

@@ -59,6 +59,16 @@ bool absorb_group_supported(const AbsorbArgs* a, int32_t n);
 hipError_t launch_absorb_group(const AbsorbArgs* a, int32_t n, const StagedArrays& st,
                                DevState* state, hipStream_t stream, const char** kname);
 
+// Split BF16x3 ring: T [kd][md] float scaled by 2^-slot -> H, L [md][kp] bf16
+// hi/lo parts, kp = split_k_padded(kd) (zero padded); md % 4 == 0.
+int64_t split_k_padded(int64_t k);
+hipError_t launch_split_transpose(const float* T, int64_t kd, int64_t md, const int32_t* slot,
+                                  uint16_t* H, uint16_t* L, hipStream_t stream);
+// C = A B^T from split operands (A [m][kp], B [n][kp]); fused dot as launch_ring.
+hipError_t launch_ring_bf16x3_nt(const uint16_t* Ah, const uint16_t* Al, const uint16_t* Bh,
+                                 const uint16_t* Bl, int64_t m, int64_t n, int64_t kp, float* c_out,
+                                 const float* dot_with, double* partials, hipStream_t stream);
+
 // Kernel policy: 0 = matrix-core kernels where the shape allows, 1 = vector-ALU
 // kernels only (absorption and ring products).
 void set_absorb_policy(int32_t policy);
@@ -93,6 +103,7 @@ hipError_t launch_ring(const RingArgs& a, hipStream_t stream, const char** kname
 // MFMA ring products (ring_mfma.hip): m % 4 == 0 and n % 4 == 0.
 bool ring_mfma_supported(const RingArgs& a);
 int64_t ring_mfma_partials(int64_t m, int64_t n);
+int64_t ring_mfma_partials_for(const RingArgs& a);   // the kernel launch_ring_mfma picks
 hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** kname);
 
 // Writes state->result from the final scalar (or the sum of `n_partials`

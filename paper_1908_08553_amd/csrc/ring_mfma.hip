@@ -302,6 +302,283 @@ __global__ __launch_bounds__(kThreads) void ring_mfma_bf16x3(
   }
 }
 
+// ------------------------------------------------ f32, 256 x 256 tiles
+// Same operand scheme as ring_mfma<float> on a 256 x 256 output tile: eight
+// waves in a 2 (m) x 4 (n) grid, each 128 x 64 (two 16-byte A reads and one
+// B read per k feed 32 MFMA tiles).  Twice the flops per staged byte of the
+// 128 x 128 tile; the LDS k-slices are double-buffered so one barrier per
+// slice separates staging from compute.
+constexpr int kBT = 256;
+constexpr int kBThreads = 512;
+
+__global__ __launch_bounds__(kBThreads) void ring_mfma_f32_big(
+    const float* __restrict__ A, const float* __restrict__ B, int64_t M, int64_t N, int64_t Kd,
+    const int32_t* sa, const int32_t* sb, float* __restrict__ C, const float* __restrict__ W,
+    double* __restrict__ partials) {
+  __shared__ __attribute__((aligned(16))) float As[2][kBK][kBT];
+  __shared__ __attribute__((aligned(16))) float Bs[2][kBK][kBT];
+  const uint32_t ntm = static_cast<uint32_t>((M + kBT - 1) / kBT);
+  const uint32_t ntn = static_cast<uint32_t>((N + kBT - 1) / kBT);
+  uint32_t tm, tn;
+  tile_of(tm, tn, ntm, ntn);
+  const int64_t m0 = static_cast<int64_t>(tm) * kBT, n0 = static_cast<int64_t>(tn) * kBT;
+  const int ea = shift_of(sa), eb = shift_of(sb);
+  const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+  const int wm = (w >> 2) * 128, wn = (w & 3) * 64;
+  constexpr int kPer = kBK * kBT / 4 / kBThreads;   // 16-byte chunks per thread per operand
+
+  f32x4 ra[kPer], rb[kPer];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int q = threadIdx.x + i * kBThreads;
+      const int kk = q / (kBT / 4), cc = (q % (kBT / 4)) * 4;
+      const int64_t kg = k0 + kk;
+      f32x4 va = {0.f, 0.f, 0.f, 0.f}, vb = {0.f, 0.f, 0.f, 0.f};
+      if (kg < Kd && m0 + cc < M) va = *reinterpret_cast<const f32x4*>(A + kg * M + m0 + cc);
+      if (kg < Kd && n0 + cc < N) vb = *reinterpret_cast<const f32x4*>(B + kg * N + n0 + cc);
+      ra[i] = va;
+      rb[i] = vb;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int q = threadIdx.x + i * kBThreads;
+      const int kk = q / (kBT / 4), cc = (q % (kBT / 4)) * 4;
+      f32x4 va = ra[i], vb = rb[i];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        va[e] = ldexpf(va[e], -ea);
+        vb[e] = ldexpf(vb[e], -eb);
+      }
+      *reinterpret_cast<f32x4*>(&As[buf][kk][cc]) = va;
+      *reinterpret_cast<f32x4*>(&Bs[buf][kk][cc]) = vb;
+    }
+  };
+
+  f32x4 acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = 0; k0 < Kd; k0 += kBK) {
+    const bool more = k0 + kBK < Kd;
+    if (more) fetch(k0 + kBK);
+#pragma unroll
+    for (int kb = 0; kb < kBK; kb += 4) {
+      const f32x4 a0 = *reinterpret_cast<const f32x4*>(&As[buf][kb + g][wm + 4 * c]);
+      const f32x4 a1 = *reinterpret_cast<const f32x4*>(&As[buf][kb + g][wm + 64 + 4 * c]);
+      const f32x4 b4 = *reinterpret_cast<const f32x4*>(&Bs[buf][kb + g][wn + 4 * c]);
+#pragma unroll
+      for (int mm = 0; mm < 4; ++mm)
+#pragma unroll
+        for (int nn = 0; nn < 4; ++nn) {
+          acc[mm][nn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[mm], b4[nn], acc[mm][nn], 0, 0, 0);
+          acc[4 + mm][nn] =
+              __builtin_amdgcn_mfma_f32_16x16x4f32(a1[mm], b4[nn], acc[4 + mm][nn], 0, 0, 0);
+        }
+    }
+    if (more) stash(buf ^ 1);   // the other buffer: last read before the previous barrier
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // lane (c, g) register r of tile (h*4 + mm, nn): m = wm + 64h + 4(4g + r) + mm, n = wn + 4c + nn
+  double part = 0.0;
+  const int64_t nb = n0 + wn + 4 * c;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int mm = 0; mm < 4; ++mm)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm + 64 * h + 4 * (4 * g + r) + mm;
+        if (m >= M || nb >= N) continue;
+        const f32x4 v = {acc[4 * h + mm][0][r], acc[4 * h + mm][1][r], acc[4 * h + mm][2][r],
+                         acc[4 * h + mm][3][r]};
+        if (W) {
+          const f32x4 y = *reinterpret_cast<const f32x4*>(W + m * N + nb);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) part += static_cast<double>(v[e]) * static_cast<double>(y[e]);
+        } else {
+          *reinterpret_cast<f32x4*>(C + m * N + nb) = v;
+        }
+      }
+  if (W) {
+    __shared__ double red[kBThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if (lane == 0) red[w] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int i = 0; i < kBThreads / 64; ++i) sum += red[i];
+      partials[static_cast<int64_t>(tm) * ntn + tn] = sum;
+    }
+  }
+}
+
+// ------------------------------------------- split + transpose for BF16x3
+// T [kd][md] float (k-major, as a quadrant sweep leaves it), scaled by 2^-e,
+// becomes H, L [md][kp] bf16 (hi, lo parts; k-contiguous, rows padded to kp
+// with zeros) so the GEMM below reads 8 consecutive k with one 16-byte load.
+// 64 (k) x 64 (m) tile per 256-thread workgroup: thread (kq, mq) = (t/16, t%16)
+// loads four 16-byte row pieces (k = 4kq..4kq+3, m = 4mq..4mq+3; 16 lanes cover
+// a 256-byte row), transposes its 4x4 block in registers and writes 8 bytes
+// (4 consecutive k) per m row into LDS; the tile leaves as 128-byte row pieces.
+constexpr int kPT = 64;
+constexpr int kPLd = kPT + 8;   // padded LDS row (bf16 entries)
+
+__global__ __launch_bounds__(kThreads) void split_transpose(const float* __restrict__ T,
+                                                            int64_t kd, int64_t md, int64_t kp,
+                                                            const int32_t* slot,
+                                                            uint16_t* __restrict__ H,
+                                                            uint16_t* __restrict__ L) {
+  __shared__ __attribute__((aligned(16))) uint16_t sh[kPT][kPLd];
+  __shared__ __attribute__((aligned(16))) uint16_t sl[kPT][kPLd];
+  const int64_t k0 = static_cast<int64_t>(blockIdx.x) * kPT;
+  const int64_t m0 = static_cast<int64_t>(blockIdx.y) * kPT;
+  const int e = shift_of(slot);
+  const int kq = threadIdx.x >> 4, mq = threadIdx.x & 15;
+  f32x4 v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t k = k0 + 4 * kq + i, m = m0 + 4 * mq;
+    v[i] = (k < kd && m < md) ? *reinterpret_cast<const f32x4*>(T + k * md + m)
+                              : f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    u16x4 h, l;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float x = ldexpf(v[i][c], -e);
+      h[i] = bf16_bits(x);
+      l[i] = bf16_bits(x - bf16_float(h[i]));
+    }
+    *reinterpret_cast<u16x4*>(&sh[4 * mq + c][4 * kq]) = h;
+    *reinterpret_cast<u16x4*>(&sl[4 * mq + c][4 * kq]) = l;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    const int q = threadIdx.x + pass * kThreads;   // 512 chunks of 8 k
+    const int row = q >> 3, j = q & 7;
+    const int64_t m = m0 + row, k = k0 + 8 * j;
+    if (m < md && k < kp) {
+      *reinterpret_cast<u16x8*>(H + m * kp + k) = *reinterpret_cast<const u16x8*>(&sh[row][8 * j]);
+      *reinterpret_cast<u16x8*>(L + m * kp + k) = *reinterpret_cast<const u16x8*>(&sl[row][8 * j]);
+    }
+  }
+}
+
+// ---------------------------------------------- bf16x3 GEMM, k-contiguous
+// C[m][n] = sum_k A[m][k] B[n][k] with A, B given as bf16 (hi, lo) pairs
+// [rows][kp]; three MFMA products per tile (lo*hi + hi*lo + hi*hi, float32
+// accumulation).  Each 32-wide k-slice of the four operand tiles (128 x 32
+// bf16 each) is copied to LDS with 16-byte loads (four lanes per 64-byte row
+// piece), no conversion; lane (c, g) then reads its 8 consecutive k of row
+// wm + 16 t + c with one 16-byte LDS load.
+__global__ __launch_bounds__(kThreads) void ring_bf16x3_nt(
+    const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al,
+    const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl, int64_t M, int64_t N,
+    int64_t kp, float* __restrict__ C, const float* __restrict__ W,
+    double* __restrict__ partials) {
+  __shared__ __attribute__((aligned(16))) uint16_t sAh[kT][kLdk];
+  __shared__ __attribute__((aligned(16))) uint16_t sAl[kT][kLdk];
+  __shared__ __attribute__((aligned(16))) uint16_t sBh[kT][kLdk];
+  __shared__ __attribute__((aligned(16))) uint16_t sBl[kT][kLdk];
+  const uint32_t ntm = static_cast<uint32_t>((M + kT - 1) / kT);
+  const uint32_t ntn = static_cast<uint32_t>((N + kT - 1) / kT);
+  uint32_t tm, tn;
+  tile_of(tm, tn, ntm, ntn);
+  const int64_t m0 = static_cast<int64_t>(tm) * kT, n0 = static_cast<int64_t>(tn) * kT;
+  const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+
+  // staging: 128 rows x 4 chunks of 16 bytes per operand tile, 2 per thread
+  u16x8 rah[2], ral[2], rbh[2], rbl[2];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int q = threadIdx.x + i * kThreads;
+      const int row = q >> 2, j = q & 3;
+      const int64_t ma = m0 + row, nb = n0 + row, k = k0 + 8 * j;
+      const u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+      rah[i] = ma < M ? *reinterpret_cast<const u16x8*>(Ah + ma * kp + k) : z;
+      ral[i] = ma < M ? *reinterpret_cast<const u16x8*>(Al + ma * kp + k) : z;
+      rbh[i] = nb < N ? *reinterpret_cast<const u16x8*>(Bh + nb * kp + k) : z;
+      rbl[i] = nb < N ? *reinterpret_cast<const u16x8*>(Bl + nb * kp + k) : z;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int q = threadIdx.x + i * kThreads;
+      const int row = q >> 2, j = q & 3;
+      *reinterpret_cast<u16x8*>(&sAh[row][8 * j]) = rah[i];
+      *reinterpret_cast<u16x8*>(&sAl[row][8 * j]) = ral[i];
+      *reinterpret_cast<u16x8*>(&sBh[row][8 * j]) = rbh[i];
+      *reinterpret_cast<u16x8*>(&sBl[row][8 * j]) = rbl[i];
+    }
+  };
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  fetch(0);
+  for (int64_t k0 = 0; k0 < kp; k0 += kBK16) {
+    __syncthreads();
+    stash();
+    __syncthreads();
+    if (k0 + kBK16 < kp) fetch(k0 + kBK16);
+    bf16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      ah[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sAh[wm + 16 * t + c][8 * g]));
+      al[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sAl[wm + 16 * t + c][8 * g]));
+      bh[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sBh[wn + 16 * t + c][8 * g]));
+      bl[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sBl[wn + 16 * t + c][8 * g]));
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        f32x4 a = acc[mt][nt];
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bh[nt], a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bl[nt], a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bh[nt], a, 0, 0, 0);
+        acc[mt][nt] = a;
+      }
+  }
+
+  double part = 0.0;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm + 16 * mt + 4 * g + r, n = n0 + wn + 16 * nt + c;
+        if (m >= M || n >= N) continue;
+        if (W) part += static_cast<double>(acc[mt][nt][r]) * static_cast<double>(W[m * N + n]);
+        else C[m * N + n] = acc[mt][nt][r];
+      }
+  if (W) {
+    const double s = block_sum(part);
+    if (threadIdx.x == 0) partials[static_cast<int64_t>(tm) * ntn + tn] = s;
+  }
+}
+
 }  // namespace
 
 bool ring_mfma_supported(const RingArgs& a) {
@@ -310,6 +587,12 @@ bool ring_mfma_supported(const RingArgs& a) {
 
 int64_t ring_mfma_partials(int64_t m, int64_t n) {
   return ((m + kT - 1) / kT) * ((n + kT - 1) / kT);
+}
+
+int64_t ring_mfma_partials_for(const RingArgs& a) {
+  if (a.type != EL_F64 && a.arith != AR_BF16X3 && a.m >= kBT && a.n >= kBT)
+    return ((a.m + kBT - 1) / kBT) * ((a.n + kBT - 1) / kBT);
+  return ring_mfma_partials(a.m, a.n);
 }
 
 hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** kname) {
@@ -328,6 +611,13 @@ hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** 
                        static_cast<const float*>(a.B), a.m, a.n, a.k, a.sa, a.sb,
                        static_cast<float*>(a.c_out), static_cast<const float*>(a.dot_with),
                        a.partials);
+  } else if (a.m >= kBT && a.n >= kBT) {
+    *kname = "ring_mfma_f32";
+    const int64_t big = ((a.m + kBT - 1) / kBT) * ((a.n + kBT - 1) / kBT);
+    hipLaunchKernelGGL(ring_mfma_f32_big, dim3(static_cast<uint32_t>(big)), dim3(kBThreads), 0,
+                       stream, static_cast<const float*>(a.A), static_cast<const float*>(a.B), a.m,
+                       a.n, a.k, a.sa, a.sb, static_cast<float*>(a.c_out),
+                       static_cast<const float*>(a.dot_with), a.partials);
   } else {
     *kname = "ring_mfma_f32";
     hipLaunchKernelGGL((ring_mfma<float>), grid, block, 0, stream,
@@ -335,6 +625,32 @@ hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** 
                        a.k, a.sa, a.sb, static_cast<float*>(a.c_out),
                        static_cast<const float*>(a.dot_with), a.partials);
   }
+  return hipGetLastError();
+}
+
+}  // namespace tn
+
+namespace tn {
+
+int64_t split_k_padded(int64_t k) { return (k + kBK16 - 1) / kBK16 * kBK16; }
+
+hipError_t launch_split_transpose(const float* T, int64_t kd, int64_t md, const int32_t* slot,
+                                  uint16_t* H, uint16_t* L, hipStream_t stream) {
+  const int64_t kp = split_k_padded(kd);
+  const int64_t gx = (kp + kPT - 1) / kPT, gy = (md + kPT - 1) / kPT;
+  if (gx > INT_MAX || gy > 65535 || md % 4 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(split_transpose, dim3(static_cast<uint32_t>(gx), static_cast<uint32_t>(gy)),
+                     dim3(kThreads), 0, stream, T, kd, md, kp, slot, H, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_ring_bf16x3_nt(const uint16_t* Ah, const uint16_t* Al, const uint16_t* Bh,
+                                 const uint16_t* Bl, int64_t m, int64_t n, int64_t kp, float* c_out,
+                                 const float* dot_with, double* partials, hipStream_t stream) {
+  const int64_t tiles = ring_mfma_partials(m, n);
+  if (tiles > INT_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(ring_bf16x3_nt, dim3(static_cast<uint32_t>(tiles)), dim3(kThreads), 0, stream,
+                     Ah, Al, Bh, Bl, m, n, kp, c_out, dot_with, partials);
   return hipGetLastError();
 }
 

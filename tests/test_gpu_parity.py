@@ -220,3 +220,19 @@ def test_cfg3_ising_13x13_d4_f64(tn):
     tm = 2 * ising_gold()[(13, 13, 0.44)]
     got = gpu(tn, li.ising_d4(13, 13, 0.44), 13, 13, P.HEURISTIC, "f64")
     assert got.sign == 1 and abs(got.log_abs - tm) <= 1e-12 * tm
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "f64"])
+def test_ring_with_ragged_tiles(tn, prec):
+    # 8x10 lattice whose quadrant cut gives m = n = 4*4*3*4*4 = 768 (three
+    # 256-wide tiles, six 128-wide ones) and k = 2^4: edge tiles of every ring kernel
+    rows, cols = 8, 10
+    h = np.full((rows, cols - 1), 2)
+    v = np.tile(np.array([4, 4, 3, 4, 4, 4, 4, 3, 4, 4]), (rows - 1, 1))
+    s = li.uniform(rows, cols, 0, 21, hdim=h, vdim=v)
+    ref = oracle(s, rows, cols, P.QUADRANT, 4, 5)
+    got = gpu(tn, s, rows, cols, P.QUADRANT, prec, 4, 5, hdim=h, vdim=v)
+    if prec == "f64":
+        close_f64(got, ref)
+    else:
+        close_log(got, ref.log_abs)
