@@ -402,7 +402,7 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
                                    reinterpret_cast<const float*>(base + L.yt), partials, stream));
       timer.after("ring_mfma_bf16x3", es * static_cast<double>(g.kx * (g.m + g.n) + g.m * g.n),
                   2.0 * static_cast<double>(g.m * g.n * g.kx) + 2.0 * static_cast<double>(g.m * g.n));
-      n_part = ring_mfma_partials(g.m, g.n);
+      n_part = ring_bf16x3_nt_partials(g.m, g.n);
     } else {
     RingArgs y;
     y.A = unit_ptr(g.ya); y.B = unit_ptr(g.yb);

@@ -65,6 +65,7 @@ int64_t split_k_padded(int64_t k);
 hipError_t launch_split_transpose(const float* T, int64_t kd, int64_t md, const int32_t* slot,
                                   uint16_t* H, uint16_t* L, hipStream_t stream);
 // C = A B^T from split operands (A [m][kp], B [n][kp]); fused dot as launch_ring.
+int64_t ring_bf16x3_nt_partials(int64_t m, int64_t n);
 hipError_t launch_ring_bf16x3_nt(const uint16_t* Ah, const uint16_t* Al, const uint16_t* Bh,
                                  const uint16_t* Bl, int64_t m, int64_t n, int64_t kp, float* c_out,
                                  const float* dot_with, double* partials, hipStream_t stream);

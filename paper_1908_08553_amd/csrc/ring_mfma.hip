@@ -579,6 +579,115 @@ __global__ __launch_bounds__(kThreads) void ring_bf16x3_nt(
   }
 }
 
+// ------------------------------------------- bf16x3 NT, 256 x 256 tiles
+// ring_bf16x3_nt on a 256 x 256 tile: eight waves (2 x 4), each 128 x 64, so
+// every staged k-slice feeds twice the MFMA work.  The four 256 x 32 operand
+// slices (80 KiB of LDS) are single-buffered with a register prefetch of the
+// next slice.
+__global__ __launch_bounds__(kBThreads) void ring_bf16x3_nt_big(
+    const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al,
+    const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl, int64_t M, int64_t N,
+    int64_t kp, float* __restrict__ C, const float* __restrict__ W,
+    double* __restrict__ partials) {
+  __shared__ __attribute__((aligned(16))) uint16_t sAh[kBT][kLdk];
+  __shared__ __attribute__((aligned(16))) uint16_t sAl[kBT][kLdk];
+  __shared__ __attribute__((aligned(16))) uint16_t sBh[kBT][kLdk];
+  __shared__ __attribute__((aligned(16))) uint16_t sBl[kBT][kLdk];
+  const uint32_t ntm = static_cast<uint32_t>((M + kBT - 1) / kBT);
+  const uint32_t ntn = static_cast<uint32_t>((N + kBT - 1) / kBT);
+  uint32_t tm, tn;
+  tile_of(tm, tn, ntm, ntn);
+  const int64_t m0 = static_cast<int64_t>(tm) * kBT, n0 = static_cast<int64_t>(tn) * kBT;
+  const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+  const int wm = (w >> 2) * 128, wn = (w & 3) * 64;
+
+  // 256 rows x 4 chunks of 16 bytes per operand slice, 2 per thread
+  u16x8 rah[2], ral[2], rbh[2], rbl[2];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int q = threadIdx.x + i * kBThreads;
+      const int row = q >> 2, j = q & 3;
+      const int64_t ma = m0 + row, nb = n0 + row, k = k0 + 8 * j;
+      const u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+      rah[i] = ma < M ? *reinterpret_cast<const u16x8*>(Ah + ma * kp + k) : z;
+      ral[i] = ma < M ? *reinterpret_cast<const u16x8*>(Al + ma * kp + k) : z;
+      rbh[i] = nb < N ? *reinterpret_cast<const u16x8*>(Bh + nb * kp + k) : z;
+      rbl[i] = nb < N ? *reinterpret_cast<const u16x8*>(Bl + nb * kp + k) : z;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int q = threadIdx.x + i * kBThreads;
+      const int row = q >> 2, j = q & 3;
+      *reinterpret_cast<u16x8*>(&sAh[row][8 * j]) = rah[i];
+      *reinterpret_cast<u16x8*>(&sAl[row][8 * j]) = ral[i];
+      *reinterpret_cast<u16x8*>(&sBh[row][8 * j]) = rbh[i];
+      *reinterpret_cast<u16x8*>(&sBl[row][8 * j]) = rbl[i];
+    }
+  };
+
+  f32x4 acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  fetch(0);
+  for (int64_t k0 = 0; k0 < kp; k0 += kBK16) {
+    __syncthreads();
+    stash();
+    __syncthreads();
+    if (k0 + kBK16 < kp) fetch(k0 + kBK16);
+    bf16x8 bh[4], bl[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      bh[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sBh[wn + 16 * t + c][8 * g]));
+      bl[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sBl[wn + 16 * t + c][8 * g]));
+    }
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+      const bf16x8 ah =
+          __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sAh[wm + 16 * mt + c][8 * g]));
+      const bf16x8 al =
+          __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sAl[wm + 16 * mt + c][8 * g]));
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        f32x4 a = acc[mt][nt];
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[nt], a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[nt], a, 0, 0, 0);
+        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[nt], a, 0, 0, 0);
+        acc[mt][nt] = a;
+      }
+    }
+  }
+
+  double part = 0.0;
+#pragma unroll
+  for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm + 16 * mt + 4 * g + r, n = n0 + wn + 16 * nt + c;
+        if (m >= M || n >= N) continue;
+        if (W) part += static_cast<double>(acc[mt][nt][r]) * static_cast<double>(W[m * N + n]);
+        else C[m * N + n] = acc[mt][nt][r];
+      }
+  if (W) {
+    __shared__ double red[kBThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if (lane == 0) red[w] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int i = 0; i < kBThreads / 64; ++i) sum += red[i];
+      partials[static_cast<int64_t>(tm) * ntn + tn] = sum;
+    }
+  }
+}
+
 }  // namespace
 
 bool ring_mfma_supported(const RingArgs& a) {
@@ -644,9 +753,21 @@ hipError_t launch_split_transpose(const float* T, int64_t kd, int64_t md, const 
   return hipGetLastError();
 }
 
+int64_t ring_bf16x3_nt_partials(int64_t m, int64_t n) {
+  if (m >= kBT && n >= kBT) return ((m + kBT - 1) / kBT) * ((n + kBT - 1) / kBT);
+  return ring_mfma_partials(m, n);
+}
+
 hipError_t launch_ring_bf16x3_nt(const uint16_t* Ah, const uint16_t* Al, const uint16_t* Bh,
                                  const uint16_t* Bl, int64_t m, int64_t n, int64_t kp, float* c_out,
                                  const float* dot_with, double* partials, hipStream_t stream) {
+  if (m >= kBT && n >= kBT) {
+    const int64_t tiles = ring_bf16x3_nt_partials(m, n);
+    if (tiles > INT_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(ring_bf16x3_nt_big, dim3(static_cast<uint32_t>(tiles)), dim3(kBThreads), 0,
+                       stream, Ah, Al, Bh, Bl, m, n, kp, c_out, dot_with, partials);
+    return hipGetLastError();
+  }
   const int64_t tiles = ring_mfma_partials(m, n);
   if (tiles > INT_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(ring_bf16x3_nt, dim3(static_cast<uint32_t>(tiles)), dim3(kThreads), 0, stream,
