@@ -36,19 +36,8 @@ def log(*a):
 
 
 def kernel_stats():
-    import ctypes as C
-    from paper_1908_08553_amd._native import lib
-
-    class KS(C.Structure):
-        _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double),
-                    ("bytes", C.c_double), ("flops", C.c_double)]
-    n = C.c_int32(0)
-    arr = (KS * 64)()
-    lib.tn_profile_read.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
-    lib.tn_profile_read(C.cast(arr, C.c_void_p), 64, C.byref(n))
-    return [{"name": arr[i].name.decode(), "launches": arr[i].launches,
-             "total_ms": arr[i].total_ms, "bytes": arr[i].bytes, "flops": arr[i].flops}
-            for i in range(min(n.value, 64))]
+    from paper_1908_08553_amd import tn_profile_read
+    return tn_profile_read()
 
 
 def pct(xs, q):

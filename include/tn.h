@@ -254,9 +254,15 @@ tn_status tn_server_destroy(tn_server* server);
  *                        vector-ALU kernels elsewhere;
  *                        1 = vector-ALU kernels only (reference path).
  *   TN_OPT_BATCH_THREADS : batch workgroup size used when a tn_batch_config is
- *                        NULL or zero (and by tn_contract_batch).            */
+ *                        NULL or zero (and by tn_contract_batch).
+ *   TN_OPT_FUSE_STEPS  : 1 (default) = two consecutive bulk absorptions of one
+ *                        column with D = 4 legs run as one pass over the
+ *                        boundary (same arithmetic, same results, half the
+ *                        boundary traffic of the pair); 0 = one launch per
+ *                        step.  Only acts with TN_OPT_KERNEL_IMPL = 0.       */
 #define TN_OPT_KERNEL_IMPL 0
 #define TN_OPT_BATCH_THREADS 1
+#define TN_OPT_FUSE_STEPS 2
 tn_status tn_set_option(int32_t option, int64_t value);
 
 /* ------------------------------------------------------------ profiling

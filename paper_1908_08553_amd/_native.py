@@ -194,6 +194,30 @@ def tn_contract_grid(plan: Plan, site_ptrs: Sequence[int], sites_on_device: bool
 
 TN_OPT_KERNEL_IMPL = 0
 TN_OPT_BATCH_THREADS = 1
+TN_OPT_FUSE_STEPS = 2
+
+
+class tn_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("bytes", C.c_double), ("flops", C.c_double)]
+
+
+lib.tn_profile_read.restype = C.c_int32
+lib.tn_profile_read.argtypes = [C.POINTER(tn_kernel_stat), C.c_int32, C.POINTER(C.c_int32)]
+
+
+def tn_profile_enable(on: bool) -> None:
+    _check(lib.tn_profile_enable(1 if on else 0))
+
+
+def tn_profile_read(cap: int = 64):
+    """Per-kernel totals recorded since tn_profile_enable(True), as dicts."""
+    arr = (tn_kernel_stat * cap)()
+    n = C.c_int32(0)
+    _check(lib.tn_profile_read(arr, cap, C.byref(n)))
+    return [{"name": arr[i].name.decode(), "launches": arr[i].launches,
+             "total_ms": arr[i].total_ms, "bytes": arr[i].bytes, "flops": arr[i].flops}
+            for i in range(min(n.value, cap))]
 
 
 def tn_set_option(option: int, value: int) -> None:

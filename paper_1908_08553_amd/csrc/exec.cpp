@@ -33,6 +33,19 @@ int32_t step_out_type(const Plan& p, const Step& s, int32_t prec) {
 
 const char* hip_msg(hipError_t e) { return hipGetErrorString(e); }
 
+// Steps s1, s2 are consecutive rows of one column of one sweep whose four
+// legs between them all have dimension 4 (K = N = 16 for both, the leg s2
+// adds to the prefix and the one s1 keeps in the suffix of dimension 4), no
+// rescale between them, and a suffix of whole 64-entry runs: the shape
+// absorb_pair fuses.
+bool pair_ok(const Step& s1, const Step& s2) {
+  if (s1.kind != STEP_ABSORB || s2.kind != STEP_ABSORB) return false;
+  if (s1.unit != s2.unit || s1.col != s2.col || s1.rescale >= 0 || s2.scale_in >= 0) return false;
+  if (s1.K != 16 || s1.N != 16 || s2.K != 16 || s2.N != 16) return false;
+  if (s2.pre != 4 * s1.pre || s1.post != 4 * s2.post || s2.post % 64 != 0) return false;
+  return s1.pre * (s2.post / 64) <= static_cast<int64_t>(INT32_MAX);
+}
+
 struct KStat { int64_t launches = 0; double ms = 0, bytes = 0, flops = 0; };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
@@ -296,8 +309,6 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
   // units and launch same-kind steps of several units together.
   const size_t nu = p.units.size();
   std::vector<int32_t> final_buf(nu, 0), cur(nu, 0);
-  int32_t max_steps = 0;
-  for (const Unit& U : p.units) max_steps = std::max(max_steps, U.n_steps);
   auto args_of = [&](size_t u, int32_t k) {
     const Step& s = p.steps[k];
     AbsorbArgs a;
@@ -318,21 +329,64 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
            static_cast<double>(s.out) * elem_bytes(a.out_type) +
            static_cast<double>(s.K * s.N) * sb;
   };
-  for (int32_t t = 1; t < max_steps; ++t) {
+  // Per unit, the absorption steps in order, each either alone or fused with
+  // the next one (first step index of each action; pair flag).
+  struct Action { int32_t k; bool pair; };
+  std::vector<std::vector<Action>> acts(nu);
+  size_t max_acts = 0;
+  for (size_t u = 0; u < nu; ++u) {
+    const Unit& U = p.units[u];
+    for (int32_t t = 1; t < U.n_steps; ++t) {
+      const int32_t k = U.first_step + t;
+      const bool pair = t + 1 < U.n_steps && fuse_steps() && absorb_policy() == 0 &&
+                        pair_ok(p.steps[k], p.steps[k + 1]) &&
+                        L.out_type[k - 1] == L.out_type[k] && L.out_type[k] == L.out_type[k + 1];
+      acts[u].push_back({k, pair});
+      if (pair) ++t;
+    }
+    max_acts = std::max(max_acts, acts[u].size());
+  }
+  for (size_t t = 0; t < max_acts; ++t) {
     AbsorbArgs group[4];
     const Step* gsteps[4];
-    size_t gunit[4];
-    int32_t n = 0;
+    PairArgs pairs[4];
+    double pair_bytes = 0.0, pair_flops = 0.0;
+    int32_t n = 0, np = 0;
     for (size_t u = 0; u < nu; ++u) {
-      const Unit& U = p.units[u];
-      if (t >= U.n_steps) continue;
-      const int32_t k = U.first_step + t;
-      group[n] = args_of(u, k);
-      gsteps[n] = &p.steps[k];
-      gunit[n] = u;
-      ++n;
+      if (t >= acts[u].size()) continue;
+      const Action& ac = acts[u][t];
+      const AbsorbArgs a = args_of(u, ac.k);
+      if (ac.pair) {
+        const Step& s1 = p.steps[ac.k];
+        const Step& s2 = p.steps[ac.k + 1];
+        PairArgs& x = pairs[np++];
+        x.in = a.in;
+        x.out = a.out;
+        x.type = a.in_type;
+        x.arith = arith;
+        x.pre = s1.pre;
+        x.post2 = s2.post;
+        x.s_off1 = L.s_off[ac.k];
+        x.s_off2 = L.s_off[ac.k + 1];
+        x.scale_slot = a.scale_slot;
+        x.max_slot = s2.rescale >= 0 ? slot_exp + s2.rescale : nullptr;
+        const double eb = elem_bytes(a.in_type);
+        pair_bytes += static_cast<double>(s1.pre * s1.K * s1.post) * eb +
+                      static_cast<double>(s2.out) * eb + 2.0 * 256.0 * eb;
+        pair_flops += static_cast<double>(s1.flops + s2.flops);
+      } else {
+        group[n] = a;
+        gsteps[n] = &p.steps[ac.k];
+        ++n;
+      }
+      cur[u] = 1 - cur[u];
     }
     const char* kname = "";
+    if (np > 0) {
+      timer.before();
+      TN_HIP(launch_absorb_pairs(pairs, np, sa, state, stream, &kname));
+      timer.after(kname, pair_bytes, pair_flops);
+    }
     if (n > 1 && absorb_policy() == 0 && absorb_group_supported(group, n)) {
       double bytes = 0.0, flops = 0.0;
       for (int32_t i = 0; i < n; ++i) {
@@ -349,7 +403,6 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
         timer.after(kname, step_bytes(group[i], *gsteps[i]), static_cast<double>(gsteps[i]->flops));
       }
     }
-    for (int32_t i = 0; i < n; ++i) cur[gunit[i]] = 1 - cur[gunit[i]];
   }
   // a rescale on the INIT step of a one-row unit needs no measurement: its
   // slot stays "zero" and scales by 2^0

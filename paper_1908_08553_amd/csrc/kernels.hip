@@ -315,10 +315,13 @@ hipError_t launch_stage(const StageDesc* descs, int32_t n_steps, StagedArrays st
 
 namespace {
 int32_t g_absorb_policy = 0;
+int32_t g_fuse_steps = 1;
 }
 
 void set_absorb_policy(int32_t policy) { g_absorb_policy = policy; }
 int32_t absorb_policy() { return g_absorb_policy; }
+void set_fuse_steps(int32_t on) { g_fuse_steps = on; }
+int32_t fuse_steps() { return g_fuse_steps; }
 
 hipError_t launch_absorb(const AbsorbArgs& a, const StagedArrays& st, DevState* state,
                          hipStream_t stream, const char** kname) {

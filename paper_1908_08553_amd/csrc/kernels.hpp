@@ -70,10 +70,29 @@ hipError_t launch_ring_bf16x3_nt(const uint16_t* Ah, const uint16_t* Al, const u
                                  const uint16_t* Bl, int64_t m, int64_t n, int64_t kp, float* c_out,
                                  const float* dot_with, double* partials, hipStream_t stream);
 
+// Two consecutive D = 4 bulk steps of one column fused into one pass (see
+// absorb_pair in absorb_mfma.hip): s1 = (pre, 16, 16, 4*post2), s2 = (4*pre,
+// 16, 16, post2), post2 % 64 == 0, same element type in and out.
+struct PairArgs {
+  const void* in;
+  void* out;
+  int32_t type;                // ElemType of in and out
+  int32_t arith;
+  int64_t pre, post2;
+  int64_t s_off1, s_off2;
+  const int32_t* scale_slot;   // scales s1's input (nullable)
+  int32_t* max_slot;           // measured after s2 (nullable)
+};
+hipError_t launch_absorb_pairs(const PairArgs* a, int32_t n, const StagedArrays& st,
+                               DevState* state, hipStream_t stream, const char** kname);
+
 // Kernel policy: 0 = matrix-core kernels where the shape allows, 1 = vector-ALU
 // kernels only (absorption and ring products).
 void set_absorb_policy(int32_t policy);
 int32_t absorb_policy();
+// 1 = fuse eligible step pairs (absorb_pair), 0 = one launch per step.
+void set_fuse_steps(int32_t on);
+int32_t fuse_steps();
 
 // *kname receives the name of the kernel variant launched.
 hipError_t launch_absorb(const AbsorbArgs& a, const StagedArrays& st, DevState* state,

@@ -52,9 +52,11 @@ def test_mixed_requests_match_the_transfer_matrix(tn):
 
 
 def test_alone_equals_in_the_mix_bitwise(tn):
-    specs = [(5, 4, 0.3, "f64"), (9, 2, 0.5, "bf16x3"), (7, 4, 0.7, "f64"), (4, 2, 0.2, "bf16x3"),
+    # the 13x13 FP64 request runs long enough for the others to be admitted
+    # beside it, whatever their own speed
+    specs = [(13, 4, 0.44, "f64"), (5, 4, 0.3, "f64"), (9, 2, 0.5, "bf16x3"), (7, 4, 0.7, "f64"), (4, 2, 0.2, "bf16x3"),
              (10, 4, 0.44, "bf16x3"), (6, 4, 0.6, "f64")]
-    srv = tn.Server(8 * GiB, max_slots=6)
+    srv = tn.Server(16 * GiB, max_slots=3)
     alone = []
     for L, D, K, prec in specs:
         sites, _ = ising_request(L, D, K)
