@@ -56,9 +56,7 @@ def run_leg(tn, torch, rows, cols, D, kind, seed, order, prec, steps, warmup, pr
     res = None
     for _ in range(warmup):
         res = tn.contract_grid(plan, sites, prec, ws, stream)
-    torch.cuda.synchronize()
-    if profile:
-        tn.lib.tn_profile_enable(1)
+    # timed pass: no per-launch events
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -68,9 +66,16 @@ def run_leg(tn, torch, rows, cols, D, kind, seed, order, prec, steps, warmup, pr
         lat.append(time.perf_counter() - a)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ks = kernel_stats() if profile else None
+    ks = None
     if profile:
-        tn.lib.tn_profile_enable(0)
+        # a second pass of the same steps with every launch bracketed by HIP
+        # events on its own stream: per-kernel durations for the roofline
+        tn.tn_profile_enable(True)
+        for _ in range(steps):
+            tn.contract_grid(plan, sites, prec, ws, stream)
+        torch.cuda.synchronize()
+        ks = kernel_stats()
+        tn.tn_profile_enable(False)
     return {"rows": rows, "cols": cols, "D": D, "inputs": kind, "order": info["order"],
             "quad": list(info["quad"]), "precision": prec, "ms": 1e3 * dt / steps,
             "p50_ms": 1e3 * pct(lat, 0.5), "p99_ms": 1e3 * pct(lat, 0.99),

@@ -230,6 +230,29 @@ void fill_stage_descs(const Plan& p, const Layout& L, int64_t s_base,
   }
 }
 
+HostKeep::~HostKeep() {
+  if (p_) (void)hipHostFree(p_);
+}
+
+char* HostKeep::block(size_t bytes, hipError_t* e) {
+  *e = hipSuccess;
+  if (bytes <= cap_) return p_;
+  if (p_) (void)hipHostFree(p_);
+  p_ = nullptr;
+  cap_ = 0;
+  const size_t want = std::max<size_t>(align_up(bytes), 64 * 1024);
+  void* q = nullptr;
+  *e = hipHostMalloc(&q, want, hipHostMallocDefault);
+  if (*e != hipSuccess) return nullptr;
+  p_ = static_cast<char*>(q);
+  cap_ = want;
+  return p_;
+}
+
+size_t head_bytes(const Plan& p, const Layout& L) {
+  return align_up(L.descs + sizeof(StageDesc) * p.steps.size());
+}
+
 tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                   void* ws, size_t ws_bytes, hipStream_t stream, HostKeep& keep,
                   LaunchTimer& timer, std::string& err) {
@@ -271,21 +294,24 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
     }
   }
 
-  // staging descriptors
+  // head image: state header (zeroed counters), exponent slots (written by the
+  // staging launch) and staging descriptors, uploaded in one copy
   const size_t nsteps = p.steps.size();
-  std::vector<StageDesc>& descs = keep.descs;
-  descs.assign(nsteps, StageDesc{});
+  const size_t head = head_bytes(p, L);
+  char* img = keep.block(head + sizeof(tn_result), &e);
+  if (!img) {
+    err = std::string("hipHostMalloc: ") + hip_msg(e);
+    return TN_ENOMEM;
+  }
+  std::memset(img, 0, L.descs);
+  DevState* hs = reinterpret_cast<DevState*>(img + L.state);
+  hs->n_slots = p.slots;
+  hs->n_steps = static_cast<int32_t>(nsteps);
   char* init_dst[4];
   for (size_t u = 0; u < p.units.size(); ++u) init_dst[u] = base + L.buf[u][0];
-  fill_stage_descs(p, L, 0, dsite.data(), init_dst, descs.data());
-  TN_HIP(hipMemcpyAsync(base + L.descs, descs.data(), sizeof(StageDesc) * nsteps,
-                        hipMemcpyHostToDevice, stream));
-  // state header
-  DevState& hs = keep.hs;
-  std::memset(&hs, 0, sizeof(hs));
-  hs.n_slots = p.slots;
-  hs.n_steps = static_cast<int32_t>(nsteps);
-  TN_HIP(hipMemcpyAsync(base + L.state, &hs, sizeof(hs), hipMemcpyHostToDevice, stream));
+  fill_stage_descs(p, L, 0, dsite.data(), init_dst, reinterpret_cast<StageDesc*>(img + L.descs));
+  TN_HIP(hipMemcpyAsync(base + L.state, img + L.state, head - L.state, hipMemcpyHostToDevice,
+                        stream));
 
   DevState* state = reinterpret_cast<DevState*>(base + L.state);
   int32_t* slot_exp = reinterpret_cast<int32_t*>(state + 1);
@@ -489,19 +515,26 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
 tn_status contract(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                    void* ws, size_t ws_bytes, hipStream_t stream, tn_result* out,
                    std::string& err) {
-  HostKeep keep;
+  // each call waits for its stream before returning, so one pinned image per
+  // thread is free again at the next call; it is kept until the process ends
+  // (never freed from a thread-exit destructor that may run after the HIP
+  // runtime has shut down)
+  thread_local HostKeep* const keep_ptr = new HostKeep;
+  HostKeep& keep = *keep_ptr;
   LaunchTimer timer(stream);
   const tn_status s = enqueue(p, sites, on_device, prec, ws, ws_bytes, stream, keep, timer, err);
   if (s != TN_OK) return s;
   const Layout L = make_layout(p, prec);
   const DevState* state = reinterpret_cast<const DevState*>(static_cast<char*>(ws) + L.state);
-  hipError_t e = hipMemcpyAsync(out, &state->result, sizeof(tn_result), hipMemcpyDeviceToHost,
+  tn_result* staged = reinterpret_cast<tn_result*>(keep.data() + head_bytes(p, L));
+  hipError_t e = hipMemcpyAsync(staged, &state->result, sizeof(tn_result), hipMemcpyDeviceToHost,
                                 stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
     err = std::string("result copy: ") + hip_msg(e);
     return TN_EDEVICE;
   }
+  *out = *staged;
   timer.flush();
   if (out->status != TN_OK) {
     err = "non-finite value in the inputs or an intermediate";

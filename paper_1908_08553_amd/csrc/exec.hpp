@@ -67,12 +67,28 @@ class LaunchTimer {
 void fill_stage_descs(const Plan& p, const Layout& L, int64_t s_base,
                       const double* const* dsite, char* const* init_dst, StageDesc* descs);
 
-// Host-side sources of the asynchronous copies an enqueue issues; they must
-// outlive the stream work.
-struct HostKeep {
-  std::vector<StageDesc> descs;
-  DevState hs;
+// Pinned host image of the workspace head (DevState, exponent slots, stage
+// descriptors) that an enqueue uploads in one asynchronous copy, plus room
+// for the result record copied back.  Grown with hipHostMalloc and reused;
+// the stream work that reads it must finish before the next enqueue through
+// the same HostKeep (one per calling thread, one per server slot).
+class HostKeep {
+ public:
+  HostKeep() = default;
+  ~HostKeep();
+  HostKeep(const HostKeep&) = delete;
+  HostKeep& operator=(const HostKeep&) = delete;
+  // At least `bytes` of pinned memory (contents unspecified), or nullptr with
+  // *e set when the allocation fails.
+  char* block(size_t bytes, hipError_t* e);
+  char* data() const { return p_; }
+ private:
+  char* p_ = nullptr;
+  size_t cap_ = 0;
 };
+
+// Bytes of the uploaded head image and offset of the result record in it.
+size_t head_bytes(const Plan& p, const Layout& L);
 
 // Issue every copy and launch of one contraction on `stream` without waiting;
 // the result record lands in the workspace's DevState (offset Layout.state).

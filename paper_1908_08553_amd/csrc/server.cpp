@@ -54,8 +54,8 @@ struct Request {
   size_t footprint = 0;
   size_t arena_off = 0;
   size_t state_off = 0;
+  size_t result_off = 0;                    // result record in the slot's pinned image
   int32_t slot = -1;
-  HostKeep keep;
   hipEvent_t done = nullptr;
   int64_t t_submit = 0, t_admit = 0, t_done = 0;
   tn_result result{};
@@ -66,7 +66,9 @@ struct Request {
 // First-fit allocator over [0, size) with coalescing.
 class Arena {
  public:
-  explicit Arena(size_t size) : size_(size) { free_[0] = size; }
+  explicit Arena(size_t size) {
+    if (size) free_[0] = size;
+  }
   bool alloc(size_t n, size_t* off) {
     for (auto it = free_.begin(); it != free_.end(); ++it) {
       if (it->second >= n) {
@@ -98,7 +100,6 @@ class Arena {
   }
   size_t used() const { return used_; }
  private:
-  size_t size_;
   size_t used_ = 0;
   std::map<size_t, size_t> free_;
 };
@@ -112,6 +113,9 @@ struct ServerImpl {
   int device = 0;
   std::vector<hipStream_t> streams;
   std::vector<int32_t> slot_busy;
+  // pinned upload image per slot: a slot runs one request at a time and is
+  // released only after that request's stream work has finished
+  std::vector<std::unique_ptr<HostKeep>> keeps;
   Arena alloc{0};
   std::deque<Request*> queue;
   std::vector<Request*> active;
@@ -129,13 +133,15 @@ namespace {
 
 void complete(ServerImpl* s, Request* r) {
   const hipStream_t st = s->streams[r->slot];
-  hipError_t e = hipMemcpyAsync(&r->result, s->arena + r->state_off, sizeof(tn_result),
+  tn_result* staged = reinterpret_cast<tn_result*>(s->keeps[r->slot]->data() + r->result_off);
+  hipError_t e = hipMemcpyAsync(staged, s->arena + r->state_off, sizeof(tn_result),
                                 hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     std::memset(&r->result, 0, sizeof(r->result));
     r->status = TN_EDEVICE;
   } else {
+    r->result = *staged;
     r->status = r->result.status;
   }
   r->t_done = now_ns();
@@ -173,9 +179,10 @@ void scheduler(ServerImpl* s) {
       const hipStream_t st = s->streams[r->slot];
       LaunchTimer timer(st, false);
       tn_status rc = enqueue(r->plan, r->site_ptrs.data(), false, r->prec, s->arena + r->arena_off,
-                             r->footprint, st, r->keep, timer, err);
+                             r->footprint, st, *s->keeps[r->slot], timer, err);
       const Layout L = make_layout(r->plan, r->prec);
       r->state_off = r->arena_off + L.state;
+      r->result_off = head_bytes(r->plan, L);
       if (rc == TN_OK && hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess)
         rc = TN_EDEVICE;
       if (rc == TN_OK && hipEventRecord(r->done, st) != hipSuccess) rc = TN_EDEVICE;
@@ -203,7 +210,6 @@ void scheduler(ServerImpl* s) {
       s->alloc.release(r->arena_off, r->footprint);
       s->slot_busy[r->slot] = 0;
       r->state = DONE;
-      r->keep.descs.clear();
       r->sites.clear();
       for (size_t k = 0; k < s->active.size(); ++k)
         if (s->active[k] == r) { s->active.erase(s->active.begin() + k); break; }
@@ -240,6 +246,7 @@ tn_status server_create(void* arena, size_t arena_bytes, int32_t max_slots, int3
   if (hipGetDevice(&s->device) != hipSuccess) { err = "hipGetDevice failed"; delete s; return TN_EDEVICE; }
   s->streams.resize(max_slots, nullptr);
   s->slot_busy.assign(max_slots, 0);
+  for (int32_t k = 0; k < max_slots; ++k) s->keeps.push_back(std::make_unique<HostKeep>());
   for (int32_t k = 0; k < max_slots; ++k) {
     if (hipStreamCreateWithFlags(&s->streams[k], hipStreamNonBlocking) != hipSuccess) {
       for (int32_t j = 0; j < k; ++j) (void)hipStreamDestroy(s->streams[j]);
