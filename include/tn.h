@@ -255,14 +255,23 @@ tn_status tn_server_destroy(tn_server* server);
  *                        1 = vector-ALU kernels only (reference path).
  *   TN_OPT_BATCH_THREADS : batch workgroup size used when a tn_batch_config is
  *                        NULL or zero (and by tn_contract_batch).
- *   TN_OPT_FUSE_STEPS  : 1 (default) = two consecutive bulk absorptions of one
- *                        column with D = 4 legs run as one pass over the
- *                        boundary (same arithmetic, same results, half the
- *                        boundary traffic of the pair); 0 = one launch per
- *                        step.  Only acts with TN_OPT_KERNEL_IMPL = 0.       */
+ *   TN_OPT_FUSE_STEPS  : how consecutive absorptions of one column share a
+ *                        pass over the boundary (only with
+ *                        TN_OPT_KERNEL_IMPL = 0):
+ *                        2 (default) = chunks of up to 4 rows (3 in FP64)
+ *                        with D = 4 legs between them, the slice held on chip;
+ *                        1 = pairs of bulk rows (same products in the same
+ *                        order as single steps: bitwise-identical results);
+ *                        0 = one launch per step.
+ *   TN_OPT_CHUNK_SCHEDULE : workgroups of a column-chunk launch: 0 (default)
+ *                        = one per 16-fibre tile; 1 = as many as are resident
+ *                        at once, each over a contiguous run of tiles with
+ *                        the next tile's slice loaded during the current one.
+ *                        Results are identical either way.                  */
 #define TN_OPT_KERNEL_IMPL 0
 #define TN_OPT_BATCH_THREADS 1
 #define TN_OPT_FUSE_STEPS 2
+#define TN_OPT_CHUNK_SCHEDULE 3
 tn_status tn_set_option(int32_t option, int64_t value);
 
 /* ------------------------------------------------------------ profiling

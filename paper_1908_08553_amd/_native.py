@@ -195,6 +195,7 @@ def tn_contract_grid(plan: Plan, site_ptrs: Sequence[int], sites_on_device: bool
 TN_OPT_KERNEL_IMPL = 0
 TN_OPT_BATCH_THREADS = 1
 TN_OPT_FUSE_STEPS = 2
+TN_OPT_CHUNK_SCHEDULE = 3
 
 
 class tn_kernel_stat(C.Structure):

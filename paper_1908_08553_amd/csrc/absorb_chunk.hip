@@ -1,0 +1,677 @@
+// Column-chunk absorption: k consecutive rows (2 <= k <= 4) of one column of a
+// sweep applied to a slice of the boundary held in LDS, so the boundary makes
+// one HBM round trip per chunk instead of one per step (paper §4: the
+// pairwise, sequential contraction; only the memory schedule changes).
+//
+// Slice.  Before the chunk the boundary is [p][K1 legs][h_{i+1} .. h_{i+k-1}]
+// [q] (p = prefix of the first step, q = suffix of the last one).  A workgroup
+// takes SP "spectator" fibres s = (p, q), SP * sizeof(T) = 128 bytes: SP
+// consecutive q of one p when the suffix has at least SP entries, else SP /
+// post consecutive p with all their q.  For those spectators the chunk only
+// touches the rows
+//     row = (prefix * 16 + kidx) * M + m
+// (prefix = new h' legs so far, kidx = (v, h) = the step's K index, m = the
+// h legs still to absorb, M = 4^(rows left after this one)): the natural
+// linear order of the slice.  Step j reads, for each (prefix, m), the 16 rows
+// kidx = 0..15 and writes its 16 outputs n = (h', v') to the same 16 rows, so
+// the slice is updated in place: one LDS buffer of 16 * 4^(k-1) rows x SP.
+//
+// Products.  D[n][s] = sum_k S[k][n] X[k][s] on 16x16 MFMA tiles: A = the
+// (zero-padded) site matrix transposed, B = 16 spectators of the 16 rows.
+// Edge rows: a first step with K = 4 (top edge) reads only kidx < 4 and its
+// site matrix is padded with zero rows; a last step with N = 4 (bottom edge)
+// writes n = 4 n' (zero columns elsewhere) and only those rows are stored.
+// The padded matrices of the chunk's steps are staged in LDS once per unit.
+//
+// Schedule: see Cfg.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+
+#include "absorb_device.hpp"
+#include "kernels.hpp"
+
+namespace tn {
+namespace {
+
+using namespace dev;
+
+constexpr int kChunkGroup = 4;
+
+struct ChunkUnit {
+  const void* in;
+  void* out;
+  const void* S[kChunkMax];
+  const uint16_t* hi[kChunkMax];
+  const uint16_t* lo[kChunkMax];
+  int64_t pre, post;     // prefix of the first step, suffix of the last
+  int32_t k, k1, nl;     // steps; K of the first step (4 or 16); N of the last (4 or 16)
+  int32_t pad;
+  const int32_t* scale_slot;
+  int32_t* max_slot;
+};
+
+struct ChunkGroup {
+  ChunkUnit u[kChunkGroup];
+  uint32_t first[kChunkGroup + 1];   // unused entries hold the total tile count
+  int32_t n;
+  int32_t* flags;
+};
+
+// The launch's ChunkGroup is read in place from the kernel-argument segment
+// (constant address space, uniform: scalar loads), so dynamic unit and step
+// indices need no private copy of it.
+#define KARG __attribute__((address_space(4)))
+typedef const KARG ChunkGroup* GroupRef;
+typedef const KARG ChunkUnit& UnitRef;
+
+// Launch shapes: SP spectators per tile, at most KM rows per chunk, NW waves
+// per workgroup, PS = persistent workgroups.
+//  schedule 0: one workgroup per tile, two or more resident per CU (float:
+//    64 KiB slices of 64-byte row runs; tiles spread over the XCDs in
+//    contiguous runs so both halves of a 128-byte line go through one L2);
+//  schedule 1: one persistent workgroup per CU over a contiguous tile range
+//    (float: 128 KiB slices of 128-byte row runs), the next slice loaded into
+//    registers while the current one is contracted.
+template <typename T, int SCHED>
+struct Cfg;
+template <>
+struct Cfg<float, 0> {
+  static constexpr int SP = 16, KM = 4, NW = 8;
+  static constexpr bool PS = false;
+};
+template <>
+struct Cfg<float, 1> {
+  static constexpr int SP = 32, KM = 4, NW = 16;
+  static constexpr bool PS = true;
+};
+template <>
+struct Cfg<double, 0> {
+  static constexpr int SP = 16, KM = 3, NW = 8;
+  static constexpr bool PS = false;
+};
+template <>
+struct Cfg<double, 1> {
+  static constexpr int SP = 16, KM = 3, NW = 8;
+  static constexpr bool PS = true;
+};
+
+// XOR of the base-4 digits of x (x < 2^16), two bits.
+__device__ inline int dx4(int x) {
+  x ^= x >> 8;
+  x ^= x >> 4;
+  x ^= x >> 2;
+  return x & 3;
+}
+
+// LDS placement.  Slice row r, spectator s = 16 h + c; with the swizzle digit
+// d = (r & 3) ^ dx4(r >> 2) = 2 d1 + d0,
+//     word = (r & ~3) * SP + (G(d) ^ 16 h) + c,
+// G(d) = 16 d (SP = 16) or 80 d0 + 32 d1 (SP = 32).  Word bit 4 (the 16-bank
+// half of a 32-bank cycle) carries d0, bits 4-5 (the 16-bank quarter of 64
+// banks) carry (d0, d1): MFMA operand reads and result writes, whose four
+// lane groups address rows that differ in one base-4 digit (the low bit of
+// that digit between the two groups of a half-wave), never share a bank.  G
+// is XOR-linear in d.
+template <int SP>
+__device__ inline int gsw(int d) {
+  return SP == 16 ? (d << 4) : (((d & 1) ? 80 : 0) | ((d & 2) << 4));
+}
+template <int SP>
+__device__ inline int word_of(int row, int s) {
+  const int d = (row & 3) ^ dx4(row >> 2);
+  return (row & ~3) * SP + (gsw<SP>(d) ^ (s & 16)) + (s & 15);
+}
+
+// In the step loops a row is base + koff with base (tile) and koff = kidx *
+// 4^(jsh/2) (kidx = K or N index < 16) in disjoint base-4 digits, so
+//     word = TB + H(kidx) + (LX ^ G(X(kidx)))
+// with TB = (base & ~3) * SP + c and LX = G(dx of base) ^ 16 h per tile,
+// H(kidx) = (jsh ? kidx : kidx & ~3) << (jsh + log2 SP) and X(kidx) =
+// (kidx & 3) ^ (kidx >> 2).  The lane-dependent parts of kidx go into
+// per-lane bases, the rest into uniform terms and XOR immediates.
+template <int SP>
+__device__ inline void tile_of(int grp, int h, int jsh, int c, int& tb, int& lx) {
+  const int base = ((grp >> jsh) << (jsh + 4)) + (grp & ((1 << jsh) - 1));
+  tb = (base & ~3) * SP + c;
+  lx = gsw<SP>((base & 3) ^ dx4(base >> 2)) ^ (h << 4);
+}
+
+template <typename T>
+__device__ inline T scale(T x, int32_t shift) {
+  return shift ? static_cast<T>(ldexp(x, -shift)) : x;
+}
+
+// Site operands of one step, from the padded matrices staged in LDS.
+//   f32/f64: lane (c, g) holds A[c][g] = S[4kk + g][c] for kk = 0..3
+//   bf16x3:  lane (c, g) holds S[2t + (g & 1)][c], t = 0..7 (high parts for
+//            g < 2 and low parts for g >= 2 in the first product; high parts
+//            and zeros in the second)
+template <typename T, int MODE>
+struct SiteOps {
+  T a[4];
+  bf16x8 a0, a1;
+};
+
+template <typename T, int MODE>
+__device__ inline SiteOps<T, MODE> site_ops(const T* sS, const uint16_t* sH, const uint16_t* sL,
+                                            int c, int gg) {
+  SiteOps<T, MODE> o;
+  if constexpr (MODE == M_BF16X3) {
+    const uint16_t zero = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = (2 * t + (gg & 1)) * 16 + c;
+      const uint16_t hb = sH[e], lb = sL[e];
+      o.a0[t] = __builtin_bit_cast(__bf16, gg < 2 ? hb : lb);
+      o.a1[t] = __builtin_bit_cast(__bf16, gg < 2 ? hb : zero);
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) o.a[kk] = sS[(4 * kk + gg) * 16 + c];
+  }
+  return o;
+}
+
+// One step (base-4 shift JSH of the K/N index in the row, compile time) on
+// every (prefix, m) group of the slice; wave w takes groups w, w + NW, ...
+// and both 16-spectator halves of each.  Lane (c, g):
+//   reads f32/f64: kidx = 4kk + g;  bf16: kidx = 2t + (g & 1)
+//   writes f32/bf16: kidx = 4g + r;  f64: kidx = g + 4r
+// A word offset is TB + H(kidx) + (LX ^ G(X(kidx))) (see tile_of); with JSH
+// fixed, H splits into a per-lane term and compile-time offsets, and the XOR
+// term takes one of four per-group values.
+// TOP: first step of a top-edge chunk (only kidx < 4 carries data).
+template <typename T, int MODE, int SP, int NW, int JSH, bool TOP>
+__device__ inline void step_groups(T* lds, int M1, const SiteOps<T, MODE>& o, int c, int gg,
+                                   int w) {
+  using V4 = typename std::conditional<MODE == M_F64, f64x4, f32x4>::type;
+  constexpr int LS = SP == 16 ? 4 : 5, HS = SP / 16, J = JSH + LS;
+  // per-lane parts of H
+  const int hb_r = (MODE == M_BF16X3) ? (JSH ? (gg & 1) << J : 0) : (JSH ? gg << J : 0);
+  const int hb_w = (MODE == M_F64) ? (JSH ? gg << J : 0) : (JSH ? gg << (J + 2) : gg << (LS + 2));
+  const int gx_r = (MODE == M_BF16X3) ? gsw<SP>(gg & 1) : gsw<SP>(gg);
+  const int gx_w = gsw<SP>(gg);
+  for (int grp = w; grp < M1; grp += NW) {
+    const int base = ((grp >> JSH) << (JSH + 4)) + (grp & ((1 << JSH) - 1));
+    const int tb = (base & ~3) * SP + c;
+    const int lb = gsw<SP>((base & 3) ^ dx4(base >> 2));
+#pragma unroll
+    for (int h = 0; h < HS; ++h) {
+      const int lx = lb ^ (h << 4);
+      int xr[4], xw[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        xr[q] = tb + hb_r + ((lx ^ gx_r) ^ gsw<SP>(q));
+        xw[q] = tb + hb_w + ((lx ^ gx_w) ^ gsw<SP>(q));
+      }
+      V4 acc;
+      if constexpr (MODE == M_BF16X3) {
+        const __bf16 zero = __builtin_bit_cast(__bf16, static_cast<uint16_t>(0));
+        bf16x8 b0, b1;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          if (TOP && t >= 2) {
+            b0[t] = zero;
+            b1[t] = zero;
+            continue;
+          }
+          const int ht = JSH ? ((2 * t) << J) : ((t >> 1) << (LS + 2));
+          const float x = lds[xr[(2 * (t & 1)) ^ (t >> 1)] + ht];
+          const __bf16 hi = static_cast<__bf16>(x);
+          b0[t] = hi;
+          b1[t] = gg < 2 ? static_cast<__bf16>(x - static_cast<float>(hi)) : zero;
+        }
+        acc = f32x4{0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a0, b0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a1, b1, acc, 0, 0, 0);
+      } else {
+        constexpr int KK = TOP ? 1 : 4;
+        T b[KK];
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+          const int ht = JSH ? (kk << (J + 2)) : (kk << (LS + 2));
+          b[kk] = lds[xr[kk] + ht];
+        }
+        acc = V4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+          if constexpr (MODE == M_F64)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[kk], b[kk], acc, 0, 0, 0);
+          else
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[kk], b[kk], acc, 0, 0, 0);
+        }
+      }
+      // register r of lane (c, g) holds D[n][c], n = 4g + r (f32 and bf16
+      // results) or n = g + 4r (f64)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ht = (MODE == M_F64) ? (JSH ? (r << (J + 2)) : (r << (LS + 2))) : (JSH ? (r << J) : 0);
+        lds[xw[r] + ht] = acc[r];
+      }
+    }
+  }
+}
+
+// Geometry of one tile (SP spectators of one unit).
+struct Tile {
+  int64_t p0, q0;
+  int ui;
+  int rows_in, rows_out, qn;
+  int qrun;   // no padding bytes: they would become a private array
+  int pad;
+};
+
+// Unit of group tile t.
+__device__ inline int unit_index(GroupRef g, uint32_t t) {
+  return static_cast<int>(t >= g->first[1]) + static_cast<int>(t >= g->first[2]) +
+         static_cast<int>(t >= g->first[3]);
+}
+
+template <int SP>
+__device__ inline Tile tile_at(GroupRef g, uint32_t t) {
+  Tile x;
+  const int ui = unit_index(g, t);
+  UnitRef d = g->u[ui];
+  const int64_t tile = t - g->first[ui];
+  x.ui = ui;
+  const int M1 = 1 << (2 * (d.k - 1));
+  x.rows_in = d.k1 * M1;
+  x.rows_out = d.nl * M1;
+  x.qrun = d.post >= SP ? 1 : 0;
+  x.qn = x.qrun ? SP : static_cast<int>(d.post);
+  if (x.qrun) {
+    const int64_t tq = d.post / SP;
+    x.p0 = tile / tq;
+    x.q0 = (tile - x.p0 * tq) * SP;
+  } else {
+    x.p0 = tile * (SP / x.qn);
+    x.q0 = 0;
+  }
+  x.pad = 0;
+  return x;
+}
+
+// Global <-> LDS traffic of a slice of `rows` rows.  Vector (4 entries)
+// index f = it * NTH + tid.
+//  * Row runs (q-run, or whole suffixes of 4..SP/2 entries): f -> (row, 4
+//    spectators s..s+3), 4 consecutive entries in global memory and in LDS.
+//    Rows are visited in the order 0, 2, 1, 3 within each group of four, so
+//    the two rows of a 16-lane LDS cycle sit in different bank halves.
+//  * Whole suffixes of 1 entry (the tile is SP consecutive p): f -> (4 rows,
+//    4 spectators); four 4-row loads transposed in registers into four rows
+//    of 4 spectators.
+template <int SP>
+__device__ inline void run_pos(int f, int& row, int& s) {
+  constexpr int PR = SP / 4;   // vectors per row
+  const int r = f / PR;
+  row = (r & ~3) | ((r & 1) << 1) | ((r >> 1) & 1);
+  s = 4 * (f % PR);
+}
+template <int SP>
+__device__ inline void blk_pos(int f, int& row4, int& s) {
+  constexpr int PB = SP / 4;   // 4-spectator blocks per 4-row group
+  const int r = f / PB;
+  row4 = 4 * ((r & ~3) | ((r & 1) << 1) | ((r >> 1) & 1));
+  s = 4 * (f % PB);
+}
+
+// Global element offset (from the tile's base) of (row, spectator s) on the
+// row-run path.
+__device__ inline int64_t run_off(const Tile& x, int64_t post, int rows, int row, int s) {
+  if (x.qrun) return static_cast<int64_t>(row) * post + s;
+  const int pl = s / x.qn, q = s - pl * x.qn;   // whole suffixes: [p_local][row][q]
+  return (static_cast<int64_t>(pl) * rows + row) * x.qn + q;
+}
+
+template <int IT>
+struct Regs {
+  static constexpr int N = IT < 4 ? 4 : IT;
+  static constexpr int NB = (IT + 3) / 4;   // 4x4 blocks per thread
+};
+
+// Issue the global loads of a tile's input slice into v (no wait).
+template <typename T, typename V4, int SP, int NTH, int IT>
+__device__ inline void slice_load(UnitRef d, const Tile& x, V4* v) {
+  const int tid = threadIdx.x;
+  const T* src = static_cast<const T*>(d.in) + x.p0 * x.rows_in * d.post + x.q0;
+  if (x.qn >= 4) {
+    const int total = x.rows_in * SP / 4;
+#pragma unroll
+    for (int it = 0; it < Regs<IT>::N; ++it) {   // slots past IT are never in range
+      const int f = it * NTH + tid;
+      if (f < total) {
+        int row, s;
+        run_pos<SP>(f, row, s);
+        v[it] = *reinterpret_cast<const V4*>(src + run_off(x, d.post, x.rows_in, row, s));
+      }
+    }
+  } else {
+    const int total = x.rows_in * SP / 16;
+#pragma unroll
+    for (int it = 0; it < Regs<IT>::NB; ++it) {
+      const int f = it * NTH + tid;
+      if (f < total) {
+        int row4, s;
+        blk_pos<SP>(f, row4, s);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          v[4 * it + i] =
+              *reinterpret_cast<const V4*>(src + static_cast<int64_t>(s + i) * x.rows_in + row4);
+      }
+    }
+  }
+}
+
+// Scale the loaded slice by 2^-shift and write it to its LDS rows.
+template <typename T, typename V4, int SP, int NTH, int IT>
+__device__ inline void slice_to_lds(UnitRef d, const Tile& x, const V4* v, T* lds) {
+  const int tid = threadIdx.x;
+  const int32_t shift = shift_of(d.scale_slot);
+  if (x.qn >= 4) {
+    const int total = x.rows_in * SP / 4;
+#pragma unroll
+    for (int it = 0; it < Regs<IT>::N; ++it) {
+      const int f = it * NTH + tid;
+      if (f < total) {
+        int row, s;
+        run_pos<SP>(f, row, s);
+        V4 y = v[it];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[i] = scale(y[i], shift);
+        *reinterpret_cast<V4*>(&lds[word_of<SP>(row, s)]) = y;
+      }
+    }
+  } else {
+    const int total = x.rows_in * SP / 16;
+#pragma unroll
+    for (int it = 0; it < Regs<IT>::NB; ++it) {
+      const int f = it * NTH + tid;
+      if (f < total) {
+        int row4, s;
+        blk_pos<SP>(f, row4, s);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          V4 y;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) y[i] = scale(v[4 * it + i][u], shift);
+          *reinterpret_cast<V4*>(&lds[word_of<SP>(row4 + u, s)]) = y;
+        }
+      }
+    }
+  }
+}
+
+// Stage the chunk's padded site matrices (and their bf16 parts) in LDS.
+template <typename T, int MODE, int NTH>
+__device__ inline void stage_sites(UnitRef d, T* sS, uint16_t* sH, uint16_t* sL) {
+  for (int e = threadIdx.x; e < d.k * 256; e += NTH) {
+    const int j = e >> 8, k = (e >> 4) & 15, n = e & 15;
+    const bool top = j == 0 && d.k1 == 4, bottom = j == d.k - 1 && d.nl == 4;
+    const bool zero = (top && k >= 4) || (bottom && (n & 3));
+    const int src = bottom ? k * 4 + (n >> 2) : k * 16 + n;
+    if constexpr (MODE == M_BF16X3) {
+      sH[e] = zero ? uint16_t(0) : d.hi[j][src];
+      sL[e] = zero ? uint16_t(0) : d.lo[j][src];
+    } else {
+      sS[e] = zero ? T(0) : static_cast<const T*>(d.S[j])[src];
+    }
+  }
+}
+
+// The chunk's k steps on the slice in LDS, in place (ends with a barrier).
+template <typename T, int MODE, int SP, int NW>
+__device__ inline void slice_steps(UnitRef d, T* lds, const T* sS, const uint16_t* sH,
+                                   const uint16_t* sL) {
+  const int lane = threadIdx.x & 63, c = lane & 15, gg = lane >> 4, w = threadIdx.x >> 6;
+  const int k = d.k, M1 = 1 << (2 * (k - 1));
+  for (int j = 0; j < k; ++j) {
+    const int jsh = 2 * (k - 1 - j);
+    const SiteOps<T, MODE> o = site_ops<T, MODE>(sS + 256 * j, sH + 256 * j, sL + 256 * j, c, gg);
+    const bool top = j == 0 && d.k1 == 4;
+    switch (jsh) {
+      case 0: step_groups<T, MODE, SP, NW, 0, false>(lds, M1, o, c, gg, w); break;
+      case 2:
+        if (top) step_groups<T, MODE, SP, NW, 2, true>(lds, M1, o, c, gg, w);
+        else step_groups<T, MODE, SP, NW, 2, false>(lds, M1, o, c, gg, w);
+        break;
+      case 4:
+        if (top) step_groups<T, MODE, SP, NW, 4, true>(lds, M1, o, c, gg, w);
+        else step_groups<T, MODE, SP, NW, 4, false>(lds, M1, o, c, gg, w);
+        break;
+      default:
+        if (top) step_groups<T, MODE, SP, NW, 6, true>(lds, M1, o, c, gg, w);
+        else step_groups<T, MODE, SP, NW, 6, false>(lds, M1, o, c, gg, w);
+        break;
+    }
+    __syncthreads();
+  }
+}
+
+// Store the rows of the last step's real outputs; track max |x| and
+// non-finite values.
+template <typename T, typename V4, int SP, int NTH, int IT>
+__device__ inline void slice_store(UnitRef d, const Tile& x, const T* lds, T& mx, int& bad) {
+  const int tid = threadIdx.x;
+  const int lsh = d.nl == 4 ? 2 : 0;
+  T* dst = static_cast<T*>(d.out) + x.p0 * x.rows_out * d.post + x.q0;
+  if (x.qn >= 4) {
+    const int total = x.rows_out * SP / 4;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int f = it * NTH + tid;
+      if (f < total) {
+        int row, s;
+        run_pos<SP>(f, row, s);
+        const V4 v = *reinterpret_cast<const V4*>(&lds[word_of<SP>(row << lsh, s)]);
+        *reinterpret_cast<V4*>(dst + run_off(x, d.post, x.rows_out, row, s)) = v;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) track(v[i], mx, bad);
+      }
+    }
+  } else {
+    const int total = x.rows_out * SP / 16;
+#pragma unroll
+    for (int it = 0; it < Regs<IT>::NB; ++it) {
+      const int f = it * NTH + tid;
+      if (f < total) {
+        int row4, s;
+        blk_pos<SP>(f, row4, s);
+        V4 r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          r[u] = *reinterpret_cast<const V4*>(&lds[word_of<SP>((row4 + u) << lsh, s)]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const V4 v = {r[0][i], r[1][i], r[2][i], r[3][i]};
+          *reinterpret_cast<V4*>(dst + static_cast<int64_t>(s + i) * x.rows_out + row4) = v;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) track(v[q], mx, bad);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int MODE, int SCHED>
+__global__ __launch_bounds__((64 * Cfg<T, SCHED>::NW)) __attribute__((amdgpu_waves_per_eu(4))) void
+absorb_chunk(ChunkGroup arg) {
+  (void)arg;   // read in place below
+  using C = Cfg<T, SCHED>;
+  using V4 = typename std::conditional<MODE == M_F64, f64x4, f32x4>::type;
+  constexpr int SP = C::SP, NW = C::NW, NTH = 64 * NW, KM = C::KM;
+  constexpr int RMAX = 16 << (2 * (KM - 1));
+  constexpr int IT = RMAX * SP / (NTH * 4);
+  __shared__ __attribute__((aligned(32))) T lds[RMAX * SP];
+  __shared__ __attribute__((aligned(16))) T sS[MODE == M_BF16X3 ? 1 : KM * 256];
+  __shared__ __attribute__((aligned(16))) uint16_t sH[MODE == M_BF16X3 ? KM * 256 : 1];
+  __shared__ __attribute__((aligned(16))) uint16_t sL[MODE == M_BF16X3 ? KM * 256 : 1];
+  const GroupRef g = (GroupRef)__builtin_amdgcn_kernarg_segment_ptr();
+  const uint32_t total = g->first[kChunkGroup];
+  V4 v[Regs<IT>::N];
+
+  if constexpr (!C::PS) {
+    // one tile; consecutive tiles on one XCD (workgroup b runs on XCD b % 8)
+    const uint32_t nb = gridDim.x;
+    const uint32_t t = (nb % 8 == 0) ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
+    const Tile x = tile_at<SP>(g, t);
+    UnitRef d = g->u[x.ui];
+    slice_load<T, V4, SP, NTH, IT>(d, x, v);   // in flight while the sites are staged
+    stage_sites<T, MODE, NTH>(d, sS, sH, sL);
+    slice_to_lds<T, V4, SP, NTH, IT>(d, x, v, lds);
+    __syncthreads();
+    slice_steps<T, MODE, SP, NW>(d, lds, sS, sH, sL);
+    T mx = 0;
+    int bad = 0;
+    slice_store<T, V4, SP, NTH, IT>(d, x, lds, mx, bad);
+    if (d.max_slot) reduce_and_publish<T, NW>(mx, bad, d.max_slot, g->flags);
+  } else {
+    const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
+    const uint32_t t0 = blockIdx.x * per;
+    const uint32_t t1 = min(total, t0 + per);
+    if (t0 >= t1) return;
+    Tile cur = tile_at<SP>(g, t0);
+    int staged = -1;
+    T mx = 0;
+    int bad = 0;
+    for (uint32_t t = t0; t < t1; ++t) {
+      UnitRef d = g->u[cur.ui];
+      if (staged != cur.ui) {
+        stage_sites<T, MODE, NTH>(d, sS, sH, sL);
+        staged = cur.ui;
+      }
+      if (t == t0) slice_load<T, V4, SP, NTH, IT>(d, cur, v);
+      slice_to_lds<T, V4, SP, NTH, IT>(d, cur, v, lds);
+      __syncthreads();
+      const bool more = t + 1 < t1;
+      Tile nxt = cur;
+      if (more) {
+        nxt = tile_at<SP>(g, t + 1);
+        slice_load<T, V4, SP, NTH, IT>(g->u[nxt.ui], nxt, v);
+      }
+      slice_steps<T, MODE, SP, NW>(d, lds, sS, sH, sL);
+      slice_store<T, V4, SP, NTH, IT>(d, cur, lds, mx, bad);
+      if (!more || nxt.ui != cur.ui) {
+        if (d.max_slot) reduce_and_publish<T, NW>(mx, bad, d.max_slot, g->flags);
+        mx = 0;
+        bad = 0;
+      }
+      __syncthreads();
+      cur = nxt;
+    }
+  }
+}
+
+// Launch schedule of the column-chunk kernels (see Cfg).
+int32_t g_chunk_sched = 0;
+
+// Resident workgroups per CU of one instantiation, times the CU count.
+template <typename T, int MODE, int SCHED>
+int32_t chunk_grid_cap() {
+  static int32_t cap = 0;
+  if (cap == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, absorb_chunk<T, MODE, SCHED>,
+                                                     64 * Cfg<T, SCHED>::NW, 0) != hipSuccess)
+      return 256;
+    cap = std::max(1, cus * std::max(1, per_cu));
+  }
+  return cap;
+}
+
+template <typename T, int MODE, int SCHED>
+hipError_t go_chunk(const ChunkArgs* a, int32_t n, const StagedArrays& st, DevState* state,
+                    hipStream_t stream) {
+  using C = Cfg<T, SCHED>;
+  ChunkGroup g;
+  std::memset(&g, 0, sizeof(g));
+  g.n = n;
+  g.flags = &state->flags;
+  uint64_t total = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    const ChunkArgs& x = a[u];
+    if (x.k < 2 || x.k > C::KM) return hipErrorInvalidValue;
+    ChunkUnit& c = g.u[u];
+    c.in = x.in;
+    c.out = x.out;
+    for (int j = 0; j < x.k; ++j) {
+      c.S[j] = (MODE == M_F64) ? static_cast<const void*>(st.s64 + x.s_off[j])
+                               : static_cast<const void*>(st.s32 + x.s_off[j]);
+      c.hi[j] = st.shi + x.s_off[j];
+      c.lo[j] = st.slo + x.s_off[j];
+    }
+    c.pre = x.pre;
+    c.post = x.post;
+    c.k = x.k;
+    c.k1 = x.k1;
+    c.nl = x.nl;
+    c.scale_slot = x.scale_slot;
+    c.max_slot = x.max_slot;
+    g.first[u] = static_cast<uint32_t>(total);
+    total += static_cast<uint64_t>(x.pre * x.post / C::SP);
+    if (total > static_cast<uint64_t>(INT_MAX)) return hipErrorInvalidValue;
+  }
+  for (int32_t u = n; u <= kChunkGroup; ++u) g.first[u] = static_cast<uint32_t>(total);
+  const uint32_t grid = static_cast<uint32_t>(
+      C::PS ? std::min<uint64_t>(total, chunk_grid_cap<T, MODE, SCHED>()) : total);
+  hipLaunchKernelGGL((absorb_chunk<T, MODE, SCHED>), dim3(grid), dim3(64 * C::NW), 0, stream, g);
+  return hipGetLastError();
+}
+
+template <int SCHED>
+hipError_t go_chunk_mode(const ChunkArgs* a, int32_t n, const StagedArrays& st, DevState* state,
+                         hipStream_t stream, const char** kname) {
+  if (a[0].type == EL_F64) {
+    *kname = "absorb_chunk_f64";
+    return go_chunk<double, M_F64, SCHED>(a, n, st, state, stream);
+  }
+  if (a[0].arith == AR_BF16X3) {
+    *kname = "absorb_chunk_bf16x3";
+    return go_chunk<float, M_BF16X3, SCHED>(a, n, st, state, stream);
+  }
+  *kname = "absorb_chunk_f32";
+  return go_chunk<float, M_F32, SCHED>(a, n, st, state, stream);
+}
+
+}  // namespace
+
+int32_t chunk_max_steps(int32_t type) {
+  if (type == EL_F64) return g_chunk_sched ? Cfg<double, 1>::KM : Cfg<double, 0>::KM;
+  return g_chunk_sched ? Cfg<float, 1>::KM : Cfg<float, 0>::KM;
+}
+
+void set_chunk_persistent(int32_t on) { g_chunk_sched = on ? 1 : 0; }
+
+bool chunk_shape_ok(int32_t type, int64_t pre, int64_t post, int32_t k, int32_t k1, int32_t nl) {
+  const int64_t sp = type == EL_F64 ? (g_chunk_sched ? Cfg<double, 1>::SP : Cfg<double, 0>::SP)
+                                    : (g_chunk_sched ? Cfg<float, 1>::SP : Cfg<float, 0>::SP);
+  if (k < 2 || k > chunk_max_steps(type) || (k1 != 4 && k1 != 16) || (nl != 4 && nl != 16))
+    return false;
+  if (pre < 1 || post < 1) return false;
+  if (post >= sp) {
+    if (post % sp) return false;
+  } else {
+    // whole suffixes per tile: SP / post consecutive p; a suffix of 2 has no
+    // kernel path (not a shape of D = 4 networks)
+    if (sp % post || pre % (sp / post) || post == 2) return false;
+  }
+  return pre <= INT_MAX / post;
+}
+
+hipError_t launch_absorb_chunks(const ChunkArgs* a, int32_t n, const StagedArrays& st,
+                                DevState* state, hipStream_t stream, const char** kname) {
+  if (n < 1 || n > kChunkGroup) return hipErrorInvalidValue;
+  for (int32_t u = 0; u < n; ++u) {
+    if (a[u].type != a[0].type || a[u].arith != a[0].arith) return hipErrorInvalidValue;
+    if (!chunk_shape_ok(a[u].type, a[u].pre, a[u].post, a[u].k, a[u].k1, a[u].nl))
+      return hipErrorInvalidValue;
+  }
+  return g_chunk_sched ? go_chunk_mode<1>(a, n, st, state, stream, kname)
+                       : go_chunk_mode<0>(a, n, st, state, stream, kname);
+}
+
+}  // namespace tn

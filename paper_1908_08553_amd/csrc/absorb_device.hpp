@@ -73,10 +73,10 @@ __device__ inline float bf16_to_f(__bf16 b) {
   return __uint_as_float(static_cast<uint32_t>(__builtin_bit_cast(uint16_t, b)) << 16);
 }
 
-template <typename T>
+template <typename T, int NW = kWaves>
 __device__ inline void reduce_and_publish(T mx, int bad, int32_t* max_slot, int32_t* flags) {
-  __shared__ double sm[kWaves];
-  __shared__ int sb[kWaves];
+  __shared__ double sm[NW];
+  __shared__ int sb[NW];
   double m = static_cast<double>(mx);
   for (int off = 32; off > 0; off >>= 1) {
     m = fmax(m, __shfl_xor(m, off));
@@ -86,7 +86,7 @@ __device__ inline void reduce_and_publish(T mx, int bad, int32_t* max_slot, int3
   if ((threadIdx.x & 63) == 0) { sm[w] = m; sb[w] = bad; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int k = 1; k < kWaves; ++k) { m = fmax(m, sm[k]); bad |= sb[k]; }
+    for (int k = 1; k < NW; ++k) { m = fmax(m, sm[k]); bad |= sb[k]; }
     m = fmax(m, sm[0]);
     bad |= sb[0];
     const int32_t e = bad ? kExpBad : exp_of_d(m);

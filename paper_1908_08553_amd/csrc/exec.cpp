@@ -46,6 +46,32 @@ bool pair_ok(const Step& s1, const Step& s2) {
   return s1.pre * (s2.post / 64) <= static_cast<int64_t>(INT32_MAX);
 }
 
+// Steps k0 .. k0+len-1 are consecutive rows of one column of one sweep that
+// absorb_chunk can run on one slice: first K in {4, 16}, inner K = N = 16 with
+// every leg between consecutive rows of dimension 4 (each row adds a
+// dimension-4 leg to the prefix and takes one from the suffix), last N in
+// {4, 16}, rescale only after the last row, one element type throughout.
+bool chunk_ok(const Plan& p, const Layout& L, int32_t k0, int32_t len) {
+  if (k0 < 1 || k0 + len > static_cast<int32_t>(p.steps.size())) return false;
+  const Step& a = p.steps[k0];
+  for (int32_t j = 0; j < len; ++j) {
+    const Step& s = p.steps[k0 + j];
+    if (s.kind != STEP_ABSORB || s.unit != a.unit || s.col != a.col) return false;
+    if (j + 1 < len && s.rescale >= 0) return false;
+    if (j > 0 && s.scale_in >= 0) return false;
+    if (j == 0 ? (s.K != 4 && s.K != 16) : s.K != 16) return false;
+    if (j + 1 == len ? (s.N != 4 && s.N != 16) : s.N != 16) return false;
+    if (L.out_type[k0 + j] != L.out_type[k0 - 1]) return false;
+    if (j + 1 < len) {
+      const Step& nx = p.steps[k0 + j + 1];
+      if (nx.pre != 4 * s.pre || s.post != 4 * nx.post) return false;
+    }
+  }
+  const Step& z = p.steps[k0 + len - 1];
+  return chunk_shape_ok(L.out_type[k0], a.pre, z.post, len, static_cast<int32_t>(a.K),
+                        static_cast<int32_t>(z.N));
+}
+
 struct KStat { int64_t launches = 0; double ms = 0, bytes = 0, flops = 0; };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
@@ -357,18 +383,31 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
   };
   // Per unit, the absorption steps in order, each either alone or fused with
   // the next one (first step index of each action; pair flag).
-  struct Action { int32_t k; bool pair; };
+  // Per unit, the absorption steps in order: alone, fused with the next one
+  // (pair), or the first of a column chunk of `len` steps.
+  enum { ACT_ONE = 0, ACT_PAIR = 1, ACT_CHUNK = 2 };
+  struct Action { int32_t k, kind, len; };
   std::vector<std::vector<Action>> acts(nu);
   size_t max_acts = 0;
+  const int32_t fuse = absorb_policy() == 0 ? fuse_steps() : 0;
   for (size_t u = 0; u < nu; ++u) {
     const Unit& U = p.units[u];
-    for (int32_t t = 1; t < U.n_steps; ++t) {
-      const int32_t k = U.first_step + t;
-      const bool pair = t + 1 < U.n_steps && fuse_steps() && absorb_policy() == 0 &&
-                        pair_ok(p.steps[k], p.steps[k + 1]) &&
+    const int32_t end = U.first_step + U.n_steps;
+    for (int32_t k = U.first_step + 1; k < end;) {
+      Action a{k, ACT_ONE, 1};
+      const bool pair = k + 1 < end && pair_ok(p.steps[k], p.steps[k + 1]) &&
                         L.out_type[k - 1] == L.out_type[k] && L.out_type[k] == L.out_type[k + 1];
-      acts[u].push_back({k, pair});
-      if (pair) ++t;
+      if (fuse == 2) {
+        // chunks of 3 or more rows; two rows go to the pair kernel where it
+        // applies (a 2-row slice is too small to amortise a chunk workgroup)
+        for (int32_t len = std::min(chunk_max_steps(L.out_type[k - 1]), end - k); len >= 2; --len)
+          if (chunk_ok(p, L, k, len)) { a = {k, ACT_CHUNK, len}; break; }
+        if (a.kind == ACT_CHUNK && a.len == 2 && pair) a = {k, ACT_PAIR, 2};
+      } else if (fuse == 1 && pair) {
+        a = {k, ACT_PAIR, 2};
+      }
+      acts[u].push_back(a);
+      k += a.len;
     }
     max_acts = std::max(max_acts, acts[u].size());
   }
@@ -376,13 +415,38 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
     AbsorbArgs group[4];
     const Step* gsteps[4];
     PairArgs pairs[4];
-    double pair_bytes = 0.0, pair_flops = 0.0;
-    int32_t n = 0, np = 0;
+    ChunkArgs chunks[4];
+    double pair_bytes = 0.0, pair_flops = 0.0, chunk_bytes = 0.0, chunk_flops = 0.0;
+    int32_t n = 0, np = 0, nc = 0;
     for (size_t u = 0; u < nu; ++u) {
       if (t >= acts[u].size()) continue;
       const Action& ac = acts[u][t];
       const AbsorbArgs a = args_of(u, ac.k);
-      if (ac.pair) {
+      if (ac.kind == ACT_CHUNK) {
+        const Step& s1 = p.steps[ac.k];
+        const Step& sl = p.steps[ac.k + ac.len - 1];
+        ChunkArgs& x = chunks[nc++];
+        x.in = a.in;
+        x.out = a.out;
+        x.type = a.in_type;
+        x.arith = arith;
+        x.pre = s1.pre;
+        x.post = sl.post;
+        x.k = ac.len;
+        x.k1 = static_cast<int32_t>(s1.K);
+        x.nl = static_cast<int32_t>(sl.N);
+        for (int32_t j = 0; j < kChunkMax; ++j) x.s_off[j] = j < ac.len ? L.s_off[ac.k + j] : 0;
+        x.scale_slot = a.scale_slot;
+        x.max_slot = sl.rescale >= 0 ? slot_exp + sl.rescale : nullptr;
+        const double eb = elem_bytes(a.in_type);
+        chunk_bytes += static_cast<double>(s1.pre * s1.K * s1.post) * eb +
+                       static_cast<double>(sl.out) * eb;
+        for (int32_t j = 0; j < ac.len; ++j) {
+          const Step& sj = p.steps[ac.k + j];
+          chunk_bytes += static_cast<double>(sj.K * sj.N) * eb;
+          chunk_flops += static_cast<double>(sj.flops);
+        }
+      } else if (ac.kind == ACT_PAIR) {
         const Step& s1 = p.steps[ac.k];
         const Step& s2 = p.steps[ac.k + 1];
         PairArgs& x = pairs[np++];
@@ -406,6 +470,12 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
         ++n;
       }
       cur[u] = 1 - cur[u];
+    }
+    if (nc > 0) {
+      const char* cname = "";
+      timer.before();
+      TN_HIP(launch_absorb_chunks(chunks, nc, sa, state, stream, &cname));
+      timer.after(cname, chunk_bytes, chunk_flops);
     }
     const char* kname = "";
     if (np > 0) {

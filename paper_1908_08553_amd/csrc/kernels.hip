@@ -315,7 +315,7 @@ hipError_t launch_stage(const StageDesc* descs, int32_t n_steps, StagedArrays st
 
 namespace {
 int32_t g_absorb_policy = 0;
-int32_t g_fuse_steps = 1;
+int32_t g_fuse_steps = 2;
 }
 
 void set_absorb_policy(int32_t policy) { g_absorb_policy = policy; }

@@ -86,11 +86,33 @@ struct PairArgs {
 hipError_t launch_absorb_pairs(const PairArgs* a, int32_t n, const StagedArrays& st,
                                DevState* state, hipStream_t stream, const char** kname);
 
+// Up to kChunkMax consecutive rows of one column (see absorb_chunk.hip): the
+// first step has K = 4 or 16, inner steps K = N = 16 with D = 4 legs between
+// them, the last N = 4 or 16; the boundary slice stays in LDS for the chunk.
+constexpr int kChunkMax = 4;
+struct ChunkArgs {
+  const void* in;
+  void* out;
+  int32_t type;                // ElemType of in and out
+  int32_t arith;
+  int64_t pre, post;           // prefix of the first step, suffix of the last
+  int32_t k, k1, nl;           // steps; K of the first; N of the last
+  int64_t s_off[kChunkMax];
+  const int32_t* scale_slot;   // scales the first step's input (nullable)
+  int32_t* max_slot;           // measured after the last step (nullable)
+};
+int32_t chunk_max_steps(int32_t type);
+void set_chunk_persistent(int32_t on);
+bool chunk_shape_ok(int32_t type, int64_t pre, int64_t post, int32_t k, int32_t k1, int32_t nl);
+hipError_t launch_absorb_chunks(const ChunkArgs* a, int32_t n, const StagedArrays& st,
+                                DevState* state, hipStream_t stream, const char** kname);
+
 // Kernel policy: 0 = matrix-core kernels where the shape allows, 1 = vector-ALU
 // kernels only (absorption and ring products).
 void set_absorb_policy(int32_t policy);
 int32_t absorb_policy();
-// 1 = fuse eligible step pairs (absorb_pair), 0 = one launch per step.
+// 2 = column chunks (absorb_chunk), 1 = step pairs (absorb_pair), 0 = one
+// launch per step.
 void set_fuse_steps(int32_t on);
 int32_t fuse_steps();
 

@@ -17,7 +17,12 @@ def tn():
     assert torch.cuda.is_available()
     import paper_1908_08553_amd as tn
     tn.tn_set_option(tn.TN_OPT_KERNEL_IMPL, 0)
-    return tn
+    # single contractions here run one launch per step: the batch kernel's own
+    # per-step bodies in the same order of arithmetic, so alone == in the
+    # batch bitwise (fused column chunks sum in another order)
+    tn.tn_set_option(tn.TN_OPT_FUSE_STEPS, 0)
+    yield tn
+    tn.tn_set_option(tn.TN_OPT_FUSE_STEPS, 2)
 
 
 def build(tn, mix):
@@ -45,7 +50,6 @@ def test_batch_vs_oracle_and_single(tn, mix48, prec):
         tol = 1e-12 if prec == "f64" else 1e-5 * max(1.0, abs(want.log_abs))
         assert abs(got.log_abs - want.log_abs) <= tol, (i, mix[i][:3], got, want)
         single = tn.contract_grid(plans[i], sites[i], prec)
-        # same bodies, same order of arithmetic: alone == in the batch, bitwise
         assert (single.mantissa, single.exp2_sum) == (got.mantissa, got.exp2_sum), i
     b.close()
 

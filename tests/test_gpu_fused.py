@@ -1,11 +1,14 @@
-"""Fused absorption of two consecutive bulk steps (one pass over the boundary
-for rows i and i+1 of a column, D = 4 legs between them).
+"""Fused absorption: several consecutive rows of one column in one pass over
+the boundary (paper §4: the pairwise sequential contraction fixes the value,
+not the launch structure).
 
-The fused kernel performs the same products in the same order as the two
-single-step launches and keeps the intermediate in the boundary's own element
-type, so the results must be bitwise identical to TN_OPT_FUSE_STEPS = 0; the
-oracle then pins both (paper §4: the pairwise sequential contraction fixes the
-value, not the launch structure)."""
+* Pairs (TN_OPT_FUSE_STEPS = 1): the same products in the same order as two
+  single-step launches, the intermediate kept in the boundary's element type,
+  so the results are bitwise identical to TN_OPT_FUSE_STEPS = 0.
+* Column chunks (TN_OPT_FUSE_STEPS = 2, the default): up to 4 rows (3 in
+  FP64) on a slice held on chip, products in a different order; checked
+  against the FP64 oracle at the stated tolerances and against the
+  transfer-matrix value of the Ising network."""
 import numpy as np
 import pytest
 
@@ -22,9 +25,8 @@ def tn():
     assert torch.cuda.is_available()
     import paper_1908_08553_amd as tn
     tn.tn_set_option(tn.TN_OPT_KERNEL_IMPL, 0)
-    tn.tn_set_option(tn.TN_OPT_FUSE_STEPS, 1)
     yield tn
-    tn.tn_set_option(tn.TN_OPT_FUSE_STEPS, 1)
+    tn.tn_set_option(tn.TN_OPT_FUSE_STEPS, 2)
 
 
 def run(tn, sites, rows, cols, order, prec, fuse, hdim=None, vdim=None, qh=0, qw=0):
@@ -38,12 +40,22 @@ def run(tn, sites, rows, cols, order, prec, fuse, hdim=None, vdim=None, qh=0, qw
         names = {k["name"]: k["launches"] for k in tn.tn_profile_read()}
     finally:
         tn.tn_profile_enable(False)
-        tn.tn_set_option(tn.TN_OPT_FUSE_STEPS, 1)
+        tn.tn_set_option(tn.TN_OPT_FUSE_STEPS, 2)
     return res, names
 
 
 def pair_launches(names):
     return sum(v for k, v in names.items() if k.startswith("absorb_pair_"))
+
+
+def chunk_launches(names):
+    return sum(v for k, v in names.items() if k.startswith("absorb_chunk_"))
+
+
+def close(got, ref, prec):
+    assert got.status == 0 and got.sign == ref.sign == 1
+    tol = 1e-12 if prec == "f64" else 1e-5 * max(1.0, abs(ref.log_abs))
+    assert abs(got.log_abs - ref.log_abs) <= tol, (prec, got.log_abs, ref.log_abs)
 
 
 def same_bits(a, b):
@@ -92,11 +104,12 @@ def test_fused_mixed_bond_dims_vs_oracle(tn, mixed10, order, prec):
     s, h, v, ref = mixed10
     fused, nf = run(tn, s, 10, 10, order, prec, 1, hdim=h, vdim=v)
     plain, _ = run(tn, s, 10, 10, order, prec, 0, hdim=h, vdim=v)
+    chunked, nc = run(tn, s, 10, 10, order, prec, 2, hdim=h, vdim=v)
     assert pair_launches(nf) > 0, nf
+    assert chunk_launches(nc) > 0, nc
     same_bits(fused, plain)
-    assert fused.sign == ref.sign == 1
-    tol = 1e-12 if prec == "f64" else 1e-5 * abs(ref.log_abs)
-    assert abs(fused.log_abs - ref.log_abs) <= tol, (fused.log_abs, ref.log_abs)
+    close(fused, ref, prec)
+    close(chunked, ref, prec)
 
 
 def test_fused_ising_d4_13x13_f64(tn):
@@ -109,6 +122,51 @@ def test_fused_ising_d4_13x13_f64(tn):
                 r, c, K, val = line.split()
                 gold[(int(r), int(c), float(K))] = float(val)
     tm = 2 * gold[(13, 13, 0.44)]
-    got, names = run(tn, li.ising_d4(13, 13, 0.44), 13, 13, P.COLSWEEP, "f64", 1)
-    assert pair_launches(names) > 0
-    assert got.sign == 1 and abs(got.log_abs - tm) <= 1e-12 * tm
+    sites = li.ising_d4(13, 13, 0.44)
+    for fuse, count in ((1, pair_launches), (2, chunk_launches)):
+        got, names = run(tn, sites, 13, 13, P.COLSWEEP, "f64", fuse)
+        assert count(names) > 0, names
+        assert got.sign == 1 and abs(got.log_abs - tm) <= 1e-12 * tm, (fuse, got.log_abs, tm)
+
+
+@pytest.fixture(scope="module")
+def oracle12(uniform12):
+    return C.contract_grid(uniform12, 12, 12, P.QUADRANT, 0, 0)
+
+
+@pytest.mark.parametrize("order", [P.COLSWEEP, P.HEURISTIC])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "f64"])
+def test_chunks_12x12_d4_vs_oracle(tn, uniform12, oracle12, order, prec):
+    got, names = run(tn, uniform12, 12, 12, order, prec, 2)
+    print(f"  chunks {prec} order={order}: {got.log_abs!r} oracle {oracle12.log_abs!r}")
+    assert chunk_launches(names) > 0, names
+    close(got, oracle12, prec)
+
+
+@pytest.mark.parametrize("prec,per_column", [("f32", 3), ("bf16x3", 3), ("f64", 4)])
+def test_chunk_partition_of_the_sweep(tn, uniform12, prec, per_column):
+    # 12 rows: chunks of 4 rows (rows 0-3 with the top edge's K = 4, 4-7, 8-11
+    # with the bottom edge's N = 4), of 3 rows in FP64; the middle columns
+    # 1..10 only (column 0 has no suffix to shrink, the last column no right legs)
+    _, names = run(tn, uniform12, 12, 12, P.COLSWEEP, prec, 2)
+    assert chunk_launches(names) == 10 * per_column, names
+
+
+def test_chunk_quadrant_launches_are_grouped(tn, uniform12):
+    # 6x6 quadrants: columns 1..5 of each unit as a chunk of rows 0-3 and
+    # rows 4-5 fused, the four units' work in one launch each; rows 4-5 take
+    # the pair kernel where the suffix (4^j in column j) is a multiple of 64
+    # (j >= 3) and a 2-row chunk otherwise
+    _, names = run(tn, uniform12, 12, 12, P.QUADRANT, "f32", 2)
+    assert chunk_launches(names) == 5 + 2, names
+    assert pair_launches(names) == 3, names
+
+
+@pytest.mark.parametrize("rows,cols", [(6, 12), (12, 6), (9, 7), (5, 13)])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_chunks_thin_and_odd_lattices(tn, rows, cols, prec):
+    s = li.uniform(rows, cols, 4, 100 + rows * cols)
+    ref = C.contract_grid(s, rows, cols, P.QUADRANT, 0, 0)
+    for order in (P.COLSWEEP, P.HEURISTIC):
+        got, _ = run(tn, s, rows, cols, order, prec, 2)
+        close(got, ref, prec)
