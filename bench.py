@@ -1,7 +1,7 @@
 """Benchmark: exact 12x12 D=4 planar-lattice contraction on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-legs]
-                    [--no-batch] [--no-serve] [--calibrate]
+                    [--no-batch] [--no-serve] [--leg NAME ...] [--calibrate]
 
 One step = one full contraction through the C ABI -- site staging, every
 pairwise absorption with its per-column exact rescale, the quadrant ring
@@ -85,24 +85,57 @@ def run_leg(tn, torch, rows, cols, D, kind, seed, order, prec, steps, warmup, pr
             "log_abs": res.log_abs, "sign": res.sign, "kernels": ks}
 
 
-def roofline(ks, prec):
-    """Dominant kernel (most GPU time) of a profiled leg against its bound."""
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_12x12_D4.json")
+
+
+def measured_traffic(key):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) that
+    rocprofv3 recorded for `key` = "<workload>:<kernel>", or None when there is
+    no record or a listed kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)["kernels"].get(key)
+    except (OSError, ValueError, KeyError):
+        return None
+    if not rec:
+        return None
+    for path, digest in rec["sources_sha256"].items():
+        try:
+            with open(os.path.join(ROOT, path), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
+        except OSError:
+            return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def roofline(ks, prec, workload=None):
+    """Dominant kernel (most GPU time) of a profiled leg against its bound;
+    `traffic` from the committed rocprofv3 counters of that kernel on
+    `workload` ("quadrant" / "sweep" of the 12x12 D=4 uniform network)."""
     if not ks:
         return None
     dom = max(ks, key=lambda k: k["total_ms"])
     avg_ms = dom["total_ms"] / dom["launches"]
     share = dom["total_ms"] / sum(k["total_ms"] for k in ks)
-    if dom["name"].startswith("ring_"):
+    traffic = measured_traffic(f"{workload}:{dom['name']}") if workload else None
+    alg_bytes = dom["bytes"] / dom["launches"]
+    extra = {"launches": dom["launches"], "avg_ms": avg_ms, "share_of_gpu_time": share,
+             "algorithmic_bytes_per_launch": alg_bytes}
+    # bound: the kernel's algorithmic intensity against the ridge point of its
+    # arithmetic (peak flops / 8 TB/s)
+    dt = "f64" if dom["name"].endswith("f64") else prec
+    peak = PEAK_TFLOPS[dt]
+    intensity = dom["flops"] / dom["bytes"] if dom["bytes"] else float("inf")
+    extra["flops_per_byte"] = intensity
+    if intensity >= peak * 1e12 / (PEAK_HBM_GBS * 1e9):
         ach = dom["flops"] / dom["launches"] / (avg_ms * 1e-3) / 1e12
-        dt = "f64" if dom["name"].endswith("f64") else prec
-        peak = PEAK_TFLOPS[dt]
         return {"kernel": dom["name"], "bound": "mfma", "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
-                "launches": dom["launches"], "avg_ms": avg_ms, "share_of_gpu_time": share}
-    ach = dom["bytes"] / dom["launches"] / (avg_ms * 1e-3) / 1e9
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic, **extra}
+    ach = alg_bytes / (avg_ms * 1e-3) / 1e9
     return {"kernel": dom["name"], "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None,
-            "launches": dom["launches"], "avg_ms": avg_ms, "share_of_gpu_time": share}
+            "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": traffic, **extra}
 
 
 def copy_calibration(torch, mib=256, reps=20):
@@ -257,6 +290,8 @@ def main():
     ap.add_argument("--no-legs", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--leg", action="append", default=None,
+                    help="run only the named leg(s) besides the headline (repeatable)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also time a plain 256 MiB device copy")
     args = ap.parse_args()
@@ -283,16 +318,20 @@ def main():
                 ("ising12_d4_quad_f32", 12, 12, 4, "ising", 1, "f32"),
                 ("sweep10_f64_normal", 10, 10, 4, "normal", 0, "f64"),
                 ("quad10_f64_normal", 10, 10, 4, "normal", 1, "f64")]
+        if args.leg:
+            spec = [x for x in spec if x[0] in args.leg]
         for name, r, c, D, kind, order, prec in spec:
             leg = run_leg(tn, torch, r, c, D, kind, 0, order, prec, max(3, args.steps // 4),
                           1, profile=True)
-            leg["roofline"] = roofline(leg["kernels"], prec)
+            wl = ({0: "sweep", 1: "quadrant"}.get(order) if (r, c, D, kind) == (12, 12, 4, "uniform")
+                  and prec == "f32" else None)
+            leg["roofline"] = roofline(leg["kernels"], prec, wl)
             legs[name] = leg
             log(f"{name}: {leg['ms']:.3f} ms, {leg['gflops']:.1f} GFLOP/s, "
                 f"log|Z|={leg['log_abs']:.10f}")
-        ref = legs["quad12_f64"]["log_abs"]
+        ref = legs["quad12_f64"]["log_abs"] if "quad12_f64" in legs else None
         for name, leg in list(legs.items()) + [("headline", head)]:
-            if leg["rows"] == 12 and leg["inputs"] == "uniform":
+            if ref is not None and leg["rows"] == 12 and leg["inputs"] == "uniform":
                 leg["dlogz_vs_gpu_f64"] = abs(leg["log_abs"] - ref)
         if not args.no_batch:
             legs["batch512_f32"] = batch_leg(tn, torch)
@@ -322,7 +361,7 @@ def main():
         "contractions_per_s": head["contractions_per_s"],
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "log_abs": head["log_abs"],
-        "roofline": roofline(head_kernels, "f32"),
+        "roofline": roofline(head_kernels, "f32", "quadrant"),
         "kernels": head_kernels,
         "legs": legs,
     }

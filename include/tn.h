@@ -264,10 +264,12 @@ tn_status tn_server_destroy(tn_server* server);
  *                        order as single steps: bitwise-identical results);
  *                        0 = one launch per step.
  *   TN_OPT_CHUNK_SCHEDULE : workgroups of a column-chunk launch: 0 (default)
- *                        = one per 16-fibre tile; 1 = as many as are resident
- *                        at once, each over a contiguous run of tiles with
- *                        the next tile's slice loaded during the current one.
- *                        Results are identical either way.                  */
+ *                        = one per tile of 16 boundary fibres, two or more
+ *                        resident per CU; 1 = one persistent workgroup per CU
+ *                        over a contiguous run of 128-byte tiles (32 FP32
+ *                        fibres), the next tile's slice loaded during the
+ *                        current one.  Both give results within the stated
+ *                        tolerances (FP32 sums may differ in the last bits).  */
 #define TN_OPT_KERNEL_IMPL 0
 #define TN_OPT_BATCH_THREADS 1
 #define TN_OPT_FUSE_STEPS 2
