@@ -185,13 +185,22 @@ def batch_leg(tn, torch, n=512, seed=2024, reps=20):
     single = [tn.contract_grid(p, s, "f32", ws) for p, s in zip(plans, sites)]
     torch.cuda.synchronize()
     dt_seq = time.perf_counter() - t0
-    same = all((a.mantissa, a.exp2_sum) == (c.mantissa, c.exp2_sum) for a, c in zip(res, single))
+    # one launch per step: the batch kernel's own per-step arithmetic, so the
+    # results must agree bit for bit (fused column chunks sum in another order)
+    tn.tn_set_option(tn.TN_OPT_FUSE_STEPS, 0)
+    try:
+        plain = [tn.contract_grid(p, s, "f32", ws) for p, s in zip(plans, sites)]
+    finally:
+        tn.tn_set_option(tn.TN_OPT_FUSE_STEPS, 2)
+    same = all((a.mantissa, a.exp2_sum) == (c.mantissa, c.exp2_sum) for a, c in zip(res, plain))
+    rel = max(abs(a.log_abs - c.log_abs) / max(1.0, abs(c.log_abs)) for a, c in zip(res, single))
     return {"lattices": n, "precision": "f32", "ms": 1e3 * dt,
             "contractions_per_s": n / dt, "gflops": flops / dt / 1e9,
             "flops_per_batch": flops, "tuned_threads": tuned["best"],
             "tuning_ms": {str(k): v for k, v in tuned["ms"].items()},
             "sequential_ms": 1e3 * dt_seq, "sequential_contractions_per_s": n / dt_seq,
-            "speedup_vs_sequential": dt_seq / dt, "bitwise_equal_to_single": same,
+            "speedup_vs_sequential": dt_seq / dt, "bitwise_equal_to_single_step_launches": same,
+            "max_rel_dlogz_vs_fused_single": rel,
             "all_finite": all(r.status == 0 for r in res)}
 
 
