@@ -274,6 +274,15 @@ tn_status tn_server_destroy(tn_server* server);
 #define TN_OPT_BATCH_THREADS 1
 #define TN_OPT_FUSE_STEPS 2
 #define TN_OPT_CHUNK_SCHEDULE 3
+/*   TN_OPT_QUADRANT_STREAMS : 1 = tn_contract_grid sweeps the two bottom
+ *                        quadrants on a second stream it creates for the
+ *                        calling thread, concurrently with the top quadrants
+ *                        and the first ring product (measured +2% at 12x12,
+ *                        D=4: the sweeps and the GEMM share the CUs); the
+ *                        stream takes one of the process's hardware queues
+ *                        (GPU_MAX_HW_QUEUES, 4 by default) for good.
+ *                        0 (default) = one stream.                          */
+#define TN_OPT_QUADRANT_STREAMS 4
 tn_status tn_set_option(int32_t option, int64_t value);
 
 /* ------------------------------------------------------------ profiling

@@ -196,6 +196,7 @@ TN_OPT_KERNEL_IMPL = 0
 TN_OPT_BATCH_THREADS = 1
 TN_OPT_FUSE_STEPS = 2
 TN_OPT_CHUNK_SCHEDULE = 3
+TN_OPT_QUADRANT_STREAMS = 4
 
 
 class tn_kernel_stat(C.Structure):

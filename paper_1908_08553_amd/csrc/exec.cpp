@@ -256,6 +256,9 @@ void fill_stage_descs(const Plan& p, const Layout& L, int64_t s_base,
   }
 }
 
+int32_t g_quadrant_streams = 0;
+void set_quadrant_streams(int32_t on) { g_quadrant_streams = on ? 1 : 0; }
+
 HostKeep::~HostKeep() {
   if (p_) (void)hipHostFree(p_);
 }
@@ -281,7 +284,8 @@ size_t head_bytes(const Plan& p, const Layout& L) {
 
 tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                   void* ws, size_t ws_bytes, hipStream_t stream, HostKeep& keep,
-                  LaunchTimer& timer, std::string& err) {
+                  LaunchTimer& timer, std::string& err, const SideStream* side,
+                  LaunchTimer* side_timer) {
   const Layout L = make_layout(p, prec);
   if (ws_bytes < L.total) {
     err = "workspace too small: need " + std::to_string(L.total) + " bytes";
@@ -411,14 +415,25 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
     }
     max_acts = std::max(max_acts, acts[u].size());
   }
-  for (size_t t = 0; t < max_acts; ++t) {
+  // Launch action t of the units in `units` on stream `st` (same-kind steps of
+  // several units go out together).
+#define TN_HIP_L(call)                                        \
+  do {                                                        \
+    const hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) {                                   \
+      err = std::string(#call) + ": " + hip_msg(e_);          \
+      return TN_EDEVICE;                                      \
+    }                                                         \
+  } while (0)
+  auto launch_actions = [&](const std::vector<size_t>& units, size_t t, hipStream_t st,
+                            LaunchTimer& tm) -> tn_status {
     AbsorbArgs group[4];
     const Step* gsteps[4];
     PairArgs pairs[4];
     ChunkArgs chunks[4];
     double pair_bytes = 0.0, pair_flops = 0.0, chunk_bytes = 0.0, chunk_flops = 0.0;
     int32_t n = 0, np = 0, nc = 0;
-    for (size_t u = 0; u < nu; ++u) {
+    for (size_t u : units) {
       if (t >= acts[u].size()) continue;
       const Action& ac = acts[u][t];
       const AbsorbArgs a = args_of(u, ac.k);
@@ -473,15 +488,15 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
     }
     if (nc > 0) {
       const char* cname = "";
-      timer.before();
-      TN_HIP(launch_absorb_chunks(chunks, nc, sa, state, stream, &cname));
-      timer.after(cname, chunk_bytes, chunk_flops);
+      tm.before();
+      TN_HIP_L(launch_absorb_chunks(chunks, nc, sa, state, st, &cname));
+      tm.after(cname, chunk_bytes, chunk_flops);
     }
     const char* kname = "";
     if (np > 0) {
-      timer.before();
-      TN_HIP(launch_absorb_pairs(pairs, np, sa, state, stream, &kname));
-      timer.after(kname, pair_bytes, pair_flops);
+      tm.before();
+      TN_HIP_L(launch_absorb_pairs(pairs, np, sa, state, st, &kname));
+      tm.after(kname, pair_bytes, pair_flops);
     }
     if (n > 1 && absorb_policy() == 0 && absorb_group_supported(group, n)) {
       double bytes = 0.0, flops = 0.0;
@@ -489,15 +504,37 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
         bytes += step_bytes(group[i], *gsteps[i]);
         flops += static_cast<double>(gsteps[i]->flops);
       }
-      timer.before();
-      TN_HIP(launch_absorb_group(group, n, sa, state, stream, &kname));
-      timer.after(kname, bytes, flops);
+      tm.before();
+      TN_HIP_L(launch_absorb_group(group, n, sa, state, st, &kname));
+      tm.after(kname, bytes, flops);
     } else {
       for (int32_t i = 0; i < n; ++i) {
-        timer.before();
-        TN_HIP(launch_absorb(group[i], sa, state, stream, &kname));
-        timer.after(kname, step_bytes(group[i], *gsteps[i]), static_cast<double>(gsteps[i]->flops));
+        tm.before();
+        TN_HIP_L(launch_absorb(group[i], sa, state, st, &kname));
+        tm.after(kname, step_bytes(group[i], *gsteps[i]), static_cast<double>(gsteps[i]->flops));
       }
+    }
+    return TN_OK;
+  };
+#undef TN_HIP_L
+  // Quadrant plans with a side stream: the bottom units (ya, yb) run on the
+  // side stream, concurrently with the top units and the first ring product.
+  const bool split_streams = p.has_ring && nu == 4 && side != nullptr && side_timer != nullptr;
+  std::vector<size_t> main_units, side_units;
+  if (split_streams) {
+    main_units = {static_cast<size_t>(p.ring.xa), static_cast<size_t>(p.ring.xb)};
+    side_units = {static_cast<size_t>(p.ring.ya), static_cast<size_t>(p.ring.yb)};
+    TN_HIP(hipEventRecord(side->fork, stream));
+    TN_HIP(hipStreamWaitEvent(side->stream, side->fork, 0));
+  } else {
+    for (size_t u = 0; u < nu; ++u) main_units.push_back(u);
+  }
+  for (size_t t = 0; t < max_acts; ++t) {
+    tn_status st = launch_actions(main_units, t, stream, timer);
+    if (st != TN_OK) return st;
+    if (split_streams) {
+      st = launch_actions(side_units, t, side->stream, *side_timer);
+      if (st != TN_OK) return st;
     }
   }
   // a rescale on the INIT step of a one-row unit needs no measurement: its
@@ -521,6 +558,17 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
     const char* kname = "";
     const double es = (t == EL_F64) ? 8.0 : 4.0;
     double* partials = reinterpret_cast<double*>(base + L.partials);
+    // X = TL^T TR (units xa, xb) first, stored; then Yt = BL^T BR (units ya,
+    // yb) with the float64 dot sum X o Yt fused into its epilogue.  With a
+    // side stream the bottom units were swept there: join before Yt.
+    hipStream_t ys = split_streams ? side->stream : stream;
+    LaunchTimer& ytm = split_streams ? *side_timer : timer;
+    auto join = [&]() -> hipError_t {
+      if (!split_streams) return hipSuccess;
+      hipError_t e2 = hipEventRecord(side->join, side->stream);
+      if (e2 == hipSuccess) e2 = hipStreamWaitEvent(stream, side->join, 0);
+      return e2;
+    };
     if (L.split_ring && absorb_policy() == 0) {
       // BF16x3: split + transpose each quadrant tensor once, then NT GEMMs
       const int64_t rows[4] = {g.m, g.n, g.n, g.m};
@@ -530,49 +578,57 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
       for (int u = 0; u < 4; ++u) {
         hs[u] = reinterpret_cast<uint16_t*>(base + L.split[u][0]);
         ls[u] = reinterpret_cast<uint16_t*>(base + L.split[u][1]);
-        timer.before();
-        TN_HIP(launch_split_transpose(reinterpret_cast<const float*>(unit_ptr(u)), kk[u], rows[u],
-                                      unit_slot(u), hs[u], ls[u], stream));
-        timer.after("split_transpose",
-                    4.0 * static_cast<double>(kk[u] * rows[u]) +
-                        4.0 * static_cast<double>(rows[u] * split_k_padded(kk[u])),
-                    0.0);
       }
-      // Yt = BL BR^T (BL = unit ya, BR = unit yb), then X = TL TR^T fused with the dot
-      timer.before();
-      TN_HIP(launch_ring_bf16x3_nt(hs[g.ya], ls[g.ya], hs[g.yb], ls[g.yb], g.m, g.n,
-                                   split_k_padded(g.ky), reinterpret_cast<float*>(base + L.yt),
-                                   nullptr, nullptr, stream));
-      timer.after("ring_mfma_bf16x3", es * static_cast<double>(g.ky * (g.m + g.n) + g.m * g.n),
-                  2.0 * static_cast<double>(g.m * g.n * g.ky));
+      auto split = [&](int32_t u, hipStream_t st, LaunchTimer& tm) -> hipError_t {
+        tm.before();
+        const hipError_t e2 = launch_split_transpose(reinterpret_cast<const float*>(unit_ptr(u)),
+                                                     kk[u], rows[u], unit_slot(u), hs[u], ls[u], st);
+        tm.after("split_transpose",
+                 4.0 * static_cast<double>(kk[u] * rows[u]) +
+                     4.0 * static_cast<double>(rows[u] * split_k_padded(kk[u])),
+                 0.0);
+        return e2;
+      };
+      TN_HIP(split(g.xa, stream, timer));
+      TN_HIP(split(g.xb, stream, timer));
+      TN_HIP(split(g.ya, ys, ytm));
+      TN_HIP(split(g.yb, ys, ytm));
       timer.before();
       TN_HIP(launch_ring_bf16x3_nt(hs[g.xa], ls[g.xa], hs[g.xb], ls[g.xb], g.m, g.n,
-                                   split_k_padded(g.kx), nullptr,
-                                   reinterpret_cast<const float*>(base + L.yt), partials, stream));
+                                   split_k_padded(g.kx), reinterpret_cast<float*>(base + L.yt),
+                                   nullptr, nullptr, stream));
       timer.after("ring_mfma_bf16x3", es * static_cast<double>(g.kx * (g.m + g.n) + g.m * g.n),
-                  2.0 * static_cast<double>(g.m * g.n * g.kx) + 2.0 * static_cast<double>(g.m * g.n));
+                  2.0 * static_cast<double>(g.m * g.n * g.kx));
+      TN_HIP(join());
+      timer.before();
+      TN_HIP(launch_ring_bf16x3_nt(hs[g.ya], ls[g.ya], hs[g.yb], ls[g.yb], g.m, g.n,
+                                   split_k_padded(g.ky), nullptr,
+                                   reinterpret_cast<const float*>(base + L.yt), partials, stream));
+      timer.after("ring_mfma_bf16x3", es * static_cast<double>(g.ky * (g.m + g.n) + g.m * g.n),
+                  2.0 * static_cast<double>(g.m * g.n * g.ky) + 2.0 * static_cast<double>(g.m * g.n));
       n_part = ring_bf16x3_nt_partials(g.m, g.n);
     } else {
-    RingArgs y;
-    y.A = unit_ptr(g.ya); y.B = unit_ptr(g.yb);
-    y.type = t; y.arith = arith;
-    y.m = g.m; y.n = g.n; y.k = g.ky;
-    y.sa = unit_slot(g.ya); y.sb = unit_slot(g.yb);
-    y.c_out = base + L.yt; y.dot_with = nullptr; y.partials = nullptr;
-    timer.before();
-    TN_HIP(launch_ring(y, stream, &kname, &n_part));
-    timer.after(kname, es * static_cast<double>(g.ky * (g.m + g.n) + g.m * g.n),
-                2.0 * static_cast<double>(g.m * g.n * g.ky));
-    RingArgs x = y;
-    x.A = unit_ptr(g.xa); x.B = unit_ptr(g.xb);
-    x.k = g.kx;
-    x.sa = unit_slot(g.xa); x.sb = unit_slot(g.xb);
-    x.c_out = nullptr; x.dot_with = base + L.yt;
-    x.partials = partials;
-    timer.before();
-    TN_HIP(launch_ring(x, stream, &kname, &n_part));
-    timer.after(kname, es * static_cast<double>(g.kx * (g.m + g.n) + g.m * g.n),
-                2.0 * static_cast<double>(g.m * g.n * g.kx) + 2.0 * static_cast<double>(g.m * g.n));
+      RingArgs x;
+      x.A = unit_ptr(g.xa); x.B = unit_ptr(g.xb);
+      x.type = t; x.arith = arith;
+      x.m = g.m; x.n = g.n; x.k = g.kx;
+      x.sa = unit_slot(g.xa); x.sb = unit_slot(g.xb);
+      x.c_out = base + L.yt; x.dot_with = nullptr; x.partials = nullptr;
+      timer.before();
+      TN_HIP(launch_ring(x, stream, &kname, &n_part));
+      timer.after(kname, es * static_cast<double>(g.kx * (g.m + g.n) + g.m * g.n),
+                  2.0 * static_cast<double>(g.m * g.n * g.kx));
+      TN_HIP(join());
+      RingArgs y = x;
+      y.A = unit_ptr(g.ya); y.B = unit_ptr(g.yb);
+      y.k = g.ky;
+      y.sa = unit_slot(g.ya); y.sb = unit_slot(g.yb);
+      y.c_out = nullptr; y.dot_with = base + L.yt;
+      y.partials = partials;
+      timer.before();
+      TN_HIP(launch_ring(y, stream, &kname, &n_part));
+      timer.after(kname, es * static_cast<double>(g.ky * (g.m + g.n) + g.m * g.n),
+                  2.0 * static_cast<double>(g.m * g.n * g.ky) + 2.0 * static_cast<double>(g.m * g.n));
     }
     timer.before();
     TN_HIP(launch_finalize(state, nullptr, nullptr, partials, n_part, stream));
@@ -591,8 +647,25 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
   // runtime has shut down)
   thread_local HostKeep* const keep_ptr = new HostKeep;
   HostKeep& keep = *keep_ptr;
+  // one side stream per thread and device, kept like the pinned image; only
+  // with the quadrant-streams option (each stream takes one of the process's
+  // few hardware queues)
+  thread_local int side_dev = -1;
+  thread_local SideStream side;
+  thread_local bool side_ok = false;
+  int dev = 0;
+  if (g_quadrant_streams && hipGetDevice(&dev) == hipSuccess && dev != side_dev) {
+    side = SideStream{};
+    side_ok = hipStreamCreateWithFlags(&side.stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&side.fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&side.join, hipEventDisableTiming) == hipSuccess;
+    side_dev = dev;
+  }
+  const bool use_side = g_quadrant_streams && side_ok;
   LaunchTimer timer(stream);
-  const tn_status s = enqueue(p, sites, on_device, prec, ws, ws_bytes, stream, keep, timer, err);
+  LaunchTimer side_timer(use_side ? side.stream : stream, use_side);
+  const tn_status s = enqueue(p, sites, on_device, prec, ws, ws_bytes, stream, keep, timer, err,
+                              use_side ? &side : nullptr, use_side ? &side_timer : nullptr);
   if (s != TN_OK) return s;
   const Layout L = make_layout(p, prec);
   const DevState* state = reinterpret_cast<const DevState*>(static_cast<char*>(ws) + L.state);
@@ -606,6 +679,7 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
   }
   *out = *staged;
   timer.flush();
+  side_timer.flush();
   if (out->status != TN_OK) {
     err = "non-finite value in the inputs or an intermediate";
     return out->status;

@@ -90,11 +90,27 @@ class HostKeep {
 // Bytes of the uploaded head image and offset of the result record in it.
 size_t head_bytes(const Plan& p, const Layout& L);
 
+// A second stream and two events: the bottom quadrant units of a quadrant
+// plan are swept on `stream` concurrently with the top units and the first
+// ring product (fork after staging, join before the second ring product).
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+// 1: tn_contract_grid sweeps the bottom quadrant units on a second stream of
+// the calling thread (see SideStream); 0 (default): one stream.
+void set_quadrant_streams(int32_t on);
+extern int32_t g_quadrant_streams;
+
 // Issue every copy and launch of one contraction on `stream` without waiting;
 // the result record lands in the workspace's DevState (offset Layout.state).
+// With `side` (and `side_timer` for its launches) quadrant plans also use
+// side->stream; all work is joined back into `stream` before it ends.
 tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                   void* ws, size_t ws_bytes, hipStream_t stream, HostKeep& keep,
-                  LaunchTimer& timer, std::string& err);
+                  LaunchTimer& timer, std::string& err, const SideStream* side = nullptr,
+                  LaunchTimer* side_timer = nullptr);
 
 tn_status contract(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                    void* ws, size_t ws_bytes, hipStream_t stream, tn_result* out,
