@@ -99,7 +99,7 @@ struct Cfg<double, 1> {
 };
 
 // XOR of the base-4 digits of x (x < 2^16), two bits.
-__device__ inline int dx4(int x) {
+__host__ __device__ constexpr int dx4(int x) {
   x ^= x >> 8;
   x ^= x >> 4;
   x ^= x >> 2;
@@ -116,7 +116,7 @@ __device__ inline int dx4(int x) {
 // that digit between the two groups of a half-wave), never share a bank.  G
 // is XOR-linear in d.
 template <int SP>
-__device__ inline int gsw(int d) {
+__host__ __device__ constexpr int gsw(int d) {
   return SP == 16 ? (d << 4) : (((d & 1) ? 80 : 0) | ((d & 2) << 4));
 }
 template <int SP>
@@ -175,83 +175,143 @@ __device__ inline SiteOps<T, MODE> site_ops(const T* sS, const uint16_t* sH, con
   return o;
 }
 
-// One step (base-4 shift JSH of the K/N index in the row, compile time) on
-// every (prefix, m) group of the slice; wave w takes groups w, w + NW, ...
-// and both 16-spectator halves of each.  Lane (c, g):
+// Slice row of the first (kidx = 0) row of group `grp` at base-4 shift JSH:
+// the group index is (prefix, m); the K/N index sits between them.  A bit
+// permutation of grp.
+__host__ __device__ constexpr int base_of(int grp, int jsh) {
+  return ((grp >> jsh) << (jsh + 4)) + (grp & ((1 << jsh) - 1));
+}
+
+// Step J of a K-row chunk on every 16-spectator tile of the slice.  Wave w
+// takes tiles w + i NW (i = 0, 1, ...): group g0 + i GS (g0 = w / HS, GS =
+// NW / HS, a power of two > g0) and half h = w % HS.  Group indices g0 and
+// i GS occupy disjoint bits, base_of permutes bits, and both the row offset
+// and the swizzle digit are XOR-linear over disjoint bits, so tile i differs
+// from tile 0 by compile-time constants: a row offset T_i (in the immediate
+// offset of the LDS instruction) and an XOR term L_i.  Lane (c, g):
 //   reads f32/f64: kidx = 4kk + g;  bf16: kidx = 2t + (g & 1)
 //   writes f32/bf16: kidx = 4g + r;  f64: kidx = g + 4r
-// A word offset is TB + H(kidx) + (LX ^ G(X(kidx))) (see tile_of); with JSH
-// fixed, H splits into a per-lane term and compile-time offsets, and the XOR
-// term takes one of four per-group values.
+// The word offset of (row base + kidx * 4^(JSH/2), spectator 16h + c) is
+//     TB + H(kidx) + (LX ^ G(X(kidx)))
+// (see tile_of) with H(kidx) = (JSH ? kidx : kidx & ~3) << (JSH + log2 SP)
+// split into per-lane terms and constants.
 // TOP: first step of a top-edge chunk (only kidx < 4 carries data).
-template <typename T, int MODE, int SP, int NW, int JSH, bool TOP>
-__device__ inline void step_groups(T* lds, int M1, const SiteOps<T, MODE>& o, int c, int gg,
-                                   int w) {
+template <typename T, int MODE, int SP, int NW, int K, int J, bool TOP, int NBM>
+__device__ inline void step_kj(T* lds, const SiteOps<T, MODE>& o, int c, int gg, int w) {
   using V4 = typename std::conditional<MODE == M_F64, f64x4, f32x4>::type;
-  constexpr int LS = SP == 16 ? 4 : 5, HS = SP / 16, J = JSH + LS;
-  // per-lane parts of H
-  const int hb_r = (MODE == M_BF16X3) ? (JSH ? (gg & 1) << J : 0) : (JSH ? gg << J : 0);
-  const int hb_w = (MODE == M_F64) ? (JSH ? gg << J : 0) : (JSH ? gg << (J + 2) : gg << (LS + 2));
-  const int gx_r = (MODE == M_BF16X3) ? gsw<SP>(gg & 1) : gsw<SP>(gg);
-  const int gx_w = gsw<SP>(gg);
-  for (int grp = w; grp < M1; grp += NW) {
-    const int base = ((grp >> JSH) << (JSH + 4)) + (grp & ((1 << JSH) - 1));
-    const int tb = (base & ~3) * SP + c;
-    const int lb = gsw<SP>((base & 3) ^ dx4(base >> 2));
+  constexpr int JSH = 2 * (K - 1 - J), LS = SP == 16 ? 4 : 5, HS = SP / 16, JB = JSH + LS;
+  constexpr int NTILE = (1 << (2 * (K - 1))) * HS;   // tiles of the step
+  constexpr int GS = NW / HS;
+  constexpr int NTW = NTILE >= NW ? NTILE / NW : 1;  // tiles per wave
+  static_assert(NTILE < NW || NTILE % NW == 0, "tiles spread evenly over the waves");
+  if (NTILE < NW && w >= NTILE) return;
+  const int g0 = w / HS, h = w % HS;
+  const int base0 = base_of(g0, JSH);
+  const int tb = (base0 & ~3) * SP + c;
+  const int lx = gsw<SP>((base0 & 3) ^ dx4(base0 >> 2)) ^ (h << 4);
+  // per-lane parts of H and of the XOR term
+  const int rb = tb + ((MODE == M_BF16X3) ? (JSH ? (gg & 1) << JB : 0) : (JSH ? gg << JB : 0));
+  const int wb = tb + ((MODE == M_F64) ? (JSH ? gg << JB : 0) : (JSH ? gg << (JB + 2) : gg << (LS + 2)));
+  const int lr = lx ^ ((MODE == M_BF16X3) ? gsw<SP>(gg & 1) : gsw<SP>(gg));
+  const int lw = lx ^ gsw<SP>(gg);
+  constexpr int NB = NTW < NBM ? NTW : NBM;   // tiles in flight
+  static_assert(NTW % NB == 0, "whole batches");
 #pragma unroll
-    for (int h = 0; h < HS; ++h) {
-      const int lx = lb ^ (h << 4);
-      int xr[4], xw[4];
+  for (int bb = 0; bb < NTW; bb += NB) {
+    V4 acc[NB];
+    if constexpr (MODE == M_BF16X3) {
+      const __bf16 zero = __builtin_bit_cast(__bf16, static_cast<uint16_t>(0));
+      bf16x8 b0[NB], b1[NB];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        xr[q] = tb + hb_r + ((lx ^ gx_r) ^ gsw<SP>(q));
-        xw[q] = tb + hb_w + ((lx ^ gx_w) ^ gsw<SP>(q));
-      }
-      V4 acc;
-      if constexpr (MODE == M_BF16X3) {
-        const __bf16 zero = __builtin_bit_cast(__bf16, static_cast<uint16_t>(0));
-        bf16x8 b0, b1;
+      for (int i = 0; i < NB; ++i) {
+        const int bi = base_of((bb + i) * GS, JSH);
+        const int ti = bi * SP, li = gsw<SP>(dx4(bi >> 2));
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
           if (TOP && t >= 2) {
-            b0[t] = zero;
-            b1[t] = zero;
+            b0[i][t] = zero;
+            b1[i][t] = zero;
             continue;
           }
-          const int ht = JSH ? ((2 * t) << J) : ((t >> 1) << (LS + 2));
-          const float x = lds[xr[(2 * (t & 1)) ^ (t >> 1)] + ht];
+          const int ht = JSH ? ((2 * t) << JB) : ((t >> 1) << (LS + 2));
+          const float x = lds[rb + ti + ht + (lr ^ (li ^ gsw<SP>((2 * (t & 1)) ^ (t >> 1))))];
           const __bf16 hi = static_cast<__bf16>(x);
-          b0[t] = hi;
-          b1[t] = gg < 2 ? static_cast<__bf16>(x - static_cast<float>(hi)) : zero;
-        }
-        acc = f32x4{0.f, 0.f, 0.f, 0.f};
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a0, b0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a1, b1, acc, 0, 0, 0);
-      } else {
-        constexpr int KK = TOP ? 1 : 4;
-        T b[KK];
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk) {
-          const int ht = JSH ? (kk << (J + 2)) : (kk << (LS + 2));
-          b[kk] = lds[xr[kk] + ht];
-        }
-        acc = V4{0, 0, 0, 0};
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk) {
-          if constexpr (MODE == M_F64)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[kk], b[kk], acc, 0, 0, 0);
-          else
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[kk], b[kk], acc, 0, 0, 0);
+          b0[i][t] = hi;
+          b1[i][t] = gg < 2 ? static_cast<__bf16>(x - static_cast<float>(hi)) : zero;
         }
       }
-      // register r of lane (c, g) holds D[n][c], n = 4g + r (f32 and bf16
-      // results) or n = g + 4r (f64)
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a0, b0[i], acc[i], 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a1, b1[i], acc[i], 0, 0, 0);
+    } else {
+      constexpr int KK = TOP ? 1 : 4;
+      T b[NB][KK];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int bi = base_of((bb + i) * GS, JSH);
+        const int ti = bi * SP, li = gsw<SP>(dx4(bi >> 2));
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+          const int ht = JSH ? (kk << (JB + 2)) : (kk << (LS + 2));
+          b[i][kk] = lds[rb + ti + ht + (lr ^ (li ^ gsw<SP>(kk)))];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i) acc[i] = V4{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          if constexpr (MODE == M_F64)
+            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[kk], b[i][kk], acc[i], 0, 0, 0);
+          else
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[kk], b[i][kk], acc[i], 0, 0, 0);
+        }
+    }
+    // register r of lane (c, g) holds D[n][c], n = 4g + r (f32 and bf16
+    // results) or n = g + 4r (f64)
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int bi = base_of((bb + i) * GS, JSH);
+      const int ti = bi * SP, li = gsw<SP>(dx4(bi >> 2));
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int ht = (MODE == M_F64) ? (JSH ? (r << (J + 2)) : (r << (LS + 2))) : (JSH ? (r << J) : 0);
-        lds[xw[r] + ht] = acc[r];
+        const int ht = (MODE == M_F64) ? (JSH ? (r << (JB + 2)) : (r << (LS + 2))) : (JSH ? (r << JB) : 0);
+        lds[wb + ti + ht + (lw ^ (li ^ gsw<SP>(r)))] = acc[i][r];
       }
     }
+  }
+}
+
+// All K steps of a K-row chunk (barrier after each).
+template <typename T, int MODE, int SP, int NW, int K, int NBM>
+__device__ inline void chunk_steps(T* lds, const T* sS, const uint16_t* sH, const uint16_t* sL,
+                                   bool top, int c, int gg, int w) {
+  {
+    const SiteOps<T, MODE> o = site_ops<T, MODE>(sS, sH, sL, c, gg);
+    if (top) step_kj<T, MODE, SP, NW, K, 0, true, NBM>(lds, o, c, gg, w);
+    else step_kj<T, MODE, SP, NW, K, 0, false, NBM>(lds, o, c, gg, w);
+    __syncthreads();
+  }
+  {
+    const SiteOps<T, MODE> o = site_ops<T, MODE>(sS + 256, sH + 256, sL + 256, c, gg);
+    step_kj<T, MODE, SP, NW, K, 1, false, NBM>(lds, o, c, gg, w);
+    __syncthreads();
+  }
+  if constexpr (K >= 3) {
+    const SiteOps<T, MODE> o = site_ops<T, MODE>(sS + 512, sH + 512, sL + 512, c, gg);
+    step_kj<T, MODE, SP, NW, K, 2, false, NBM>(lds, o, c, gg, w);
+    __syncthreads();
+  }
+  if constexpr (K >= 4) {
+    const SiteOps<T, MODE> o = site_ops<T, MODE>(sS + 768, sH + 768, sL + 768, c, gg);
+    step_kj<T, MODE, SP, NW, K, 3, false, NBM>(lds, o, c, gg, w);
+    __syncthreads();
   }
 }
 
@@ -303,20 +363,43 @@ __device__ inline Tile tile_at(GroupRef g, uint32_t t) {
 //  * Whole suffixes of 1 entry (the tile is SP consecutive p): f -> (4 rows,
 //    4 spectators); four 4-row loads transposed in registers into four rows
 //    of 4 spectators.
-template <int SP>
-__device__ inline void run_pos(int f, int& row, int& s) {
-  constexpr int PR = SP / 4;   // vectors per row
-  const int r = f / PR;
-  row = (r & ~3) | ((r & 1) << 1) | ((r >> 1) & 1);
-  s = 4 * (f % PR);
-}
-template <int SP>
-__device__ inline void blk_pos(int f, int& row4, int& s) {
-  constexpr int PB = SP / 4;   // 4-spectator blocks per 4-row group
-  const int r = f / PB;
-  row4 = 4 * ((r & ~3) | ((r & 1) << 1) | ((r >> 1) & 1));
-  s = 4 * (f % PB);
-}
+// Iteration it adds a multiple of 4 rows that shares no bits with the
+// thread's own row, so its LDS word is the thread's word plus a compile-time
+// offset, with a compile-time XOR of the swizzle (word_of is XOR-linear over
+// disjoint bits); see run_lds / blk_lds.
+__host__ __device__ constexpr int swap01(int r) { return (r & ~3) | ((r & 1) << 1) | ((r >> 1) & 1); }
+
+template <int SP, int NTH>
+struct RunPos {
+  static constexpr int PR = SP / 4, RS = NTH / PR;   // vectors per row; rows per iteration
+  static_assert(RS % 4 == 0, "iterations move whole row quads");
+  int row0, s0, bw, x0;   // first row and spectator; LDS word = bw + (x0 ^ X(it)) + it RS SP
+  __device__ explicit RunPos(int tid) {
+    row0 = swap01(tid / PR);
+    s0 = 4 * (tid % PR);
+    const int d = (row0 & 3) ^ dx4(row0 >> 2);
+    bw = (row0 & ~3) * SP + (s0 & 15);
+    x0 = gsw<SP>(d) ^ (s0 & 16);
+  }
+  __device__ int lds(int it) const { return bw + it * RS * SP + (x0 ^ gsw<SP>(dx4((it * RS) >> 2))); }
+};
+
+template <int SP, int NTH>
+struct BlkPos {
+  static constexpr int PB = SP / 4, RB = 4 * (NTH / PB);   // blocks per row quad; rows per iteration
+  int row4, s0, bw, x0;   // LDS word of row row4 + it RB + u: bw + it RB SP + (x0 ^ G(u) ^ X(it))
+  __device__ explicit BlkPos(int tid) {
+    row4 = 4 * swap01(tid / PB);
+    s0 = 4 * (tid % PB);
+    bw = row4 * SP + (s0 & 15);
+    x0 = gsw<SP>(dx4(row4 >> 2)) ^ (s0 & 16);
+  }
+  __device__ int lds(int it, int u, int lsh) const {
+    // the store of a bottom-edge chunk reads rows (row4 + it RB + u) << 2
+    if (lsh == 0) return bw + it * RB * SP + ((x0 ^ gsw<SP>(u)) ^ gsw<SP>(dx4((it * RB) >> 2)));
+    return word_of<SP>((row4 + it * RB + u) << lsh, s0);
+  }
+};
 
 // Global element offset (from the tile's base) of (row, spectator s) on the
 // row-run path.
@@ -338,69 +421,60 @@ __device__ inline void slice_load(UnitRef d, const Tile& x, V4* v) {
   const int tid = threadIdx.x;
   const T* src = static_cast<const T*>(d.in) + x.p0 * x.rows_in * d.post + x.q0;
   if (x.qn >= 4) {
+    using P = RunPos<SP, NTH>;
+    const P ps(tid);
     const int total = x.rows_in * SP / 4;
+    const T* g0 = src + run_off(x, d.post, x.rows_in, ps.row0, ps.s0);
+    const int64_t step = static_cast<int64_t>(P::RS) * (x.qrun ? d.post : x.qn);
 #pragma unroll
-    for (int it = 0; it < Regs<IT>::N; ++it) {   // slots past IT are never in range
-      const int f = it * NTH + tid;
-      if (f < total) {
-        int row, s;
-        run_pos<SP>(f, row, s);
-        v[it] = *reinterpret_cast<const V4*>(src + run_off(x, d.post, x.rows_in, row, s));
-      }
-    }
+    for (int it = 0; it < Regs<IT>::N; ++it)   // slots past IT are never in range
+      if (it * NTH + tid < total) v[it] = *reinterpret_cast<const V4*>(g0 + it * step);
   } else {
+    using P = BlkPos<SP, NTH>;
+    const P ps(tid);
     const int total = x.rows_in * SP / 16;
+    const T* g0 = src + static_cast<int64_t>(ps.s0) * x.rows_in + ps.row4;
 #pragma unroll
-    for (int it = 0; it < Regs<IT>::NB; ++it) {
-      const int f = it * NTH + tid;
-      if (f < total) {
-        int row4, s;
-        blk_pos<SP>(f, row4, s);
+    for (int it = 0; it < Regs<IT>::NB; ++it)
+      if (it * NTH + tid < total) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          v[4 * it + i] =
-              *reinterpret_cast<const V4*>(src + static_cast<int64_t>(s + i) * x.rows_in + row4);
+          v[4 * it + i] = *reinterpret_cast<const V4*>(g0 + static_cast<int64_t>(i) * x.rows_in +
+                                                       it * P::RB);
       }
-    }
   }
 }
 
 // Scale the loaded slice by 2^-shift and write it to its LDS rows.
 template <typename T, typename V4, int SP, int NTH, int IT>
-__device__ inline void slice_to_lds(UnitRef d, const Tile& x, const V4* v, T* lds) {
+__device__ inline void slice_to_lds(UnitRef d, const Tile& x, V4* v, T* lds) {
   const int tid = threadIdx.x;
   const int32_t shift = shift_of(d.scale_slot);
   if (x.qn >= 4) {
+    const RunPos<SP, NTH> ps(tid);
     const int total = x.rows_in * SP / 4;
 #pragma unroll
-    for (int it = 0; it < Regs<IT>::N; ++it) {
-      const int f = it * NTH + tid;
-      if (f < total) {
-        int row, s;
-        run_pos<SP>(f, row, s);
+    for (int it = 0; it < Regs<IT>::N; ++it)
+      if (it * NTH + tid < total) {
         V4 y = v[it];
 #pragma unroll
         for (int i = 0; i < 4; ++i) y[i] = scale(y[i], shift);
-        *reinterpret_cast<V4*>(&lds[word_of<SP>(row, s)]) = y;
+        *reinterpret_cast<V4*>(&lds[ps.lds(it)]) = y;
       }
-    }
   } else {
+    const BlkPos<SP, NTH> ps(tid);
     const int total = x.rows_in * SP / 16;
 #pragma unroll
-    for (int it = 0; it < Regs<IT>::NB; ++it) {
-      const int f = it * NTH + tid;
-      if (f < total) {
-        int row4, s;
-        blk_pos<SP>(f, row4, s);
+    for (int it = 0; it < Regs<IT>::NB; ++it)
+      if (it * NTH + tid < total) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           V4 y;
 #pragma unroll
           for (int i = 0; i < 4; ++i) y[i] = scale(v[4 * it + i][u], shift);
-          *reinterpret_cast<V4*>(&lds[word_of<SP>(row4 + u, s)]) = y;
+          *reinterpret_cast<V4*>(&lds[ps.lds(it, u, 0)]) = y;
         }
       }
-    }
   }
 }
 
@@ -422,31 +496,17 @@ __device__ inline void stage_sites(UnitRef d, T* sS, uint16_t* sH, uint16_t* sL)
 }
 
 // The chunk's k steps on the slice in LDS, in place (ends with a barrier).
-template <typename T, int MODE, int SP, int NW>
+template <typename T, int MODE, int SP, int NW, int KM, int NBM>
 __device__ inline void slice_steps(UnitRef d, T* lds, const T* sS, const uint16_t* sH,
                                    const uint16_t* sL) {
   const int lane = threadIdx.x & 63, c = lane & 15, gg = lane >> 4, w = threadIdx.x >> 6;
-  const int k = d.k, M1 = 1 << (2 * (k - 1));
-  for (int j = 0; j < k; ++j) {
-    const int jsh = 2 * (k - 1 - j);
-    const SiteOps<T, MODE> o = site_ops<T, MODE>(sS + 256 * j, sH + 256 * j, sL + 256 * j, c, gg);
-    const bool top = j == 0 && d.k1 == 4;
-    switch (jsh) {
-      case 0: step_groups<T, MODE, SP, NW, 0, false>(lds, M1, o, c, gg, w); break;
-      case 2:
-        if (top) step_groups<T, MODE, SP, NW, 2, true>(lds, M1, o, c, gg, w);
-        else step_groups<T, MODE, SP, NW, 2, false>(lds, M1, o, c, gg, w);
-        break;
-      case 4:
-        if (top) step_groups<T, MODE, SP, NW, 4, true>(lds, M1, o, c, gg, w);
-        else step_groups<T, MODE, SP, NW, 4, false>(lds, M1, o, c, gg, w);
-        break;
-      default:
-        if (top) step_groups<T, MODE, SP, NW, 6, true>(lds, M1, o, c, gg, w);
-        else step_groups<T, MODE, SP, NW, 6, false>(lds, M1, o, c, gg, w);
-        break;
-    }
-    __syncthreads();
+  const bool top = d.k1 == 4;
+  if (d.k == 2) {
+    chunk_steps<T, MODE, SP, NW, 2, NBM>(lds, sS, sH, sL, top, c, gg, w);
+  } else if (d.k == 3 || KM < 4) {
+    chunk_steps<T, MODE, SP, NW, 3, NBM>(lds, sS, sH, sL, top, c, gg, w);
+  } else {
+    if constexpr (KM >= 4) chunk_steps<T, MODE, SP, NW, 4, NBM>(lds, sS, sH, sL, top, c, gg, w);
   }
 }
 
@@ -458,40 +518,39 @@ __device__ inline void slice_store(UnitRef d, const Tile& x, const T* lds, T& mx
   const int lsh = d.nl == 4 ? 2 : 0;
   T* dst = static_cast<T*>(d.out) + x.p0 * x.rows_out * d.post + x.q0;
   if (x.qn >= 4) {
+    using P = RunPos<SP, NTH>;
+    const P ps(tid);
     const int total = x.rows_out * SP / 4;
+    T* g0 = dst + run_off(x, d.post, x.rows_out, ps.row0, ps.s0);
+    const int64_t step = static_cast<int64_t>(P::RS) * (x.qrun ? d.post : x.qn);
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int f = it * NTH + tid;
-      if (f < total) {
-        int row, s;
-        run_pos<SP>(f, row, s);
-        const V4 v = *reinterpret_cast<const V4*>(&lds[word_of<SP>(row << lsh, s)]);
-        *reinterpret_cast<V4*>(dst + run_off(x, d.post, x.rows_out, row, s)) = v;
+    for (int it = 0; it < Regs<IT>::N; ++it)
+      if (it * NTH + tid < total) {
+        const int wd = lsh ? word_of<SP>((ps.row0 + it * P::RS) << lsh, ps.s0) : ps.lds(it);
+        const V4 v = *reinterpret_cast<const V4*>(&lds[wd]);
+        *reinterpret_cast<V4*>(g0 + it * step) = v;
 #pragma unroll
         for (int i = 0; i < 4; ++i) track(v[i], mx, bad);
       }
-    }
   } else {
+    using P = BlkPos<SP, NTH>;
+    const P ps(tid);
     const int total = x.rows_out * SP / 16;
+    T* g0 = dst + static_cast<int64_t>(ps.s0) * x.rows_out + ps.row4;
 #pragma unroll
-    for (int it = 0; it < Regs<IT>::NB; ++it) {
-      const int f = it * NTH + tid;
-      if (f < total) {
-        int row4, s;
-        blk_pos<SP>(f, row4, s);
+    for (int it = 0; it < Regs<IT>::NB; ++it)
+      if (it * NTH + tid < total) {
         V4 r[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          r[u] = *reinterpret_cast<const V4*>(&lds[word_of<SP>((row4 + u) << lsh, s)]);
+        for (int u = 0; u < 4; ++u) r[u] = *reinterpret_cast<const V4*>(&lds[ps.lds(it, u, lsh)]);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const V4 v = {r[0][i], r[1][i], r[2][i], r[3][i]};
-          *reinterpret_cast<V4*>(dst + static_cast<int64_t>(s + i) * x.rows_out + row4) = v;
+          *reinterpret_cast<V4*>(g0 + static_cast<int64_t>(i) * x.rows_out + it * P::RB) = v;
 #pragma unroll
           for (int q = 0; q < 4; ++q) track(v[q], mx, bad);
         }
       }
-    }
   }
 }
 
@@ -522,7 +581,7 @@ absorb_chunk(ChunkGroup arg) {
     stage_sites<T, MODE, NTH>(d, sS, sH, sL);
     slice_to_lds<T, V4, SP, NTH, IT>(d, x, v, lds);
     __syncthreads();
-    slice_steps<T, MODE, SP, NW>(d, lds, sS, sH, sL);
+    slice_steps<T, MODE, SP, NW, KM, C::PS ? 2 : 8>(d, lds, sS, sH, sL);
     T mx = 0;
     int bad = 0;
     slice_store<T, V4, SP, NTH, IT>(d, x, lds, mx, bad);
@@ -551,7 +610,7 @@ absorb_chunk(ChunkGroup arg) {
         nxt = tile_at<SP>(g, t + 1);
         slice_load<T, V4, SP, NTH, IT>(g->u[nxt.ui], nxt, v);
       }
-      slice_steps<T, MODE, SP, NW>(d, lds, sS, sH, sL);
+      slice_steps<T, MODE, SP, NW, KM, C::PS ? 2 : 8>(d, lds, sS, sH, sL);
       slice_store<T, V4, SP, NTH, IT>(d, cur, lds, mx, bad);
       if (!more || nxt.ui != cur.ui) {
         if (d.max_slot) reduce_and_publish<T, NW>(mx, bad, d.max_slot, g->flags);
