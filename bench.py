@@ -326,7 +326,9 @@ def main():
                 ("quad12_f64", 12, 12, 4, "uniform", 1, "f64"),
                 ("ising12_d4_quad_f32", 12, 12, 4, "ising", 1, "f32"),
                 ("sweep10_f64_normal", 10, 10, 4, "normal", 0, "f64"),
-                ("quad10_f64_normal", 10, 10, 4, "normal", 1, "f64")]
+                ("quad10_f64_normal", 10, 10, 4, "normal", 1, "f64"),
+                ("quad10_f32", 10, 10, 4, "uniform", 1, "f32"),
+                ("quad10_bf16x3", 10, 10, 4, "uniform", 1, "bf16x3")]
         if args.leg:
             spec = [x for x in spec if x[0] in args.leg]
         for name, r, c, D, kind, order, prec in spec:

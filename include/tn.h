@@ -105,6 +105,9 @@ typedef struct {
   int64_t moved_entries;   /* algorithmic boundary traffic: sum of d(in)+d(out)  */
   int64_t workspace_bytes[3]; /* per precision (TN_PREC_*): bytes tn_contract_grid needs */
   int64_t hbm_bytes[3];       /* per precision: algorithmic HBM bytes of one contraction */
+  int32_t ring_slices[3];     /* per precision: split-K slices the workspace holds for the
+                                 stored ring product (1 = unsplit, 0 = no ring)          */
+  int32_t reserved2;
 } tn_plan_info;
 
 typedef struct tn_plan tn_plan;

@@ -48,7 +48,8 @@ class tn_plan_info(C.Structure):
                 ("n_slots", C.c_int32), ("reserved", C.c_int32),
                 ("peak_entries", C.c_int64), ("flops", C.c_int64),
                 ("moved_entries", C.c_int64), ("workspace_bytes", C.c_int64 * 3),
-                ("hbm_bytes", C.c_int64 * 3)]
+                ("hbm_bytes", C.c_int64 * 3), ("ring_slices", C.c_int32 * 3),
+                ("reserved2", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -167,7 +168,8 @@ def tn_plan_stats(plan: Plan) -> dict:
             "peak_entries": info.peak_entries, "flops": info.flops,
             "moved_entries": info.moved_entries,
             "workspace_bytes": list(info.workspace_bytes),
-            "hbm_bytes": list(info.hbm_bytes)}
+            "hbm_bytes": list(info.hbm_bytes),
+            "ring_slices": list(info.ring_slices)}
 
 
 def tn_plan_text(plan: Plan) -> str:

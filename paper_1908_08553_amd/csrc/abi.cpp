@@ -82,8 +82,10 @@ tn_status tn_plan_stats(const tn_plan* plan, tn_plan_info* out) {
     out->flops = p.flops;
     out->moved_entries = p.moved;
     for (int32_t prec = 0; prec < 3; ++prec) {
-      out->workspace_bytes[prec] = static_cast<int64_t>(tn::make_layout(p, prec).total);
+      const tn::Layout L = tn::make_layout(p, prec);
+      out->workspace_bytes[prec] = static_cast<int64_t>(L.total);
       out->hbm_bytes[prec] = tn::algorithmic_bytes(p, prec);
+      out->ring_slices[prec] = p.has_ring ? L.yt_slices : 0;
     }
     return TN_OK;
   } catch (...) {

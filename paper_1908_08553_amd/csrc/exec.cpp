@@ -181,14 +181,35 @@ Layout make_layout(const Plan& p, int32_t prec) {
   }
   if (p.has_ring) {
     const int32_t t = prec == TN_PREC_F64 ? EL_F64 : EL_F32;
-    L.yt = off;
-    L.yt_bytes = align_up(static_cast<size_t>(p.ring.m * p.ring.n) * elem_bytes(t));
-    off += L.yt_bytes;
-    L.n_partials = ring_partials(p.ring.m, p.ring.n);
-    L.partials = off;
-    off = align_up(off + sizeof(double) * static_cast<size_t>(L.n_partials));
     const Ring& g = p.ring;
     L.split_ring = prec == TN_PREC_BF16X3 && g.m % 4 == 0 && g.n % 4 == 0;
+    // Room for every kernel choice of either ring product, whatever the
+    // kernel policy is when the plan runs: split-K slices of X and partial
+    // sums of the fused dot follow from the shapes alone.
+    RingArgs rx{};
+    rx.type = t;
+    rx.arith = prec == TN_PREC_F64 ? AR_F64 : AR_F32;
+    rx.m = g.m; rx.n = g.n; rx.k = g.kx;
+    RingArgs ry = rx;
+    ry.k = g.ky;
+    int32_t slices = 1;
+    int64_t parts = ring_partials(g.m, g.n);
+    if (ring_mfma_supported(rx)) {
+      slices = std::max(slices, ring_mfma_splits(rx));
+      parts = std::max(parts, ring_mfma_partials_for(ry));
+    }
+    if (L.split_ring) {
+      slices = std::max(slices, ring_bf16x3_nt_splits(g.m, g.n, split_k_padded(g.kx)));
+      parts = std::max(parts, ring_bf16x3_nt_partials(g.m, g.n, split_k_padded(g.ky)));
+    }
+    L.yt = off;
+    L.yt_slices = slices;
+    L.yt_bytes = align_up(static_cast<size_t>(slices) * static_cast<size_t>(g.m * g.n) *
+                          elem_bytes(t));
+    off += L.yt_bytes;
+    L.n_partials = parts;
+    L.partials = off;
+    off = align_up(off + sizeof(double) * static_cast<size_t>(L.n_partials));
     if (L.split_ring) {
       // unit u as [k][rows]: rows = m for TL/BL, n for TR/BR; k = kx (top) / ky (bottom)
       const int64_t rows[4] = {g.m, g.n, g.n, g.m};
@@ -593,20 +614,31 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
       TN_HIP(split(g.xb, stream, timer));
       TN_HIP(split(g.ya, ys, ytm));
       TN_HIP(split(g.yb, ys, ytm));
+      NtArgs x{};
+      x.Ah = hs[g.xa]; x.Al = ls[g.xa]; x.Bh = hs[g.xb]; x.Bl = ls[g.xb];
+      x.m = g.m; x.n = g.n; x.kp = split_k_padded(g.kx);
+      x.c_out = reinterpret_cast<float*>(base + L.yt); x.dot_with = nullptr;
+      x.c_slices_cap = L.yt_slices;
+      int32_t x_slices = 0;
+      int64_t unused = 0;
       timer.before();
-      TN_HIP(launch_ring_bf16x3_nt(hs[g.xa], ls[g.xa], hs[g.xb], ls[g.xb], g.m, g.n,
-                                   split_k_padded(g.kx), reinterpret_cast<float*>(base + L.yt),
-                                   nullptr, nullptr, stream));
-      timer.after("ring_mfma_bf16x3", es * static_cast<double>(g.kx * (g.m + g.n) + g.m * g.n),
+      TN_HIP(launch_ring_bf16x3_nt(x, stream, &unused, &x_slices));
+      timer.after("ring_mfma_bf16x3",
+                  es * static_cast<double>(g.kx * (g.m + g.n) + x_slices * g.m * g.n),
                   2.0 * static_cast<double>(g.m * g.n * g.kx));
       TN_HIP(join());
+      NtArgs y{};
+      y.Ah = hs[g.ya]; y.Al = ls[g.ya]; y.Bh = hs[g.yb]; y.Bl = ls[g.yb];
+      y.m = g.m; y.n = g.n; y.kp = split_k_padded(g.ky);
+      y.c_out = nullptr; y.dot_with = reinterpret_cast<const float*>(base + L.yt);
+      y.w_slices = x_slices;
+      y.partials = partials; y.partials_cap = L.n_partials;
+      int32_t none = 0;
       timer.before();
-      TN_HIP(launch_ring_bf16x3_nt(hs[g.ya], ls[g.ya], hs[g.yb], ls[g.yb], g.m, g.n,
-                                   split_k_padded(g.ky), nullptr,
-                                   reinterpret_cast<const float*>(base + L.yt), partials, stream));
-      timer.after("ring_mfma_bf16x3", es * static_cast<double>(g.ky * (g.m + g.n) + g.m * g.n),
+      TN_HIP(launch_ring_bf16x3_nt(y, stream, &n_part, &none));
+      timer.after("ring_mfma_bf16x3",
+                  es * static_cast<double>(g.ky * (g.m + g.n) + x_slices * g.m * g.n),
                   2.0 * static_cast<double>(g.m * g.n * g.ky) + 2.0 * static_cast<double>(g.m * g.n));
-      n_part = ring_bf16x3_nt_partials(g.m, g.n);
     } else {
       RingArgs x;
       x.A = unit_ptr(g.xa); x.B = unit_ptr(g.xb);
@@ -614,9 +646,12 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
       x.m = g.m; x.n = g.n; x.k = g.kx;
       x.sa = unit_slot(g.xa); x.sb = unit_slot(g.xb);
       x.c_out = base + L.yt; x.dot_with = nullptr; x.partials = nullptr;
+      x.c_slices_cap = L.yt_slices;
+      int32_t x_slices = 0;
+      int64_t unused = 0;
       timer.before();
-      TN_HIP(launch_ring(x, stream, &kname, &n_part));
-      timer.after(kname, es * static_cast<double>(g.kx * (g.m + g.n) + g.m * g.n),
+      TN_HIP(launch_ring(x, stream, &kname, &unused, &x_slices));
+      timer.after(kname, es * static_cast<double>(g.kx * (g.m + g.n) + x_slices * g.m * g.n),
                   2.0 * static_cast<double>(g.m * g.n * g.kx));
       TN_HIP(join());
       RingArgs y = x;
@@ -624,10 +659,12 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
       y.k = g.ky;
       y.sa = unit_slot(g.ya); y.sb = unit_slot(g.yb);
       y.c_out = nullptr; y.dot_with = base + L.yt;
-      y.partials = partials;
+      y.w_slices = x_slices;
+      y.partials = partials; y.partials_cap = L.n_partials;
+      int32_t none = 0;
       timer.before();
-      TN_HIP(launch_ring(y, stream, &kname, &n_part));
-      timer.after(kname, es * static_cast<double>(g.ky * (g.m + g.n) + g.m * g.n),
+      TN_HIP(launch_ring(y, stream, &kname, &n_part, &none));
+      timer.after(kname, es * static_cast<double>(g.ky * (g.m + g.n) + x_slices * g.m * g.n),
                   2.0 * static_cast<double>(g.m * g.n * g.ky) + 2.0 * static_cast<double>(g.m * g.n));
     }
     timer.before();

@@ -23,7 +23,8 @@ struct Layout {
   size_t s64 = 0, s32 = 0, shi = 0, slo = 0;
   size_t buf[4][2] = {};             // unit boundary ping-pong buffers
   size_t buf_bytes[4] = {};
-  size_t yt = 0, yt_bytes = 0;       // ring: C^T E
+  size_t yt = 0, yt_bytes = 0;       // ring: the stored product X (split-K slices)
+  int32_t yt_slices = 1;
   size_t partials = 0;
   int64_t n_partials = 0;
   bool split_ring = false;           // BF16x3 ring from pre-split operands

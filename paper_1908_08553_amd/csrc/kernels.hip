@@ -368,14 +368,18 @@ int64_t ring_partials(int64_t m, int64_t n) {
 }
 
 hipError_t launch_ring(const RingArgs& a, hipStream_t stream, const char** kname,
-                       int64_t* n_partials) {
-  if (g_absorb_policy == 0 && ring_mfma_supported(a)) {
-    *n_partials = ring_mfma_partials_for(a);
-    return launch_ring_mfma(a, stream, kname);
-  }
-  *n_partials = ((a.m + kRT - 1) / kRT) * ((a.n + kRT - 1) / kRT);
+                       int64_t* n_partials, int32_t* c_slices) {
+  // split BF16x3 rings on the matrix cores take launch_ring_bf16x3_nt
+  if (g_absorb_policy == 0 && ring_mfma_supported(a) && a.arith != AR_BF16X3)
+    return launch_ring_mfma(a, stream, kname, n_partials, c_slices);
+  // one 64 x 64 tile per workgroup, no split-K
+  const bool dot = a.dot_with != nullptr;
+  *n_partials = dot ? ring_partials(a.m, a.n) : 0;
+  *c_slices = dot ? 0 : 1;
   const int64_t gx = (a.n + kRT - 1) / kRT, gy = (a.m + kRT - 1) / kRT;
-  if (gx > INT_MAX || gy > 65535) return hipErrorInvalidValue;
+  if (gx > INT_MAX || gy > 65535 || a.w_slices != 1 || (dot && *n_partials > a.partials_cap) ||
+      (!dot && a.c_slices_cap < 1))
+    return hipErrorInvalidValue;
   dim3 g(static_cast<uint32_t>(gx), static_cast<uint32_t>(gy)), b(kBlock);
   *kname = a.type == EL_F64 ? "ring_valu_f64" : (a.arith == AR_BF16X3 ? "ring_valu_bf16x3" : "ring_valu_f32");
   if (a.type == EL_F64) {

@@ -64,11 +64,25 @@ hipError_t launch_absorb_group(const AbsorbArgs* a, int32_t n, const StagedArray
 int64_t split_k_padded(int64_t k);
 hipError_t launch_split_transpose(const float* T, int64_t kd, int64_t md, const int32_t* slot,
                                   uint16_t* H, uint16_t* L, hipStream_t stream);
-// C = A B^T from split operands (A [m][kp], B [n][kp]); fused dot as launch_ring.
-int64_t ring_bf16x3_nt_partials(int64_t m, int64_t n);
-hipError_t launch_ring_bf16x3_nt(const uint16_t* Ah, const uint16_t* Al, const uint16_t* Bh,
-                                 const uint16_t* Bl, int64_t m, int64_t n, int64_t kp, float* c_out,
-                                 const float* dot_with, double* partials, hipStream_t stream);
+// C = A B^T from split operands (A [m][kp], B [n][kp], kp a multiple of 32);
+// split-K slices, caps and the fused dot as RingArgs / launch_ring.
+struct NtArgs {
+  const uint16_t* Ah;
+  const uint16_t* Al;
+  const uint16_t* Bh;
+  const uint16_t* Bl;
+  int64_t m, n, kp;
+  float* c_out;
+  const float* dot_with;
+  int32_t w_slices = 1;
+  int32_t c_slices_cap = 1;
+  double* partials = nullptr;
+  int64_t partials_cap = 0;
+};
+int32_t ring_bf16x3_nt_splits(int64_t m, int64_t n, int64_t kp);
+int64_t ring_bf16x3_nt_partials(int64_t m, int64_t n, int64_t kp);
+hipError_t launch_ring_bf16x3_nt(const NtArgs& a, hipStream_t stream, int64_t* n_partials,
+                                 int32_t* c_slices);
 
 // Two consecutive D = 4 bulk steps of one column fused into one pass (see
 // absorb_pair in absorb_mfma.hip): s1 = (pre, 16, 16, 4*post2), s2 = (4*pre,
@@ -121,8 +135,10 @@ hipError_t launch_absorb(const AbsorbArgs& a, const StagedArrays& st, DevState* 
                          hipStream_t stream, const char** kname);
 
 // Ring: C = 2^-(sa+sb) * A^T B with A [k][m], B [k][n].  If dot_with != nullptr
-// the tile results are multiplied elementwise with dot_with [m][n] and summed
-// in float64 into partials[tile]; otherwise C is stored to c_out [m][n].
+// the tile results are multiplied elementwise with W = sum of the w_slices
+// slices of dot_with (each [m][n], stride m*n) and summed in float64 into
+// partials (at most partials_cap); otherwise C is stored to c_out as up to
+// c_slices_cap split-K slices [m][n] whose sum is the product.
 struct RingArgs {
   const void* A;
   const void* B;
@@ -134,19 +150,25 @@ struct RingArgs {
   void* c_out;
   const void* dot_with;
   double* partials;
+  int32_t w_slices = 1;
+  int32_t c_slices_cap = 1;
+  int64_t partials_cap = 0;
 };
 
-// Upper bound on the float64 partials a fused-dot ring launch writes.
+// Partials the vector-ALU ring writes (64 x 64 tiles).
 int64_t ring_partials(int64_t m, int64_t n);
-// *n_partials receives the number of partials this launch writes (fused dot).
+// *n_partials receives the number of partials this launch writes (fused dot),
+// *c_slices the number of slices it stored (stored product).
 hipError_t launch_ring(const RingArgs& a, hipStream_t stream, const char** kname,
-                       int64_t* n_partials);
+                       int64_t* n_partials, int32_t* c_slices);
 
-// MFMA ring products (ring_mfma.hip): m % 4 == 0 and n % 4 == 0.
+// MFMA ring products (ring_mfma.hip): m % 4 == 0 and n % 4 == 0.  The split
+// count and partial count follow from the shape alone (before the caps).
 bool ring_mfma_supported(const RingArgs& a);
-int64_t ring_mfma_partials(int64_t m, int64_t n);
-int64_t ring_mfma_partials_for(const RingArgs& a);   // the kernel launch_ring_mfma picks
-hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** kname);
+int32_t ring_mfma_splits(const RingArgs& a);
+int64_t ring_mfma_partials_for(const RingArgs& a);
+hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** kname,
+                            int64_t* n_partials, int32_t* c_slices);
 
 // Writes state->result from the final scalar (or the sum of `n_partials`
 // partials), the site exponents and the rescale slots.

@@ -7,21 +7,28 @@
 // multiplies every entry with W[m][n] and sums in float64.
 //
 // Tiling: 128 x 128 output tile per 256-thread workgroup, four waves of 64 x 64.
-// Each k-slice of 16 is staged in LDS k-major ([k][m], [k][n]); a lane reads
-// 4 consecutive m (and n) with one 16-byte LDS load and feeds element mm of
-// its A vector and nn of its B vector to the MFMA for tile (mm, nn), so a
-// wave's 4x4 register tiles come from two LDS reads per k.  Output tile
-// (mm, nn) row i / column j is m = 4i + mm, n = 4j + nn inside the wave's
-// 64 x 64 block.  Workgroups are renumbered so that consecutive tiles of one
-// tile-row land on the same XCD (the dispatcher deals workgroups to the 8 XCDs
-// round-robin), sharing A panels in that XCD's L2.
+// Each k-slice of 16 is staged in LDS k-major ([k][m], [k][n]), double
+// buffered; a lane reads 4 consecutive m (and n) with 16-byte LDS loads and
+// feeds element mm of its A vector and nn of its B vector to the MFMA for tile
+// (mm, nn), so a wave's 4x4 register tiles come from two LDS reads per k.
+// Output tile (mm, nn) row i / column j is m = 4i + mm, n = 4j + nn inside the
+// wave's 64 x 64 block.  Workgroups are renumbered so that consecutive tiles
+// of one tile-row land on the same XCD (the dispatcher deals workgroups to the
+// 8 XCDs round-robin), sharing A panels in that XCD's L2.
 //
-// Split BF16x3 (ring_mfma_bf16x3): the staging pass converts each scaled
-// float to bf16 high/low parts and transposes into [m][k] / [n][k] so a lane
-// reads its 8 consecutive k with one 16-byte load; each 16x16x32 MFMA tile
-// accumulates hi*hi + hi*lo + lo*hi.
+// Split-K: when the output has too few tiles to give every CU two workgroups
+// the k extent is cut into S ranges of whole k-slices (workgroup s * tiles + t
+// takes range s of tile t).  A stored product then leaves S partial slices
+// C_s at stride m*n; the fused-dot launch that consumes it as W sums the
+// slices in float64 in a fixed order, and its own split ranges each write one
+// partial sum, so results do not depend on scheduling.
+//
+// Split BF16x3: split_transpose converts each scaled float to bf16 high/low
+// parts in [m][k] / [n][k] order so a lane reads its 8 consecutive k with one
+// 16-byte load; each 16x16x32 MFMA tile accumulates hi*hi + hi*lo + lo*hi.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <type_traits>
@@ -41,6 +48,8 @@ constexpr int kT = 128;      // output tile edge
 constexpr int kBK = 16;      // k-slice staged per step
 constexpr int kThreads = 256;
 constexpr int kXcd = 8;
+constexpr int kMaxSplits = 8;
+constexpr int64_t kFillGroups = 512;   // two workgroups per CU
 
 __device__ inline int32_t shift_of(const int32_t* slot) {
   if (!slot) return 0;
@@ -48,15 +57,26 @@ __device__ inline int32_t shift_of(const int32_t* slot) {
   return (e == kExpZero || e == kExpBad) ? 0 : e;
 }
 
-// Tile index -> (tile row, tile col) with XCD-aware renumbering.
-__device__ inline void tile_of(uint32_t& tm, uint32_t& tn, uint32_t ntm, uint32_t ntn) {
+// Tile index id -> (tile row, tile col) with XCD-aware renumbering.
+__device__ inline void tile_of(uint32_t& tm, uint32_t& tn, uint32_t ntm, uint32_t ntn,
+                               uint32_t id) {
   const uint32_t total = ntm * ntn;
-  const uint32_t id = blockIdx.x;
   const uint32_t per = (total + kXcd - 1) / kXcd;
   uint32_t t = (id % kXcd) * per + id / kXcd;
   if (total % kXcd != 0) t = id;   // keep it a bijection when tiles do not split evenly
   tm = t / ntn;
   tn = t - tm * ntn;
+}
+
+// k range [b, e) of split s out of S, in whole slices of bk.
+struct KRange {
+  int64_t b, e;
+};
+__device__ inline KRange k_range(int64_t kd, int32_t S, uint32_t s, int bk) {
+  const int64_t per = ((kd + bk - 1) / bk + S - 1) / S * bk;
+  const int64_t b0 = static_cast<int64_t>(s) * per;
+  const int64_t b = b0 < kd ? b0 : kd;
+  return {b, b + per < kd ? b + per : kd};
 }
 
 __device__ inline double block_sum(double v) {
@@ -70,31 +90,53 @@ __device__ inline double block_sum(double v) {
   return s;
 }
 
-// ------------------------------------------------------------ f32 / f64
+// Four consecutive entries of the W operand, summed over its slices in float64.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void ring_mfma(
-    const T* __restrict__ A, const T* __restrict__ B, int64_t M, int64_t N, int64_t Kd,
+__device__ inline void w_sum(const T* __restrict__ W, int64_t slice, int32_t w_slices, int64_t at,
+                             double (&y)[4]) {
+  using V4 = typename std::conditional<std::is_same<T, double>::value, f64x4, f32x4>::type;
+  const V4 w0 = *reinterpret_cast<const V4*>(W + at);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) y[e] = static_cast<double>(w0[e]);
+  for (int32_t j = 1; j < w_slices; ++j) {
+    const V4 wj = *reinterpret_cast<const V4*>(W + j * slice + at);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) y[e] += static_cast<double>(wj[e]);
+  }
+}
+
+// ------------------------------------------------------------ f32 / f64
+// The register budget (two waves per SIMD) keeps the 64 (f32) or 128 (f64)
+// accumulator registers in VGPRs; with more live registers the compiler parks
+// them in AGPRs and copies them out and back around every k-slice, which
+// drains the matrix pipe each time.  Two workgroups per CU (LDS: 32 KiB f32,
+// 64 KiB f64); one barrier per k-slice.
+template <typename T>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void ring_mfma(
+    const T* __restrict__ A, const T* __restrict__ B, int64_t M, int64_t N, int64_t Kd, int32_t S,
     const int32_t* sa, const int32_t* sb, T* __restrict__ C, const T* __restrict__ W,
-    double* __restrict__ partials) {
+    int32_t w_slices, double* __restrict__ partials) {
   constexpr bool F64 = std::is_same<T, double>::value;
   using V4 = typename std::conditional<F64, f64x4, f32x4>::type;
+  using C16 = typename std::conditional<F64, f64x2, f32x4>::type;
   constexpr int kVec = 16 / sizeof(T);                 // elements per 16-byte chunk
-  constexpr int kChunks = kBK * kT / kVec;             // 16-byte chunks per operand tile
-  constexpr int kPer = kChunks / kThreads;             // per thread
-  __shared__ __attribute__((aligned(32))) T As[kBK][kT];
-  __shared__ __attribute__((aligned(32))) T Bs[kBK][kT];
+  constexpr int kPer = kBK * kT / kVec / kThreads;     // 16-byte chunks per thread per operand
+  __shared__ __attribute__((aligned(32))) T As[2][kBK][kT];
+  __shared__ __attribute__((aligned(32))) T Bs[2][kBK][kT];
 
   const uint32_t ntm = static_cast<uint32_t>((M + kT - 1) / kT);
   const uint32_t ntn = static_cast<uint32_t>((N + kT - 1) / kT);
+  const uint32_t tiles = ntm * ntn;
+  const uint32_t s = blockIdx.x / tiles;
   uint32_t tm, tn;
-  tile_of(tm, tn, ntm, ntn);
+  tile_of(tm, tn, ntm, ntn, blockIdx.x - s * tiles);
+  const KRange kr = k_range(Kd, S, s, kBK);
   const int64_t m0 = static_cast<int64_t>(tm) * kT, n0 = static_cast<int64_t>(tn) * kT;
   const int ea = shift_of(sa), eb = shift_of(sb);
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
   const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
 
   // staging: chunk q -> (row kk, column cc)
-  using C16 = typename std::conditional<F64, f64x2, f32x4>::type;
   C16 ra[kPer], rb[kPer];
   auto fetch = [&](int64_t k0) {
 #pragma unroll
@@ -103,13 +145,13 @@ __global__ __launch_bounds__(kThreads) void ring_mfma(
       const int kk = q / (kT / kVec), cc = (q % (kT / kVec)) * kVec;
       const int64_t kg = k0 + kk;
       C16 va = {}, vb = {};
-      if (kg < Kd && m0 + cc < M) va = *reinterpret_cast<const C16*>(A + kg * M + m0 + cc);
-      if (kg < Kd && n0 + cc < N) vb = *reinterpret_cast<const C16*>(B + kg * N + n0 + cc);
+      if (kg < kr.e && m0 + cc < M) va = *reinterpret_cast<const C16*>(A + kg * M + m0 + cc);
+      if (kg < kr.e && n0 + cc < N) vb = *reinterpret_cast<const C16*>(B + kg * N + n0 + cc);
       ra[i] = va;
       rb[i] = vb;
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const int q = threadIdx.x + i * kThreads;
@@ -120,8 +162,8 @@ __global__ __launch_bounds__(kThreads) void ring_mfma(
         va[e] = ldexp(va[e], -ea);
         vb[e] = ldexp(vb[e], -eb);
       }
-      *reinterpret_cast<C16*>(&As[kk][cc]) = va;
-      *reinterpret_cast<C16*>(&Bs[kk][cc]) = vb;
+      *reinterpret_cast<C16*>(&As[buf][kk][cc]) = va;
+      *reinterpret_cast<C16*>(&Bs[buf][kk][cc]) = vb;
     }
   };
 
@@ -131,16 +173,17 @@ __global__ __launch_bounds__(kThreads) void ring_mfma(
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
-  fetch(0);
-  for (int64_t k0 = 0; k0 < Kd; k0 += kBK) {
-    __syncthreads();
-    stash();
-    __syncthreads();
-    if (k0 + kBK < Kd) fetch(k0 + kBK);
+  fetch(kr.b);
+  stash(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kr.b; k0 < kr.e; k0 += kBK) {
+    const bool more = k0 + kBK < kr.e;
+    if (more) fetch(k0 + kBK);
 #pragma unroll
     for (int kb = 0; kb < kBK; kb += 4) {
-      const V4 a4 = *reinterpret_cast<const V4*>(&As[kb + g][wm + 4 * c]);
-      const V4 b4 = *reinterpret_cast<const V4*>(&Bs[kb + g][wn + 4 * c]);
+      const V4 a4 = *reinterpret_cast<const V4*>(&As[buf][kb + g][wm + 4 * c]);
+      const V4 b4 = *reinterpret_cast<const V4*>(&Bs[buf][kb + g][wn + 4 * c]);
 #pragma unroll
       for (int mm = 0; mm < 4; ++mm)
 #pragma unroll
@@ -151,12 +194,16 @@ __global__ __launch_bounds__(kThreads) void ring_mfma(
             acc[mm][nn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[mm], b4[nn], acc[mm][nn], 0, 0, 0);
         }
     }
+    if (more) stash(buf ^ 1);   // the other buffer: last read before the previous barrier
+    __syncthreads();
+    buf ^= 1;
   }
 
   // epilogue: lane (c, g) register r of tile (mm, nn) holds
   //   m = wm + 4*i + mm with i = 4g + r (f32) or g + 4r (f64),  n = wn + 4c + nn
   double part = 0.0;
   const int64_t nb = n0 + wn + 4 * c;
+  T* Cs = C ? C + static_cast<int64_t>(s) * M * N : nullptr;
 #pragma unroll
   for (int mm = 0; mm < 4; ++mm) {
 #pragma unroll
@@ -166,161 +213,40 @@ __global__ __launch_bounds__(kThreads) void ring_mfma(
       if (m >= M || nb >= N) continue;
       const V4 v = {acc[mm][0][r], acc[mm][1][r], acc[mm][2][r], acc[mm][3][r]};
       if (W) {
-        const V4 y = *reinterpret_cast<const V4*>(W + m * N + nb);
+        double y[4];
+        w_sum(W, M * N, w_slices, m * N + nb, y);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) part += static_cast<double>(v[e]) * static_cast<double>(y[e]);
+        for (int e = 0; e < 4; ++e) part += static_cast<double>(v[e]) * y[e];
       } else {
-        *reinterpret_cast<V4*>(C + m * N + nb) = v;
+        *reinterpret_cast<V4*>(Cs + m * N + nb) = v;
       }
     }
   }
   if (W) {
-    const double s = block_sum(part);
-    if (threadIdx.x == 0) partials[static_cast<int64_t>(tm) * ntn + tn] = s;
-  }
-}
-
-// ------------------------------------------------------------- bf16 x 3
-__device__ inline uint16_t bf16_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
-}
-__device__ inline float bf16_float(uint16_t b) {
-  return __uint_as_float(static_cast<uint32_t>(b) << 16);
-}
-
-constexpr int kBK16 = 32;    // k-slice for the bf16 path (one MFMA k)
-constexpr int kLdk = kBK16 + 8;   // padded LDS row (bf16 entries)
-
-__global__ __launch_bounds__(kThreads) void ring_mfma_bf16x3(
-    const float* __restrict__ A, const float* __restrict__ B, int64_t M, int64_t N, int64_t Kd,
-    const int32_t* sa, const int32_t* sb, float* __restrict__ C, const float* __restrict__ W,
-    double* __restrict__ partials) {
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[kT][kLdk];
-  __shared__ __attribute__((aligned(16))) uint16_t Al[kT][kLdk];
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[kT][kLdk];
-  __shared__ __attribute__((aligned(16))) uint16_t Bl[kT][kLdk];
-
-  const uint32_t ntm = static_cast<uint32_t>((M + kT - 1) / kT);
-  const uint32_t ntn = static_cast<uint32_t>((N + kT - 1) / kT);
-  uint32_t tm, tn;
-  tile_of(tm, tn, ntm, ntn);
-  const int64_t m0 = static_cast<int64_t>(tm) * kT, n0 = static_cast<int64_t>(tn) * kT;
-  const int ea = shift_of(sa), eb = shift_of(sb);
-  const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
-  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
-
-  // staging: thread (kq, mq) = (t % 8, t / 8) owns the 4k x 4m block
-  // k = 4kq..4kq+3, m = 4mq..4mq+3 of the 32 x 128 slice: four 16-byte loads
-  // (one per k row), a register transpose, then one 8-byte LDS write of four
-  // consecutive k per m row and per split part.
-  const int kq = threadIdx.x & 7, mq = threadIdx.x >> 3;
-  f32x4 ra[4], rb[4];
-  auto fetch = [&](int64_t k0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t kg = k0 + 4 * kq + i;
-      const int cc = 4 * mq;
-      f32x4 va = {0.f, 0.f, 0.f, 0.f}, vb = {0.f, 0.f, 0.f, 0.f};
-      if (kg < Kd && m0 + cc < M) va = *reinterpret_cast<const f32x4*>(A + kg * M + m0 + cc);
-      if (kg < Kd && n0 + cc < N) vb = *reinterpret_cast<const f32x4*>(B + kg * N + n0 + cc);
-      ra[i] = va;
-      rb[i] = vb;
-    }
-  };
-  typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
-  auto stash = [&]() {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      u16x4 h_a, l_a, h_b, l_b;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float xa = ldexpf(ra[i][e], -ea), xb = ldexpf(rb[i][e], -eb);
-        h_a[i] = bf16_bits(xa);
-        l_a[i] = bf16_bits(xa - bf16_float(h_a[i]));
-        h_b[i] = bf16_bits(xb);
-        l_b[i] = bf16_bits(xb - bf16_float(h_b[i]));
-      }
-      const int row = 4 * mq + e, col = 4 * kq;
-      *reinterpret_cast<u16x4*>(&Ah[row][col]) = h_a;
-      *reinterpret_cast<u16x4*>(&Al[row][col]) = l_a;
-      *reinterpret_cast<u16x4*>(&Bh[row][col]) = h_b;
-      *reinterpret_cast<u16x4*>(&Bl[row][col]) = l_b;
-    }
-  };
-
-  f32x4 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  fetch(0);
-  for (int64_t k0 = 0; k0 < Kd; k0 += kBK16) {
-    __syncthreads();
-    stash();
-    __syncthreads();
-    if (k0 + kBK16 < Kd) fetch(k0 + kBK16);
-    // tile (mt, nt): rows wm + 16 mt + c, k = 8g .. 8g+7
-    bf16x8 ah[4], al[4], bh[4], bl[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      ah[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&Ah[wm + 16 * t + c][8 * g]));
-      al[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&Al[wm + 16 * t + c][8 * g]));
-      bh[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&Bh[wn + 16 * t + c][8 * g]));
-      bl[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&Bl[wn + 16 * t + c][8 * g]));
-    }
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        f32x4 a = acc[mt][nt];
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bh[nt], a, 0, 0, 0);
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bl[nt], a, 0, 0, 0);
-        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bh[nt], a, 0, 0, 0);
-        acc[mt][nt] = a;
-      }
-  }
-
-  // lane (c, g) register r of tile (mt, nt): m = wm + 16 mt + 4g + r, n = wn + 16 nt + c
-  double part = 0.0;
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm + 16 * mt + 4 * g + r, n = n0 + wn + 16 * nt + c;
-        if (m >= M || n >= N) continue;
-        if (W) part += static_cast<double>(acc[mt][nt][r]) * static_cast<double>(W[m * N + n]);
-        else C[m * N + n] = acc[mt][nt][r];
-      }
-  if (W) {
-    const double s = block_sum(part);
-    if (threadIdx.x == 0) partials[static_cast<int64_t>(tm) * ntn + tn] = s;
+    const double sum = block_sum(part);
+    if (threadIdx.x == 0) partials[static_cast<int64_t>(s) * tiles + tm * ntn + tn] = sum;
   }
 }
 
 // ------------------------------------------------ f32, 256 x 256 tiles
-// Same operand scheme as ring_mfma<float> on a 256 x 256 output tile: eight
-// waves in a 2 (m) x 4 (n) grid, each 128 x 64 (two 16-byte A reads and one
-// B read per k feed 32 MFMA tiles).  Twice the flops per staged byte of the
-// 128 x 128 tile; the LDS k-slices are double-buffered so one barrier per
-// slice separates staging from compute.
+// Same operand scheme on a 256 x 256 output tile: eight waves in a 2 (m) x 4
+// (n) grid, each 128 x 64 (two 16-byte A reads and one B read per k feed 32
+// MFMA tiles).  Twice the flops per staged byte of the 128 x 128 tile; the
+// LDS k-slices are double-buffered so one barrier per slice separates staging
+// from compute.  Used without split-K, when the output alone fills the chip.
 constexpr int kBT = 256;
 constexpr int kBThreads = 512;
 
 __global__ __launch_bounds__(kBThreads) void ring_mfma_f32_big(
     const float* __restrict__ A, const float* __restrict__ B, int64_t M, int64_t N, int64_t Kd,
     const int32_t* sa, const int32_t* sb, float* __restrict__ C, const float* __restrict__ W,
-    double* __restrict__ partials) {
+    int32_t w_slices, double* __restrict__ partials) {
   __shared__ __attribute__((aligned(16))) float As[2][kBK][kBT];
   __shared__ __attribute__((aligned(16))) float Bs[2][kBK][kBT];
   const uint32_t ntm = static_cast<uint32_t>((M + kBT - 1) / kBT);
   const uint32_t ntn = static_cast<uint32_t>((N + kBT - 1) / kBT);
   uint32_t tm, tn;
-  tile_of(tm, tn, ntm, ntn);
+  tile_of(tm, tn, ntm, ntn, blockIdx.x);
   const int64_t m0 = static_cast<int64_t>(tm) * kBT, n0 = static_cast<int64_t>(tn) * kBT;
   const int ea = shift_of(sa), eb = shift_of(sb);
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
@@ -403,9 +329,10 @@ __global__ __launch_bounds__(kBThreads) void ring_mfma_f32_big(
         const f32x4 v = {acc[4 * h + mm][0][r], acc[4 * h + mm][1][r], acc[4 * h + mm][2][r],
                          acc[4 * h + mm][3][r]};
         if (W) {
-          const f32x4 y = *reinterpret_cast<const f32x4*>(W + m * N + nb);
+          double y[4];
+          w_sum(W, M * N, w_slices, m * N + nb, y);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) part += static_cast<double>(v[e]) * static_cast<double>(y[e]);
+          for (int e = 0; e < 4; ++e) part += static_cast<double>(v[e]) * y[e];
         } else {
           *reinterpret_cast<f32x4*>(C + m * N + nb) = v;
         }
@@ -424,6 +351,18 @@ __global__ __launch_bounds__(kBThreads) void ring_mfma_f32_big(
 }
 
 // ------------------------------------------- split + transpose for BF16x3
+__device__ inline uint16_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ inline float bf16_float(uint16_t b) {
+  return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+constexpr int kBK16 = 32;    // k-slice for the bf16 path (one MFMA k)
+constexpr int kLdk = kBK16 + 8;   // padded LDS row (bf16 entries)
+
 // T [kd][md] float (k-major, as a quadrant sweep leaves it), scaled by 2^-e,
 // becomes H, L [md][kp] bf16 (hi, lo parts; k-contiguous, rows padded to kp
 // with zeros) so the GEMM below reads 8 consecutive k with one 16-byte load.
@@ -478,17 +417,33 @@ __global__ __launch_bounds__(kThreads) void split_transpose(const float* __restr
   }
 }
 
+// Fused-dot terms of one lane's results, added to part in row order: entry
+// (m, n) of the product times the sum of the W slices there, for a lane
+// holding rows m = mb + r (r < 4) of column n.
+__device__ inline void dot_bf16_lane(double& part, const f32x4& v, const float* __restrict__ W,
+                                     int64_t M, int64_t N, int32_t w_slices, int64_t mb,
+                                     int64_t n) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t m = mb + r;
+    if (m >= M || n >= N) continue;
+    double y = static_cast<double>(W[m * N + n]);
+    for (int32_t j = 1; j < w_slices; ++j) y += static_cast<double>(W[j * M * N + m * N + n]);
+    part += static_cast<double>(v[r]) * y;
+  }
+}
+
 // ---------------------------------------------- bf16x3 GEMM, k-contiguous
 // C[m][n] = sum_k A[m][k] B[n][k] with A, B given as bf16 (hi, lo) pairs
 // [rows][kp]; three MFMA products per tile (lo*hi + hi*lo + hi*hi, float32
 // accumulation).  Each 32-wide k-slice of the four operand tiles (128 x 32
 // bf16 each) is copied to LDS with 16-byte loads (four lanes per 64-byte row
 // piece), no conversion; lane (c, g) then reads its 8 consecutive k of row
-// wm + 16 t + c with one 16-byte LDS load.
+// wm + 16 t + c with one 16-byte LDS load.  Split-K as ring_mfma.
 __global__ __launch_bounds__(kThreads) void ring_bf16x3_nt(
     const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al,
     const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl, int64_t M, int64_t N,
-    int64_t kp, float* __restrict__ C, const float* __restrict__ W,
+    int64_t kp, int32_t S, float* __restrict__ C, const float* __restrict__ W, int32_t w_slices,
     double* __restrict__ partials) {
   __shared__ __attribute__((aligned(16))) uint16_t sAh[kT][kLdk];
   __shared__ __attribute__((aligned(16))) uint16_t sAl[kT][kLdk];
@@ -496,8 +451,11 @@ __global__ __launch_bounds__(kThreads) void ring_bf16x3_nt(
   __shared__ __attribute__((aligned(16))) uint16_t sBl[kT][kLdk];
   const uint32_t ntm = static_cast<uint32_t>((M + kT - 1) / kT);
   const uint32_t ntn = static_cast<uint32_t>((N + kT - 1) / kT);
+  const uint32_t tiles = ntm * ntn;
+  const uint32_t s = blockIdx.x / tiles;
   uint32_t tm, tn;
-  tile_of(tm, tn, ntm, ntn);
+  tile_of(tm, tn, ntm, ntn, blockIdx.x - s * tiles);
+  const KRange kr = k_range(kp, S, s, kBK16);
   const int64_t m0 = static_cast<int64_t>(tm) * kT, n0 = static_cast<int64_t>(tn) * kT;
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
   const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
@@ -535,12 +493,12 @@ __global__ __launch_bounds__(kThreads) void ring_bf16x3_nt(
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  fetch(0);
-  for (int64_t k0 = 0; k0 < kp; k0 += kBK16) {
+  if (kr.b < kr.e) fetch(kr.b);
+  for (int64_t k0 = kr.b; k0 < kr.e; k0 += kBK16) {
     __syncthreads();
     stash();
     __syncthreads();
-    if (k0 + kBK16 < kp) fetch(k0 + kBK16);
+    if (k0 + kBK16 < kr.e) fetch(k0 + kBK16);
     bf16x8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -561,21 +519,25 @@ __global__ __launch_bounds__(kThreads) void ring_bf16x3_nt(
       }
   }
 
+  // lane (c, g) register r of tile (mt, nt): m = wm + 16 mt + 4g + r, n = wn + 16 nt + c
   double part = 0.0;
+  float* Cs = C ? C + static_cast<int64_t>(s) * M * N : nullptr;
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int nt = 0; nt < 4; ++nt) {
+      const int64_t mb = m0 + wm + 16 * mt + 4 * g, n = n0 + wn + 16 * nt + c;
+      if (W) {
+        dot_bf16_lane(part, acc[mt][nt], W, M, N, w_slices, mb, n);
+      } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm + 16 * mt + 4 * g + r, n = n0 + wn + 16 * nt + c;
-        if (m >= M || n >= N) continue;
-        if (W) part += static_cast<double>(acc[mt][nt][r]) * static_cast<double>(W[m * N + n]);
-        else C[m * N + n] = acc[mt][nt][r];
+        for (int r = 0; r < 4; ++r)
+          if (mb + r < M && n < N) Cs[(mb + r) * N + n] = acc[mt][nt][r];
       }
+    }
   if (W) {
-    const double s = block_sum(part);
-    if (threadIdx.x == 0) partials[static_cast<int64_t>(tm) * ntn + tn] = s;
+    const double sum = block_sum(part);
+    if (threadIdx.x == 0) partials[static_cast<int64_t>(s) * tiles + tm * ntn + tn] = sum;
   }
 }
 
@@ -583,11 +545,11 @@ __global__ __launch_bounds__(kThreads) void ring_bf16x3_nt(
 // ring_bf16x3_nt on a 256 x 256 tile: eight waves (2 x 4), each 128 x 64, so
 // every staged k-slice feeds twice the MFMA work.  The four 256 x 32 operand
 // slices (80 KiB of LDS) are single-buffered with a register prefetch of the
-// next slice.
+// next slice.  Used without split-K, when the output alone fills the chip.
 __global__ __launch_bounds__(kBThreads) void ring_bf16x3_nt_big(
     const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al,
     const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl, int64_t M, int64_t N,
-    int64_t kp, float* __restrict__ C, const float* __restrict__ W,
+    int64_t kp, float* __restrict__ C, const float* __restrict__ W, int32_t w_slices,
     double* __restrict__ partials) {
   __shared__ __attribute__((aligned(16))) uint16_t sAh[kBT][kLdk];
   __shared__ __attribute__((aligned(16))) uint16_t sAl[kBT][kLdk];
@@ -596,7 +558,7 @@ __global__ __launch_bounds__(kBThreads) void ring_bf16x3_nt_big(
   const uint32_t ntm = static_cast<uint32_t>((M + kBT - 1) / kBT);
   const uint32_t ntn = static_cast<uint32_t>((N + kBT - 1) / kBT);
   uint32_t tm, tn;
-  tile_of(tm, tn, ntm, ntn);
+  tile_of(tm, tn, ntm, ntn, blockIdx.x);
   const int64_t m0 = static_cast<int64_t>(tm) * kBT, n0 = static_cast<int64_t>(tn) * kBT;
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
   const int wm = (w >> 2) * 128, wn = (w & 3) * 64;
@@ -667,14 +629,16 @@ __global__ __launch_bounds__(kBThreads) void ring_bf16x3_nt_big(
 #pragma unroll
   for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int nt = 0; nt < 4; ++nt) {
+      const int64_t mb = m0 + wm + 16 * mt + 4 * g, n = n0 + wn + 16 * nt + c;
+      if (W) {
+        dot_bf16_lane(part, acc[mt][nt], W, M, N, w_slices, mb, n);
+      } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm + 16 * mt + 4 * g + r, n = n0 + wn + 16 * nt + c;
-        if (m >= M || n >= N) continue;
-        if (W) part += static_cast<double>(acc[mt][nt][r]) * static_cast<double>(W[m * N + n]);
-        else C[m * N + n] = acc[mt][nt][r];
+        for (int r = 0; r < 4; ++r)
+          if (mb + r < M && n < N) C[(mb + r) * N + n] = acc[mt][nt][r];
       }
+    }
   if (W) {
     __shared__ double red[kBThreads / 64];
     for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
@@ -688,58 +652,88 @@ __global__ __launch_bounds__(kBThreads) void ring_bf16x3_nt_big(
   }
 }
 
+// Split count for `tiles` output tiles over `slices` k-slices: double S while
+// the grid is short of two workgroups per CU and every split keeps at least
+// eight k-slices.
+int32_t pick_splits(int64_t tiles, int64_t slices) {
+  int32_t s = 1;
+  while (tiles * s < kFillGroups && slices >= 16 * s && 2 * s <= kMaxSplits) s *= 2;
+  return s;
+}
+
+int64_t tiles_of(int64_t m, int64_t n, int64_t edge) {
+  return ((m + edge - 1) / edge) * ((n + edge - 1) / edge);
+}
+
+// The 256 x 256 kernels run when their tiles alone cover every CU.
+bool big_tiles(int64_t m, int64_t n) { return tiles_of(m, n, kBT) >= 256; }
+
+// Clamp S to what the caller's buffers hold: C slices for a stored product,
+// partial sums for a fused dot.
+int32_t capped(int32_t s, int64_t tiles, bool dot, int32_t c_cap, int64_t p_cap) {
+  const int64_t cap = dot ? p_cap / std::max<int64_t>(tiles, 1) : c_cap;
+  while (s > 1 && s > cap) s /= 2;
+  return s;
+}
+
 }  // namespace
 
 bool ring_mfma_supported(const RingArgs& a) {
   return a.m % 4 == 0 && a.n % 4 == 0 && a.m >= 1 && a.n >= 1 && a.k >= 1;
 }
 
-int64_t ring_mfma_partials(int64_t m, int64_t n) {
-  return ((m + kT - 1) / kT) * ((n + kT - 1) / kT);
+int32_t ring_mfma_splits(const RingArgs& a) {
+  if (a.type != EL_F64 && a.arith != AR_BF16X3 && big_tiles(a.m, a.n)) return 1;
+  return pick_splits(tiles_of(a.m, a.n, kT), (a.k + kBK - 1) / kBK);
 }
 
 int64_t ring_mfma_partials_for(const RingArgs& a) {
-  if (a.type != EL_F64 && a.arith != AR_BF16X3 && a.m >= kBT && a.n >= kBT)
-    return ((a.m + kBT - 1) / kBT) * ((a.n + kBT - 1) / kBT);
-  return ring_mfma_partials(a.m, a.n);
+  if (a.type != EL_F64 && a.arith != AR_BF16X3 && big_tiles(a.m, a.n))
+    return tiles_of(a.m, a.n, kBT);
+  return tiles_of(a.m, a.n, kT) * ring_mfma_splits(a);
 }
 
-hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** kname) {
-  const int64_t tiles = ring_mfma_partials(a.m, a.n);
-  if (tiles > INT_MAX) return hipErrorInvalidValue;
-  const dim3 grid(static_cast<uint32_t>(tiles)), block(kThreads);
+hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** kname,
+                            int64_t* n_partials, int32_t* c_slices) {
+  const bool dot = a.dot_with != nullptr;
+  if (a.w_slices < 1 || (dot && a.partials == nullptr) || (!dot && a.c_out == nullptr))
+    return hipErrorInvalidValue;
+  if (a.type != EL_F64 && a.arith != AR_BF16X3 && big_tiles(a.m, a.n)) {
+    const int64_t tiles = tiles_of(a.m, a.n, kBT);
+    if (tiles > INT_MAX || (dot && tiles > a.partials_cap)) return hipErrorInvalidValue;
+    *kname = "ring_mfma_f32";
+    *n_partials = dot ? tiles : 0;
+    *c_slices = 1;
+    hipLaunchKernelGGL(ring_mfma_f32_big, dim3(static_cast<uint32_t>(tiles)), dim3(kBThreads), 0,
+                       stream, static_cast<const float*>(a.A), static_cast<const float*>(a.B), a.m,
+                       a.n, a.k, a.sa, a.sb, static_cast<float*>(a.c_out),
+                       static_cast<const float*>(a.dot_with), a.w_slices, a.partials);
+    return hipGetLastError();
+  }
+  const int64_t tiles = tiles_of(a.m, a.n, kT);
+  const int32_t S = capped(ring_mfma_splits(a), tiles, dot, a.c_slices_cap, a.partials_cap);
+  if (tiles * S > INT_MAX || (dot && tiles * S > a.partials_cap) || (!dot && S > a.c_slices_cap))
+    return hipErrorInvalidValue;
+  const dim3 grid(static_cast<uint32_t>(tiles * S)), block(kThreads);
+  *n_partials = dot ? tiles * S : 0;
+  *c_slices = dot ? 0 : S;
   if (a.type == EL_F64) {
     *kname = "ring_mfma_f64";
     hipLaunchKernelGGL((ring_mfma<double>), grid, block, 0, stream,
                        static_cast<const double*>(a.A), static_cast<const double*>(a.B), a.m, a.n,
-                       a.k, a.sa, a.sb, static_cast<double*>(a.c_out),
-                       static_cast<const double*>(a.dot_with), a.partials);
+                       a.k, S, a.sa, a.sb, static_cast<double*>(a.c_out),
+                       static_cast<const double*>(a.dot_with), a.w_slices, a.partials);
   } else if (a.arith == AR_BF16X3) {
-    *kname = "ring_mfma_bf16x3";
-    hipLaunchKernelGGL(ring_mfma_bf16x3, grid, block, 0, stream, static_cast<const float*>(a.A),
-                       static_cast<const float*>(a.B), a.m, a.n, a.k, a.sa, a.sb,
-                       static_cast<float*>(a.c_out), static_cast<const float*>(a.dot_with),
-                       a.partials);
-  } else if (a.m >= kBT && a.n >= kBT) {
-    *kname = "ring_mfma_f32";
-    const int64_t big = ((a.m + kBT - 1) / kBT) * ((a.n + kBT - 1) / kBT);
-    hipLaunchKernelGGL(ring_mfma_f32_big, dim3(static_cast<uint32_t>(big)), dim3(kBThreads), 0,
-                       stream, static_cast<const float*>(a.A), static_cast<const float*>(a.B), a.m,
-                       a.n, a.k, a.sa, a.sb, static_cast<float*>(a.c_out),
-                       static_cast<const float*>(a.dot_with), a.partials);
+    return hipErrorInvalidValue;   // split BF16x3 rings go through launch_ring_bf16x3_nt
   } else {
     *kname = "ring_mfma_f32";
     hipLaunchKernelGGL((ring_mfma<float>), grid, block, 0, stream,
                        static_cast<const float*>(a.A), static_cast<const float*>(a.B), a.m, a.n,
-                       a.k, a.sa, a.sb, static_cast<float*>(a.c_out),
-                       static_cast<const float*>(a.dot_with), a.partials);
+                       a.k, S, a.sa, a.sb, static_cast<float*>(a.c_out),
+                       static_cast<const float*>(a.dot_with), a.w_slices, a.partials);
   }
   return hipGetLastError();
 }
-
-}  // namespace tn
-
-namespace tn {
 
 int64_t split_k_padded(int64_t k) { return (k + kBK16 - 1) / kBK16 * kBK16; }
 
@@ -753,25 +747,42 @@ hipError_t launch_split_transpose(const float* T, int64_t kd, int64_t md, const 
   return hipGetLastError();
 }
 
-int64_t ring_bf16x3_nt_partials(int64_t m, int64_t n) {
-  if (m >= kBT && n >= kBT) return ((m + kBT - 1) / kBT) * ((n + kBT - 1) / kBT);
-  return ring_mfma_partials(m, n);
+int32_t ring_bf16x3_nt_splits(int64_t m, int64_t n, int64_t kp) {
+  if (big_tiles(m, n)) return 1;
+  return pick_splits(tiles_of(m, n, kT), (kp + kBK16 - 1) / kBK16);
 }
 
-hipError_t launch_ring_bf16x3_nt(const uint16_t* Ah, const uint16_t* Al, const uint16_t* Bh,
-                                 const uint16_t* Bl, int64_t m, int64_t n, int64_t kp, float* c_out,
-                                 const float* dot_with, double* partials, hipStream_t stream) {
-  if (m >= kBT && n >= kBT) {
-    const int64_t tiles = ring_bf16x3_nt_partials(m, n);
-    if (tiles > INT_MAX) return hipErrorInvalidValue;
+int64_t ring_bf16x3_nt_partials(int64_t m, int64_t n, int64_t kp) {
+  if (big_tiles(m, n)) return tiles_of(m, n, kBT);
+  return tiles_of(m, n, kT) * ring_bf16x3_nt_splits(m, n, kp);
+}
+
+hipError_t launch_ring_bf16x3_nt(const NtArgs& a, hipStream_t stream, int64_t* n_partials,
+                                 int32_t* c_slices) {
+  const bool dot = a.dot_with != nullptr;
+  if (a.w_slices < 1 || (dot && a.partials == nullptr) || (!dot && a.c_out == nullptr) ||
+      a.kp % kBK16 != 0)
+    return hipErrorInvalidValue;
+  if (big_tiles(a.m, a.n)) {
+    const int64_t tiles = tiles_of(a.m, a.n, kBT);
+    if (tiles > INT_MAX || (dot && tiles > a.partials_cap)) return hipErrorInvalidValue;
+    *n_partials = dot ? tiles : 0;
+    *c_slices = 1;
     hipLaunchKernelGGL(ring_bf16x3_nt_big, dim3(static_cast<uint32_t>(tiles)), dim3(kBThreads), 0,
-                       stream, Ah, Al, Bh, Bl, m, n, kp, c_out, dot_with, partials);
+                       stream, a.Ah, a.Al, a.Bh, a.Bl, a.m, a.n, a.kp, a.c_out, a.dot_with,
+                       a.w_slices, a.partials);
     return hipGetLastError();
   }
-  const int64_t tiles = ring_mfma_partials(m, n);
-  if (tiles > INT_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(ring_bf16x3_nt, dim3(static_cast<uint32_t>(tiles)), dim3(kThreads), 0, stream,
-                     Ah, Al, Bh, Bl, m, n, kp, c_out, dot_with, partials);
+  const int64_t tiles = tiles_of(a.m, a.n, kT);
+  const int32_t S =
+      capped(ring_bf16x3_nt_splits(a.m, a.n, a.kp), tiles, dot, a.c_slices_cap, a.partials_cap);
+  if (tiles * S > INT_MAX || (dot && tiles * S > a.partials_cap) || (!dot && S > a.c_slices_cap))
+    return hipErrorInvalidValue;
+  *n_partials = dot ? tiles * S : 0;
+  *c_slices = dot ? 0 : S;
+  hipLaunchKernelGGL(ring_bf16x3_nt, dim3(static_cast<uint32_t>(tiles * S)), dim3(kThreads), 0,
+                     stream, a.Ah, a.Al, a.Bh, a.Bl, a.m, a.n, a.kp, S, a.c_out, a.dot_with,
+                     a.w_slices, a.partials);
   return hipGetLastError();
 }
 

@@ -92,3 +92,19 @@ def test_batch_workspace_host_only():
     with pytest.raises(tn.TnError) as e:
         tn.tn_batch_workspace([tn.tn_plan_grid(4, 4, 2, order=tn.TN_ORDER_QUADRANT)], "f32")
     assert e.value.status == tn.TN_EINVAL
+
+
+def test_ring_split_slices_host_only():
+    # Split-K of the ring products (1024 x 1024 output at D = 4 on 10 x 10 has
+    # 64 tiles of 128 x 128: eight k ranges fill 512 workgroups); the
+    # workspace holds that many slices of the stored product X.  A 12 x 12
+    # ring has 1024 tiles (FP64) or 256 of 256 x 256 (FP32) and is not split.
+    cases = {(10, 10): 8, (9, 7): 8, (8, 8): 2, (7, 9): 2, (12, 12): 1, (13, 13): 1}
+    for (r, c), s in cases.items():
+        info = tn.tn_plan_grid(r, c, 4, order=tn.TN_ORDER_QUADRANT).info()
+        assert info["ring_slices"] == [s, s, s], (r, c, info["ring_slices"])
+    one = tn.tn_plan_grid(10, 10, 4, order=tn.TN_ORDER_QUADRANT).info()
+    assert one["workspace_bytes"][0] >= 8 * 1024 * 1024 * 8
+    # no ring: sweeps; no MFMA ring: D = 3 gives m = 243
+    assert tn.tn_plan_grid(10, 10, 4).info()["ring_slices"] == [0, 0, 0]
+    assert tn.tn_plan_grid(10, 10, 3, order=tn.TN_ORDER_QUADRANT).info()["ring_slices"] == [1, 1, 1]
