@@ -274,33 +274,43 @@ __global__ __launch_bounds__(kBlock) void ring_generic(
 __global__ __launch_bounds__(kBlock) void finalize_kernel(DevState* state, const double* scalar,
                                                           const double* partials, int64_t np) {
   __shared__ double red[kBlock];
+  __shared__ int64_t red_e[kBlock];
+  __shared__ int32_t red_bad[kBlock];
+  const int32_t* slot_exp = reinterpret_cast<const int32_t*>(state + 1);
+  const int32_t* site_exp = slot_exp + state->n_slots;
+  const int32_t* site_bad = site_exp + state->n_steps;
+  // every thread takes a strided share of the partials, rescale slots and
+  // step exponents; the double sums keep one fixed order (strided, then a tree)
   double s = 0.0;
   if (partials) {
     for (int64_t i = threadIdx.x; i < np; i += blockDim.x) s += partials[i];
   }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int st = kBlock / 2; st > 0; st >>= 1) {
-    if (static_cast<int>(threadIdx.x) < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  const double mval = partials ? red[0] : *scalar;
-  const int32_t* slot_exp = reinterpret_cast<const int32_t*>(state + 1);
-  const int32_t* site_exp = slot_exp + state->n_slots;
-  const int32_t* site_bad = site_exp + state->n_steps;
   int64_t E = 0;
-  int bad = state->flags & 1;
-  for (int i = 0; i < state->n_slots; ++i) {
+  int32_t bad = 0;
+  for (int i = threadIdx.x; i < state->n_slots; i += blockDim.x) {
     const int32_t e = slot_exp[i];
     if (e == kExpBad) bad = 1;
     else if (e != kExpZero) E += e;
   }
-  for (int i = 0; i < state->n_steps; ++i) {
+  for (int i = threadIdx.x; i < state->n_steps; i += blockDim.x) {
     E += site_exp[i];
     bad |= site_bad[i];
   }
-  const tn_result r = dev::assemble_result(mval, E, bad);
+  red[threadIdx.x] = s;
+  red_e[threadIdx.x] = E;
+  red_bad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (static_cast<int>(threadIdx.x) < st) {
+      red[threadIdx.x] += red[threadIdx.x + st];
+      red_e[threadIdx.x] += red_e[threadIdx.x + st];
+      red_bad[threadIdx.x] |= red_bad[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double mval = partials ? red[0] : *scalar;
+  const tn_result r = dev::assemble_result(mval, red_e[0], red_bad[0] | (state->flags & 1));
   state->result = r;
 }
 
