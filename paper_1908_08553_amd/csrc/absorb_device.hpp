@@ -90,7 +90,10 @@ __device__ inline void reduce_and_publish(T mx, int bad, int32_t* max_slot, int3
     m = fmax(m, sm[0]);
     bad |= sb[0];
     const int32_t e = bad ? kExpBad : exp_of_d(m);
-    if (e != kExpZero) atomicMax(max_slot, e);
+    // the slot only grows during a launch: skip the atomic (all workgroups
+    // of a launch would queue on one cache line) when it cannot raise it
+    if (e != kExpZero && e > __hip_atomic_load(max_slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(max_slot, e);
     if (bad) atomicOr(flags, 1);
   }
 }
