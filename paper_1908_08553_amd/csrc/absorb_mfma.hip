@@ -293,14 +293,25 @@ __global__ __launch_bounds__(kThreads) void absorb_pair(PairGroup g) {
         }
       }
     }
-    T* dst = out + (4 * p + w) * 16 * P + static_cast<int64_t>(c) * P + q0;
+    // results go back through the wave's own LDS rows (every wave has read
+    // its s2 operands once the barrier passes) so that each 16 lanes store
+    // one whole 64-fibre output row
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int f = F64 ? (4 * gg + 16 * r) : (16 * gg + 4 * r);
       const V4 v = {acc[0][r], acc[1][r], acc[2][r], acc[3][r]};
-      *reinterpret_cast<V4*>(dst + f) = v;
+      *reinterpret_cast<V4*>(&buf[w][c][f]) = v;
 #pragma unroll
       for (int m = 0; m < 4; ++m) track(v[m], mx, bad);
+    }
+    __syncthreads();
+    T* dst = out + (4 * p + w) * 16 * P + q0 + 4 * c;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = 4 * i + gg;
+      *reinterpret_cast<V4*>(dst + static_cast<int64_t>(row) * P) =
+          *reinterpret_cast<const V4*>(&buf[w][row][4 * c]);
     }
   }
   if (st.max_slot) reduce_and_publish(mx, bad, st.max_slot, g.flags);

@@ -57,15 +57,22 @@ __device__ inline int32_t shift_of(const int32_t* slot) {
   return (e == kExpZero || e == kExpBad) ? 0 : e;
 }
 
-// Tile index id -> (tile row, tile col) with XCD-aware renumbering.
+// Tile index id -> (tile row, tile col).  Workgroup id runs on XCD id % 8, so
+// t = (id % 8) * per + id / 8 gives every XCD a contiguous range of t; t is
+// then read in groups of kGroupRows tile rows walked column by column, so the
+// workgroups resident on one XCD at a time form a near-square block of tiles
+// and share their A and B panels in that XCD's L2.
+constexpr uint32_t kGroupRows = 8;
 __device__ inline void tile_of(uint32_t& tm, uint32_t& tn, uint32_t ntm, uint32_t ntn,
                                uint32_t id) {
   const uint32_t total = ntm * ntn;
   const uint32_t per = (total + kXcd - 1) / kXcd;
   uint32_t t = (id % kXcd) * per + id / kXcd;
   if (total % kXcd != 0) t = id;   // keep it a bijection when tiles do not split evenly
-  tm = t / ntn;
-  tn = t - tm * ntn;
+  const uint32_t g = t / (kGroupRows * ntn), r = t - g * kGroupRows * ntn;
+  const uint32_t rows = min(kGroupRows, ntm - g * kGroupRows);
+  tn = r / rows;
+  tm = g * kGroupRows + (r - tn * rows);
 }
 
 // k range [b, e) of split s out of S, in whole slices of bk.
