@@ -335,7 +335,7 @@ def main():
             leg = run_leg(tn, torch, r, c, D, kind, 0, order, prec, max(3, args.steps // 4),
                           1, profile=True)
             wl = ({0: "sweep", 1: "quadrant"}.get(order) if (r, c, D, kind) == (12, 12, 4, "uniform")
-                  and prec == "f32" else None)
+                  else None)
             leg["roofline"] = roofline(leg["kernels"], prec, wl)
             legs[name] = leg
             log(f"{name}: {leg['ms']:.3f} ms, {leg['gflops']:.1f} GFLOP/s, "
