@@ -182,3 +182,21 @@ def batch_mix(n: int, base_seed: int, sides=(4, 8), dims=(2, 3, 4)):
         D = int(master.choice(dims))
         out.append((r, c, D, uniform(r, c, D, base_seed + 1 + i)))
     return out
+
+
+# ------------------------------------------------------------------ PEPS
+def peps(rows: int, cols: int, chi: int, seed: int, d: int = 2, kind: str = "normal"):
+    """Real PEPS site tensors: the spin index first (dimension d), then the
+    bond legs in canonical order with bond dimension chi (rank 5 in the bulk,
+    4 on edges, 3 at corners).  Entries i.i.d. N(0, 1) (``kind="normal"``) or
+    uniform[0, 1) (``kind="uniform"``) from ``default_rng(seed)``, row-major."""
+    rng = np.random.default_rng(seed)
+    draw = rng.standard_normal if kind == "normal" else rng.random
+    return [draw((d,) + s) for s in shapes(rows, cols, chi)]
+
+
+def spin_half():
+    """Spin-1/2 operators (S^x, S^z) in the basis (up, down), S = sigma / 2."""
+    sx = np.array([[0.0, 0.5], [0.5, 0.0]])
+    sz = np.array([[0.5, 0.0], [0.0, -0.5]])
+    return sx, sz

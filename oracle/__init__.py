@@ -23,6 +23,9 @@ Modules (each function cites the passage of the paper it follows):
                        experiments do), with exact power-of-two rescaling.
 * ``closed_forms`` -- product-state, all-ones and Ising special cases.
 * ``invariants``   -- transformations with a known effect on Z.
+* ``peps``         -- norm and expectation-value networks of a real PEPS
+                       (paper §3 and §5): double-layer sites, the observable
+                       set m^x, m^z, c_ij, and brute-force amplitudes.
 
 Parity status of every function is stated in its docstring; nothing here is
 "parity unpinned": each is pinned by brute force, a closed form, a textbook

@@ -78,3 +78,22 @@ def test_split_ring_repeatable(tn, prec):
     a, _, _ = run(tn, s, 10, 10, prec)
     b, _, _ = run(tn, s, 10, 10, prec)
     assert (a.mantissa, a.exp2_sum, a.sign) == (b.mantissa, b.exp2_sum, b.sign)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_split_ring_with_ragged_tiles(tn, prec):
+    # 10x10, quadrant 5,5, mixed bond dimensions: the ring output is m = 4*4*3*4*1 = 192
+    # (one full and one half 128-row tile) by n = 4*4*3*4*4 = 768, over k = 4^5 = 1024:
+    # 12 tiles, so both products run in 8 k ranges with ragged edge tiles
+    import numpy as np
+    rows, cols = 10, 10
+    h = np.full((rows, cols - 1), 4)
+    v = np.tile(np.array([4, 4, 3, 4, 1, 4, 4, 3, 4, 4]), (rows - 1, 1))
+    s = li.uniform(rows, cols, 0, 5, hdim=h, vdim=v)
+    ref = C.contract_grid(s, rows, cols, P.QUADRANT, 5, 5)
+    plan = tn.tn_plan_grid(rows, cols, 1, h, v, P.QUADRANT, 5, 5)
+    assert plan.info()["ring_slices"][PREC[prec]] == 8
+    print(f"[gpu] ring split ragged 10x10 prec={prec}", flush=True)
+    tn.tn_set_option(tn.TN_OPT_KERNEL_IMPL, 0)
+    got = tn.contract_grid(plan, tn.device_sites(s), prec)
+    close(got, ref, prec)
