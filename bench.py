@@ -204,6 +204,33 @@ def batch_leg(tn, torch, n=512, seed=2024, reps=20):
             "all_finite": all(r.status == 0 for r in res)}
 
 
+def peps_leg(tn, torch, rows=6, cols=6, chi=2, seed=3, reps=10):
+    """One observable evaluation of a real rows x cols PEPS (bond dimension chi,
+    spin 1/2, N(0,1) tensors): the norm, m^x and m^z at every site and c_ij on
+    every nearest-neighbour pair, 1 + 2 L^2 + 2 L (L-1) networks of bond
+    dimension chi^2, FP64: double-layer sites in one call, all networks in one
+    batch launch, ratios in the library."""
+    import lattice_inputs as li
+    from paper_1908_08553_amd.peps import ObservableSet
+    sx, sz = (torch.as_tensor(m, dtype=torch.float64).cuda() for m in li.spin_half())
+    peps = [torch.as_tensor(a, dtype=torch.float64).cuda() for a in li.peps(rows, cols, chi, seed)]
+    obs = ObservableSet(rows, cols, chi, precision="f64")
+    out = obs.run(peps, sx, sz)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = obs.run(peps, sx, sz)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    flops = obs.count * obs.plan.info()["flops"]
+    obs.close()
+    return {"rows": rows, "cols": cols, "chi": chi, "precision": "f64", "networks": obs.count,
+            "ms_per_evaluation": 1e3 * dt, "networks_per_s": obs.count / dt,
+            "gflops": flops / dt / 1e9, "norm_log_abs": out["results"][0].log_abs,
+            "mean_mx": sum(out["mx"]) / len(out["mx"]),
+            "all_finite": all(r.status == 0 for r in out["results"])}
+
+
 def served_leg(tn, torch, n=240, seed=5):
     """Poisson stream: L ~ U{4..13} square Ising lattices, D ~ U{2,4} (D=4 is
     the two-replica network), tag ~ U{FP64, BF16x3}, beta*J ~ U[0.1, 0.8],
@@ -347,6 +374,9 @@ def main():
         if not args.no_batch:
             legs["batch512_f32"] = batch_leg(tn, torch)
             log(f"batch: {legs['batch512_f32']['contractions_per_s']:.0f} contractions/s")
+        if not args.no_batch:
+            legs["peps6_observables_f64"] = peps_leg(tn, torch)
+            log(f"peps observables: {json.dumps(legs['peps6_observables_f64'])}")
         if not args.no_serve:
             legs["served"] = served_leg(tn, torch)
             log(f"served: {json.dumps(legs['served'])}")

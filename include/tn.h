@@ -201,6 +201,47 @@ tn_status tn_contract_batch(const tn_plan* const* plans, const double* const* co
                             int32_t n, int32_t precision, void* workspace, size_t ws_bytes,
                             void* hip_stream, tn_result* outs);
 
+/* ------------------------------------------------------------ PEPS observables
+ * Paper §3: a state's amplitudes A({s}) are a planar network of rank-5 site
+ * tensors (four bonds and the spin index; edges and corners have fewer
+ * bonds); its norm is the sum over all spin configurations of A* A, and
+ * m^x_k = <S^x_k>, m^z_k = <S^z_k>, c_ij = <S^z_i S^z_j> - <S^z_i><S^z_j>,
+ * each <O> = <Psi|O|Psi> / <Psi|Psi>.  §5: each of these is one contraction
+ * of O|Psi> against <Psi| along every spin index, L^2 (m^x) and 2L(L-1)
+ * (c_ij, nearest neighbours) networks on an L x L lattice.  Tensors are real.
+ *
+ * tn_double_layer builds, for each site j, the single-layer tensor of that
+ * contraction:
+ *   E[(a_1 a_1')..(a_r a_r')] = sum_{s,s'} A[s][a_1..a_r] O[s'][s] A[s'][a_1'..a_r']
+ * with the paired bond index a_k * dims[k] + a_k' (ket-major), so a lattice
+ * of such sites is a planar network with bond dimensions dims^2 that
+ * tn_contract_grid / the batch calls contract.  All pointers are device
+ * memory the caller owns; the work is enqueued on hip_stream (asynchronous:
+ * synchronise the stream before reading E).  Errors: TN_EINVAL (NULL A or E,
+ * d outside 1..64, rank outside 0..4, a dimension < 1, more than 2^30
+ * entries in A), TN_EDEVICE.                                                */
+typedef struct {
+  const double* A;   /* [d][dims[0]]..[dims[rank-1]], C-order                  */
+  const double* op;  /* [d][d] operator O[s'][s], or NULL for the identity     */
+  double* E;         /* [dims[0]^2]..[dims[rank-1]^2], C-order (output)        */
+  int32_t d;         /* spin dimension                                         */
+  int32_t rank;      /* bond legs in canonical order (left, up, right, down)   */
+  int32_t dims[4];   /* bond dimensions, the first `rank` are used             */
+} tn_double_layer_site;
+
+tn_status tn_double_layer(const tn_double_layer_site* sites, int32_t n, void* hip_stream);
+
+/* Observables of a rows x cols state from the results of its networks, in
+ * this order: the norm (no operator), S^x at each site (row-major), S^z at
+ * each site, S^z S^z on each nearest-neighbour pair (horizontal pairs row by
+ * row, then vertical pairs row by row): 1 + 2 rows cols + rows (cols - 1) +
+ * (rows - 1) cols results.  Writes mx[rows cols], mz[rows cols] and
+ * czz[pairs] (host arrays) from exact ratios of the results' mantissas and
+ * exponents.  Errors: TN_EINVAL (NULL, rows or cols < 1, zero norm),
+ * TN_ENONFINITE (a result with a non-finite status).                        */
+tn_status tn_observables(const tn_result* results, int32_t rows, int32_t cols, double* mx,
+                         double* mz, double* czz);
+
 /* ------------------------------------------------------------ serving
  * A request loop that admits contractions of different sizes and precisions
  * as they arrive.  A scheduler thread admits queued requests first-come-

@@ -88,6 +88,20 @@ lib.tn_contract_grid.argtypes = [_P, C.POINTER(C.c_void_p), C.c_int32, C.c_int32
                                  C.c_size_t, _P, C.POINTER(tn_result)]
 
 
+
+class tn_double_layer_site(C.Structure):
+    _fields_ = [("A", C.c_void_p), ("op", C.c_void_p), ("E", C.c_void_p), ("d", C.c_int32),
+                ("rank", C.c_int32), ("dims", C.c_int32 * 4)]
+
+
+lib.tn_double_layer.restype = C.c_int32
+lib.tn_double_layer.argtypes = [C.POINTER(tn_double_layer_site), C.c_int32, _P]
+lib.tn_observables.restype = C.c_int32
+lib.tn_observables.argtypes = [C.POINTER(tn_result), C.c_int32, C.c_int32,
+                               C.POINTER(C.c_double), C.POINTER(C.c_double),
+                               C.POINTER(C.c_double)]
+
+
 class TnError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"tn status {status}: {msg}")
@@ -350,6 +364,45 @@ def tn_contract_batch(plans, site_lists, precision="f32", workspace=None, stream
         _check(status)
     del keep
     return [Result.from_c(o) for o in outs]
+
+
+# ------------------------------------------------------------------ PEPS
+def tn_double_layer(pairs, stream=None):
+    """pairs: (A, op, E) device float64 tensors (op may be None): A [d][dims...],
+    op [d][d], E [dims^2...] preallocated.  One asynchronous library call on
+    `stream` (default: torch's current stream)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    arr = (tn_double_layer_site * max(len(pairs), 1))()
+    for i, (A, op, E) in enumerate(pairs):
+        for t in (A, E) + ((op,) if op is not None else ()):
+            if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("double-layer tensors must be contiguous float64 device tensors")
+        dims = list(A.shape[1:])
+        if len(dims) > 4 or tuple(E.shape) != tuple(n * n for n in dims):
+            raise ValueError("E must have shape dims^2 of A's bond legs (at most 4)")
+        arr[i] = tn_double_layer_site(A.data_ptr(), op.data_ptr() if op is not None else None,
+                                      E.data_ptr(), A.shape[0], len(dims),
+                                      (C.c_int32 * 4)(*(dims + [1] * (4 - len(dims)))))
+    _check(lib.tn_double_layer(arr, len(pairs), C.c_void_p(stream.cuda_stream)))
+
+
+def tn_observables(results, rows: int, cols: int):
+    """(mx, mz, czz) lists from the results of a state's networks in the order
+    tn.h documents (norm, S^x per site, S^z per site, S^z S^z per pair)."""
+    n = rows * cols
+    pairs = rows * (cols - 1) + (rows - 1) * cols
+    if len(results) != 1 + 2 * n + pairs:
+        raise ValueError("need 1 + 2 rows cols + pairs results")
+    res = (tn_result * len(results))()
+    for i, r in enumerate(results):
+        res[i] = tn_result(r.sign, r.status, r.log_abs, r.value, r.mantissa, r.exp2_sum)
+    mx = (C.c_double * n)()
+    mz = (C.c_double * n)()
+    czz = (C.c_double * max(pairs, 1))()
+    _check(lib.tn_observables(res, rows, cols, mx, mz, czz))
+    return list(mx), list(mz), list(czz)[:pairs]
 
 
 # ------------------------------------------------------------------ serving

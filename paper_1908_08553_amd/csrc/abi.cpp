@@ -2,6 +2,7 @@
 // catches everything: no exception crosses the ABI.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -327,6 +328,78 @@ tn_status tn_profile_read(tn_kernel_stat* out, int32_t cap, int32_t* n) {
     return TN_OK;
   } catch (...) {
     return fail(TN_EINVAL, "tn_profile_read failed");
+  }
+}
+
+tn_status tn_double_layer(const tn_double_layer_site* sites, int32_t n, void* hip_stream) {
+  try {
+    if (n < 0 || (n > 0 && !sites)) return fail(TN_EINVAL, "null argument");
+    std::vector<tn::DoubleLayerSite> v(static_cast<size_t>(n));
+    for (int32_t i = 0; i < n; ++i) {
+      const tn_double_layer_site& x = sites[i];
+      tn::DoubleLayerSite& y = v[static_cast<size_t>(i)];
+      y.A = x.A;
+      y.op = x.op;
+      y.E = x.E;
+      y.d = x.d;
+      y.rank = x.rank;
+      int64_t m = 1;
+      for (int k = 0; k < 4; ++k) {
+        y.dims[k] = k < x.rank ? x.dims[k] : 1;
+        if (k < x.rank && (x.dims[k] < 1 || m > (int64_t{1} << 30)))
+          return fail(TN_EINVAL, "bad double-layer site dimensions");
+        if (k < x.rank) m *= x.dims[k];
+      }
+      y.n_in = m;
+      y.n_out = m * m;
+      if (x.rank < 0 || x.rank > 4 || !tn::double_layer_ok(y))
+        return fail(TN_EINVAL, "bad double-layer site " + std::to_string(i));
+    }
+    if (n == 0) return TN_OK;
+    const hipError_t e =
+        tn::launch_double_layer(v.data(), n, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(TN_EDEVICE, hipGetErrorString(e));
+    return TN_OK;
+  } catch (...) {
+    return fail(TN_EINVAL, "tn_double_layer failed");
+  }
+}
+
+tn_status tn_observables(const tn_result* results, int32_t rows, int32_t cols, double* mx,
+                         double* mz, double* czz) {
+  try {
+    if (!results || !mx || !mz || !czz || rows < 1 || cols < 1)
+      return fail(TN_EINVAL, "null argument or empty lattice");
+    const int64_t n = static_cast<int64_t>(rows) * cols;
+    const int64_t pairs = static_cast<int64_t>(rows) * (cols - 1) + static_cast<int64_t>(rows - 1) * cols;
+    const int64_t total = 1 + 2 * n + pairs;
+    for (int64_t i = 0; i < total; ++i)
+      if (results[i].status != TN_OK) return fail(TN_ENONFINITE, "non-finite network result");
+    const tn_result& norm = results[0];
+    if (norm.sign == 0) return fail(TN_EINVAL, "zero norm");
+    // <O> = Z_O / Z: mantissas in [0.5, 1) carry the sign, exponents are exact
+    auto ratio = [&](const tn_result& r) {
+      if (r.sign == 0) return 0.0;
+      return std::ldexp(r.mantissa / norm.mantissa, static_cast<int>(r.exp2_sum - norm.exp2_sum));
+    };
+    for (int64_t k = 0; k < n; ++k) {
+      mx[k] = ratio(results[1 + k]);
+      mz[k] = ratio(results[1 + n + k]);
+    }
+    int64_t b = 0;
+    for (int32_t r = 0; r < rows; ++r)
+      for (int32_t c = 0; c + 1 < cols; ++c, ++b) {
+        const int64_t i = static_cast<int64_t>(r) * cols + c;
+        czz[b] = ratio(results[1 + 2 * n + b]) - mz[i] * mz[i + 1];
+      }
+    for (int32_t r = 0; r + 1 < rows; ++r)
+      for (int32_t c = 0; c < cols; ++c, ++b) {
+        const int64_t i = static_cast<int64_t>(r) * cols + c;
+        czz[b] = ratio(results[1 + 2 * n + b]) - mz[i] * mz[i + cols];
+      }
+    return TN_OK;
+  } catch (...) {
+    return fail(TN_EINVAL, "tn_observables failed");
   }
 }
 

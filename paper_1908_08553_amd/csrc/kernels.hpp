@@ -170,6 +170,20 @@ int64_t ring_mfma_partials_for(const RingArgs& a);
 hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** kname,
                             int64_t* n_partials, int32_t* c_slices);
 
+// Double-layer site of a real PEPS tensor (peps.hip): A [d][dims...] and
+// E [dims_0^2]..[dims_{rank-1}^2] on the device, op [d][d] or null
+// (identity); n_in = prod dims, n_out = n_in^2.
+struct DoubleLayerSite {
+  const double* A;
+  const double* op;
+  double* E;
+  int64_t n_in, n_out;
+  int32_t d, rank;
+  int32_t dims[4];
+};
+bool double_layer_ok(const DoubleLayerSite& s);
+hipError_t launch_double_layer(const DoubleLayerSite* sites, int32_t n, hipStream_t stream);
+
 // Writes state->result from the final scalar (or the sum of `n_partials`
 // partials), the site exponents and the rescale slots.
 hipError_t launch_finalize(DevState* state, const double* scalar, const float* scalar_f,
