@@ -88,7 +88,6 @@ lib.tn_contract_grid.argtypes = [_P, C.POINTER(C.c_void_p), C.c_int32, C.c_int32
                                  C.c_size_t, _P, C.POINTER(tn_result)]
 
 
-
 class tn_double_layer_site(C.Structure):
     _fields_ = [("A", C.c_void_p), ("op", C.c_void_p), ("E", C.c_void_p), ("d", C.c_int32),
                 ("rank", C.c_int32), ("dims", C.c_int32 * 4)]
@@ -325,11 +324,17 @@ class Batch:
                                    self.workspace.numel(), C.byref(h)))
         self._h = h
 
-    def run(self, site_lists, stream=None):
+    def prepare(self, site_lists):
+        """Pointer tables of `site_lists` for repeated runs over the same tensors."""
+        if len(site_lists) != len(self.plans):
+            raise ValueError("one site list per plan")
+        return _site_table(site_lists) + (site_lists,)
+
+    def run(self, site_lists, stream=None, prepared=None):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
-        table, keep = _site_table(site_lists)
+        table, keep = prepared[:2] if prepared is not None else _site_table(site_lists)
         outs = (tn_result * len(self.plans))()
         status = lib.tn_batch_run(self._h, table, C.c_void_p(stream.cuda_stream), outs)
         if status not in (TN_OK, TN_ENONFINITE):
@@ -367,13 +372,10 @@ def tn_contract_batch(plans, site_lists, precision="f32", workspace=None, stream
 
 
 # ------------------------------------------------------------------ PEPS
-def tn_double_layer(pairs, stream=None):
-    """pairs: (A, op, E) device float64 tensors (op may be None): A [d][dims...],
-    op [d][d], E [dims^2...] preallocated.  One asynchronous library call on
-    `stream` (default: torch's current stream)."""
+def tn_double_layer_prepare(pairs):
+    """Checked descriptor array of (A, op, E) triples for repeated calls over
+    the same tensors (it keeps them alive)."""
     import torch
-    if stream is None:
-        stream = torch.cuda.current_stream()
     arr = (tn_double_layer_site * max(len(pairs), 1))()
     for i, (A, op, E) in enumerate(pairs):
         for t in (A, E) + ((op,) if op is not None else ()):
@@ -385,7 +387,18 @@ def tn_double_layer(pairs, stream=None):
         arr[i] = tn_double_layer_site(A.data_ptr(), op.data_ptr() if op is not None else None,
                                       E.data_ptr(), A.shape[0], len(dims),
                                       (C.c_int32 * 4)(*(dims + [1] * (4 - len(dims)))))
-    _check(lib.tn_double_layer(arr, len(pairs), C.c_void_p(stream.cuda_stream)))
+    return arr, len(pairs), list(pairs)
+
+
+def tn_double_layer(pairs, stream=None, prepared=None):
+    """pairs: (A, op, E) device float64 tensors (op may be None): A [d][dims...],
+    op [d][d], E [dims^2...] preallocated.  One asynchronous library call on
+    `stream` (default: torch's current stream)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    arr, n, _ = prepared if prepared is not None else tn_double_layer_prepare(pairs)
+    _check(lib.tn_double_layer(arr, n, C.c_void_p(stream.cuda_stream)))
 
 
 def tn_observables(results, rows: int, cols: int):

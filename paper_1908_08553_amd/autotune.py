@@ -69,8 +69,9 @@ def tune_batch(plans, site_lists, precision="f32", candidates=CANDIDATES, reps=5
     ref = None
     for threads in candidates:
         b = N.Batch(plans, precision, threads)
+        prep = b.prepare(site_lists)
         for _ in range(warmup):
-            res = b.run(site_lists)
+            res = b.run(None, prepared=prep)
         if ref is None:
             ref = [(r.mantissa, r.exp2_sum) for r in res]
         elif [(r.mantissa, r.exp2_sum) for r in res] != ref:
@@ -80,7 +81,7 @@ def tune_batch(plans, site_lists, precision="f32", candidates=CANDIDATES, reps=5
             a = torch.cuda.Event(enable_timing=True)
             z = torch.cuda.Event(enable_timing=True)
             a.record()
-            b.run(site_lists)
+            b.run(None, prepared=prep)
             z.record()
             torch.cuda.synchronize()
             ms.append(a.elapsed_time(z))

@@ -11,8 +11,8 @@ and lists which site tensor each network uses.
 """
 from __future__ import annotations
 
-from ._native import (TN_ORDER_SWEEP_AUTO, Batch, tn_double_layer, tn_observables,
-                      tn_plan_grid)
+from ._native import (TN_ORDER_SWEEP_AUTO, Batch, tn_double_layer, tn_double_layer_prepare,
+                      tn_observables, tn_plan_grid)
 
 
 def pairs(rows: int, cols: int):
@@ -36,6 +36,7 @@ class ObservableSet:
         self.pairs = pairs(rows, cols)
         self.plan = tn_plan_grid(rows, cols, chi * chi, order=TN_ORDER_SWEEP_AUTO)
         self.count = 1 + 2 * self.n + len(self.pairs)
+        self.precision, self.device = precision, device
         self.batch = Batch([self.plan] * self.count, precision=precision, threads=threads,
                            device=device)
         self.E = [[None] * self.n for _ in range(3)]   # norm, S^x, S^z sites
@@ -45,6 +46,7 @@ class ObservableSet:
                 for k in range(3):
                     self.E[k][r * cols + c] = torch.empty((chi * chi,) * legs,
                                                           dtype=torch.float64, device=device)
+        self.table = self.batch.prepare(self.networks())   # the buffers never move
 
     def networks(self):
         """Site lists of every network, in the documented order."""
@@ -62,14 +64,31 @@ class ObservableSet:
         """peps: rows*cols contiguous float64 device tensors [d][bonds...];
         sx, sz: [d][d] device operators.  Returns the batch results and the
         observables (mx, mz per site, czz per pair)."""
-        norm, ex, ez = self.E
-        work = []
-        for k, A in enumerate(peps):
-            work += [(A, None, norm[k]), (A, sx, ex[k]), (A, sz, ez[k])]
-        tn_double_layer(work, stream)
-        results = self.batch.run(self.networks(), stream)
+        key = tuple(A.data_ptr() for A in peps) + (sx.data_ptr(), sz.data_ptr())
+        if key != getattr(self, "_dl_key", None):
+            norm, ex, ez = self.E
+            work = []
+            for k, A in enumerate(peps):
+                work += [(A, None, norm[k]), (A, sx, ex[k]), (A, sz, ez[k])]
+            self._dl, self._dl_key = tn_double_layer_prepare(work), key
+        tn_double_layer(None, stream, prepared=self._dl)
+        results = self.batch.run(None, stream, prepared=self.table)
         mx, mz, czz = tn_observables(results, self.rows, self.cols)
         return {"results": results, "mx": mx, "mz": mz, "czz": czz}
+
+    def tune(self, peps, sx, sz, reps: int = 5):
+        """Pick the batch workgroup size with the autotuner on this state's
+        networks (the candidates must agree bit for bit) and rebuild the
+        batch with it; returns the autotuner's report."""
+        from . import autotune
+        self.run(peps, sx, sz)   # builds the double-layer sites the networks point to
+        report = autotune.tune_batch([self.plan] * self.count, self.networks(), self.precision,
+                                     reps=reps)
+        self.batch.close()
+        self.batch = Batch([self.plan] * self.count, precision=self.precision,
+                           threads=report["best"], device=self.device)
+        self.table = self.batch.prepare(self.networks())
+        return report
 
     def close(self):
         self.batch.close()

@@ -97,3 +97,19 @@ def test_observable_set_repeatable(tn):
     b = obs.run(peps, dev(SX), dev(SZ))
     obs.close()
     assert a["mx"] == b["mx"] and a["mz"] == b["mz"] and a["czz"] == b["czz"]
+
+
+def test_observable_set_tuned_matches_default(tn, tmp_path, monkeypatch):
+    # the autotuner times 256/512/1024-thread workgroups on these networks and
+    # raises if any of them changes a result; the tuned batch must then agree
+    # with the default one bit for bit
+    from paper_1908_08553_amd.peps import ObservableSet
+    monkeypatch.setenv("TN_TUNE_CACHE", str(tmp_path / "tune.json"))
+    peps = [dev(A) for A in li.peps(4, 4, 2, 13)]
+    obs = ObservableSet(4, 4, 2, precision="f64")
+    a = obs.run(peps, dev(SX), dev(SZ))
+    report = obs.tune(peps, dev(SX), dev(SZ), reps=2)
+    b = obs.run(peps, dev(SX), dev(SZ))
+    obs.close()
+    assert report["best"] in (256, 512, 1024)
+    assert a["mx"] == b["mx"] and a["mz"] == b["mz"] and a["czz"] == b["czz"]
