@@ -327,6 +327,14 @@ tn_status tn_server_destroy(tn_server* server);
  *                        (GPU_MAX_HW_QUEUES, 4 by default) for good.
  *                        0 (default) = one stream.                          */
 #define TN_OPT_QUADRANT_STREAMS 4
+/*   TN_OPT_CHAIN_STEPS : 1 (default) = with TN_OPT_FUSE_STEPS = 2, runs of
+ *                        2..14 consecutive single steps of a unit whose
+ *                        input and output have at most 16384 entries each
+ *                        (the edge columns, small lattices) run as one
+ *                        launch, one workgroup per unit, with the same
+ *                        per-step arithmetic as one launch per step
+ *                        (bitwise-identical results); 0 = one launch each. */
+#define TN_OPT_CHAIN_STEPS 5
 tn_status tn_set_option(int32_t option, int64_t value);
 
 /* ------------------------------------------------------------ profiling

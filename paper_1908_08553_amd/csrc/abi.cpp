@@ -294,6 +294,11 @@ tn_status tn_set_option(int32_t option, int64_t value) {
     tn::set_absorb_policy(static_cast<int32_t>(value));
     return TN_OK;
   }
+  if (option == TN_OPT_CHAIN_STEPS) {
+    if (value < 0 || value > 1) return fail(TN_EINVAL, "TN_OPT_CHAIN_STEPS must be 0 or 1");
+    tn::set_chain_steps(static_cast<int32_t>(value));
+    return TN_OK;
+  }
   if (option == TN_OPT_QUADRANT_STREAMS) {
     if (value < 0 || value > 1) return fail(TN_EINVAL, "TN_OPT_QUADRANT_STREAMS must be 0 or 1");
     tn::set_quadrant_streams(static_cast<int32_t>(value));

@@ -158,7 +158,99 @@ __global__ __launch_bounds__(THREADS) void batch_kernel(
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// ------------------------------------------------------------------ chains
+// Small consecutive steps of up to four sweep units, one workgroup per unit:
+// the steps' single-launch arithmetic (run_step) with a workgroup barrier
+// between steps instead of a kernel boundary.  A rescale slot the chain
+// measures is kept in registers for the steps after it; other slots were
+// written by earlier launches.
+constexpr int kChainUnits = 4;
+constexpr int kChainThreads = 512;
+
+struct ChainLaunch {
+  ChainUnit u[kChainUnits];
+  StagedArrays st;
+  int32_t* slot_exp;
+  int32_t* flags;
+  int32_t arith;
+};
+
+__global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainLaunch a) {
+  __shared__ double s_max[kChainThreads / 64];
+  __shared__ int s_bad[kChainThreads / 64];
+  const uint32_t wave = threadIdx.x >> 6, nw = kChainThreads / 64;
+  const ChainUnit& c = a.u[blockIdx.x];
+  int cur = c.cur;
+  int32_t known_slot = -1, known_shift = 0;
+  for (int32_t j = 0; j < c.n; ++j) {
+    const ChainStep& x = c.s[j];
+    int32_t shift = 0;
+    if (x.scale_slot >= 0) {
+      if (x.scale_slot == known_slot) {
+        shift = known_shift;
+      } else {
+        const int32_t e = a.slot_exp[x.scale_slot];
+        shift = (e == kExpZero || e == kExpBad) ? 0 : e;
+      }
+    }
+    BStep s;
+    s.pre = x.pre;
+    s.post = x.post;
+    s.s_off = x.s_off;
+    s.K = x.K;
+    s.N = x.N;
+    s.in_f64 = x.in_f64;
+    s.out_f64 = x.out_f64;
+    s.rescale = x.rescale_slot >= 0;
+    s.scale_in = x.scale_slot >= 0;
+    double mx = 0.0;
+    int b = 0;
+    run_step(s, c.buf[cur], c.buf[cur ^ 1], shift, a.arith, a.st, wave, nw, mx, b);
+    if (x.rescale_slot >= 0) {
+      for (int off = 32; off > 0; off >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, off));
+        b |= __shfl_xor(b, off);
+      }
+      if ((threadIdx.x & 63) == 0) { s_max[wave] = mx; s_bad[wave] = b; }
+      __syncthreads();
+      double m = 0.0;
+      int bb = 0;
+      for (uint32_t w = 0; w < nw; ++w) { m = fmax(m, s_max[w]); bb |= s_bad[w]; }
+      const int32_t e = bb ? kExpBad : exp_of_d(m);
+      if (threadIdx.x == 0) {
+        if (e != kExpZero) a.slot_exp[x.rescale_slot] = e;
+        if (bb) atomicOr(a.flags, 1);
+      }
+      known_slot = x.rescale_slot;
+      known_shift = (e == kExpZero || e == kExpBad) ? 0 : e;
+    }
+    __syncthreads();   // the step's output is complete before anyone reads it
+    cur ^= 1;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_chain(const ChainUnit* units, int32_t n, const StagedArrays& st,
+                        int32_t* slot_exp, int32_t* flags, int32_t arith, hipStream_t stream,
+                        const char** kname) {
+  if (n < 1 || n > kChainUnits) return hipErrorInvalidValue;
+  ChainLaunch a;
+  std::memset(&a, 0, sizeof(a));
+  for (int32_t i = 0; i < n; ++i) {
+    if (units[i].n < 1 || units[i].n > kChainMax) return hipErrorInvalidValue;
+    a.u[i] = units[i];
+  }
+  a.st = st;
+  a.slot_exp = slot_exp;
+  a.flags = flags;
+  a.arith = arith;
+  const bool f64 = units[0].s[0].out_f64 && units[0].s[0].in_f64;
+  *kname = f64 ? "absorb_chain_f64" : (arith == AR_BF16X3 ? "absorb_chain_bf16x3" : "absorb_chain_f32");
+  hipLaunchKernelGGL(chain_kernel, dim3(static_cast<uint32_t>(n)), dim3(kChainThreads), 0, stream,
+                     a);
+  return hipGetLastError();
+}
 
 struct BatchImpl {
   std::vector<Plan> plan_copies;        // the batch owns copies of its plans

@@ -278,6 +278,8 @@ void fill_stage_descs(const Plan& p, const Layout& L, int64_t s_base,
 }
 
 int32_t g_quadrant_streams = 0;
+int32_t g_chain_steps = 1;
+void set_chain_steps(int32_t on) { g_chain_steps = on ? 1 : 0; }
 void set_quadrant_streams(int32_t on) { g_quadrant_streams = on ? 1 : 0; }
 
 HostKeep::~HostKeep() {
@@ -410,7 +412,7 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
   // the next one (first step index of each action; pair flag).
   // Per unit, the absorption steps in order: alone, fused with the next one
   // (pair), or the first of a column chunk of `len` steps.
-  enum { ACT_ONE = 0, ACT_PAIR = 1, ACT_CHUNK = 2 };
+  enum { ACT_ONE = 0, ACT_PAIR = 1, ACT_CHUNK = 2, ACT_CHAIN = 3 };
   struct Action { int32_t k, kind, len; };
   std::vector<std::vector<Action>> acts(nu);
   size_t max_acts = 0;
@@ -434,6 +436,27 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
       acts[u].push_back(a);
       k += a.len;
     }
+    if (fuse == 2 && g_chain_steps) {
+      // runs of small single steps: one workgroup, one launch
+      auto small = [&](const Action& a) {
+        const Step& st = p.steps[a.k];
+        return a.kind == ACT_ONE && st.kind == STEP_ABSORB && st.out <= kChainEntries &&
+               st.pre * st.K * st.post <= kChainEntries;
+      };
+      std::vector<Action> merged;
+      for (size_t i = 0; i < acts[u].size();) {
+        size_t j = i;
+        while (j < acts[u].size() && small(acts[u][j]) && j - i < static_cast<size_t>(kChainMax)) ++j;
+        if (j - i >= 2) {
+          merged.push_back({acts[u][i].k, ACT_CHAIN, static_cast<int32_t>(j - i)});
+          i = j;
+        } else {
+          merged.push_back(acts[u][i]);
+          ++i;
+        }
+      }
+      acts[u].swap(merged);
+    }
     max_acts = std::max(max_acts, acts[u].size());
   }
   // Launch action t of the units in `units` on stream `st` (same-kind steps of
@@ -452,13 +475,36 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
     const Step* gsteps[4];
     PairArgs pairs[4];
     ChunkArgs chunks[4];
+    ChainUnit chains[4];
     double pair_bytes = 0.0, pair_flops = 0.0, chunk_bytes = 0.0, chunk_flops = 0.0;
-    int32_t n = 0, np = 0, nc = 0;
+    double chain_bytes = 0.0, chain_flops = 0.0;
+    int32_t n = 0, np = 0, nc = 0, nch = 0;
     for (size_t u : units) {
       if (t >= acts[u].size()) continue;
       const Action& ac = acts[u][t];
       const AbsorbArgs a = args_of(u, ac.k);
-      if (ac.kind == ACT_CHUNK) {
+      if (ac.kind == ACT_CHAIN) {
+        ChainUnit& x = chains[nch++];
+        x.buf[0] = base + L.buf[u][0];
+        x.buf[1] = base + L.buf[u][1];
+        x.cur = cur[u];
+        x.n = ac.len;
+        for (int32_t j = 0; j < ac.len; ++j) {
+          const int32_t k = ac.k + j;
+          const Step& sj = p.steps[k];
+          ChainStep& c = x.s[j];
+          c.pre = sj.pre; c.post = sj.post; c.s_off = L.s_off[k];
+          c.K = static_cast<int32_t>(sj.K); c.N = static_cast<int32_t>(sj.N);
+          c.in_f64 = L.out_type[k - 1] == EL_F64;
+          c.out_f64 = L.out_type[k] == EL_F64;
+          c.rescale_slot = sj.rescale;
+          c.scale_slot = sj.scale_in;
+          chain_bytes += step_bytes(args_of(u, k), sj);
+          chain_flops += static_cast<double>(sj.flops);
+        }
+        // every step of the chain swaps the buffers; the common swap below is one
+        if ((ac.len & 1) == 0) cur[u] = 1 - cur[u];
+      } else if (ac.kind == ACT_CHUNK) {
         const Step& s1 = p.steps[ac.k];
         const Step& sl = p.steps[ac.k + ac.len - 1];
         ChunkArgs& x = chunks[nc++];
@@ -518,6 +564,11 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
       tm.before();
       TN_HIP_L(launch_absorb_pairs(pairs, np, sa, state, st, &kname));
       tm.after(kname, pair_bytes, pair_flops);
+    }
+    if (nch > 0) {
+      tm.before();
+      TN_HIP_L(launch_chain(chains, nch, sa, slot_exp, &state->flags, arith, st, &kname));
+      tm.after(kname, chain_bytes, chain_flops);
     }
     if (n > 1 && absorb_policy() == 0 && absorb_group_supported(group, n)) {
       double bytes = 0.0, flops = 0.0;

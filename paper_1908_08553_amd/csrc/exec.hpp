@@ -102,6 +102,11 @@ struct SideStream {
 // 1: tn_contract_grid sweeps the bottom quadrant units on a second stream of
 // the calling thread (see SideStream); 0 (default): one stream.
 void set_quadrant_streams(int32_t on);
+// Runs of small consecutive single steps of a unit as one chain launch
+// (default on; only with the default step fusion).
+void set_chain_steps(int32_t on);
+extern int32_t g_chain_steps;
+constexpr int64_t kChainEntries = 16384;   // largest step input / output of a chain
 extern int32_t g_quadrant_streams;
 
 // Issue every copy and launch of one contraction on `stream` without waiting;

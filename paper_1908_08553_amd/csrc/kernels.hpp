@@ -170,6 +170,27 @@ int64_t ring_mfma_partials_for(const RingArgs& a);
 hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** kname,
                             int64_t* n_partials, int32_t* c_slices);
 
+// A run of consecutive small single steps of one sweep unit in one workgroup
+// (batch.hip): step j reads buf[cur ^ (j & 1)] and writes the other buffer,
+// with the same per-step arithmetic as one launch per step.  Slots are
+// indices into slot_exp (-1: none); a step with rescale_slot writes that
+// slot's exponent (it starts at the "zero" sentinel and has no other writer).
+constexpr int kChainMax = 14;
+struct ChainStep {
+  int64_t pre, post, s_off;
+  int32_t K, N;
+  int32_t in_f64, out_f64;
+  int32_t rescale_slot, scale_slot;
+};
+struct ChainUnit {
+  void* buf[2];
+  int32_t cur, n;
+  ChainStep s[kChainMax];
+};
+hipError_t launch_chain(const ChainUnit* units, int32_t n, const StagedArrays& st,
+                        int32_t* slot_exp, int32_t* flags, int32_t arith, hipStream_t stream,
+                        const char** kname);
+
 // Double-layer site of a real PEPS tensor (peps.hip): A [d][dims...] and
 // E [dims_0^2]..[dims_{rank-1}^2] on the device, op [d][d] or null
 // (identity); n_in = prod dims, n_out = n_in^2.
