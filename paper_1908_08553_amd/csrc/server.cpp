@@ -14,6 +14,7 @@
 // first-come-first-served (a large request at the head of the queue is not
 // overtaken), which keeps the largest requests from starving.
 #include "server.hpp"
+#include "server_arena.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -61,47 +62,6 @@ struct Request {
   tn_result result{};
   tn_status status = TN_OK;
   int32_t state = QUEUED;
-};
-
-// First-fit allocator over [0, size) with coalescing.
-class Arena {
- public:
-  explicit Arena(size_t size) {
-    if (size) free_[0] = size;
-  }
-  bool alloc(size_t n, size_t* off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= n) {
-        *off = it->first;
-        const size_t rest = it->second - n, at = it->first + n;
-        free_.erase(it);
-        if (rest) free_[at] = rest;
-        used_ += n;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t n) {
-    used_ -= n;
-    auto it = free_.emplace(off, n).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t used() const { return used_; }
- private:
-  size_t used_ = 0;
-  std::map<size_t, size_t> free_;
 };
 
 }  // namespace

@@ -1,7 +1,7 @@
 // Drives the C++ planner over every lattice shape 1..12 x 1..12, bond
 // dimensions 1..5 (uniform and mixed), every order and every quadrant split,
 // checking the plan's bookkeeping on the way.  Built with AddressSanitizer and
-// UndefinedBehaviorSanitizer by tests/test_planner_sanitized.py (host code only).
+// UndefinedBehaviorSanitizer by tests/test_host_sanitized.py (host code only).
 #include <cstdio>
 #include <cstdlib>
 #include <string>
