@@ -18,5 +18,5 @@ from ._native import (  # noqa: F401
     tn_profile_enable, tn_profile_read,
     Batch, tn_batch_workspace, tn_contract_batch, Server,
     plan_grid, contract_grid, device_sites, workspace_for,
-    tn_double_layer, tn_double_layer_prepare, tn_observables,
+    tn_double_layer, tn_double_layer_prepare, tn_observables, Sites, prepare_sites,
 )

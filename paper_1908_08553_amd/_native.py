@@ -193,10 +193,10 @@ def tn_plan_text(plan: Plan) -> str:
     return buf.value.decode()
 
 
-def tn_contract_grid(plan: Plan, site_ptrs: Sequence[int], sites_on_device: bool,
+def tn_contract_grid(plan: Plan, site_ptrs, sites_on_device: bool,
                      precision: int, workspace_ptr: int, ws_bytes: int,
                      stream_ptr: int) -> Result:
-    arr = (C.c_void_p * len(site_ptrs))(*site_ptrs)
+    arr = site_ptrs if isinstance(site_ptrs, C.Array) else (C.c_void_p * len(site_ptrs))(*site_ptrs)
     out = tn_result()
     status = lib.tn_contract_grid(plan.handle, arr, 1 if sites_on_device else 0, precision,
                                   C.c_void_p(workspace_ptr), ws_bytes, C.c_void_p(stream_ptr),
@@ -259,11 +259,40 @@ def workspace_for(plan: Plan, precision: int, device="cuda"):
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
 
 
+class Sites:
+    """Device sites checked once, with their pointer table, for repeated
+    contractions over the same tensors (keeps them alive)."""
+
+    def __init__(self, sites):
+        import torch
+        self.keep = list(sites)
+        for t in self.keep:
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                    and t.is_contiguous()):
+                raise ValueError("device sites must be contiguous float64 device tensors")
+        self.table = (C.c_void_p * len(self.keep))(*[t.data_ptr() for t in self.keep])
+
+    def __len__(self):
+        return len(self.keep)
+
+
+def prepare_sites(sites) -> Sites:
+    return Sites(sites)
+
+
 def contract_grid(plan: Plan, sites, precision="f64", workspace=None, stream=None) -> Result:
-    """Contract with device-resident torch sites (or host numpy arrays)."""
+    """Contract with device-resident torch sites (a list, or prepare_sites'
+    Sites) or host numpy arrays."""
     import torch
     if isinstance(precision, str):
         precision = _PRECS[precision]
+    if isinstance(sites, Sites):
+        if workspace is None:
+            workspace = workspace_for(plan, precision)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        return tn_contract_grid(plan, sites.table, True, precision, workspace.data_ptr(),
+                                workspace.numel() * workspace.element_size(), stream.cuda_stream)
     on_device = all(isinstance(s, torch.Tensor) and s.is_cuda for s in sites)
     if on_device:
         for s in sites:

@@ -236,3 +236,18 @@ def test_ring_with_ragged_tiles(tn, prec):
         close_f64(got, ref)
     else:
         close_log(got, ref.log_abs)
+
+
+def test_prepared_sites_same_result(tn):
+    # a pointer table built once gives the same contraction as the site list
+    s = li.uniform(6, 7, 3, 5)
+    plan = tn.tn_plan_grid(6, 7, 3, order=P.HEURISTIC)
+    dev = tn.device_sites(s)
+    a = tn.contract_grid(plan, dev, "f64")
+    prepared = tn.prepare_sites(dev)
+    b = tn.contract_grid(plan, prepared, "f64")
+    c = tn.contract_grid(plan, prepared, "f64")
+    assert (a.mantissa, a.exp2_sum, a.sign) == (b.mantissa, b.exp2_sum, b.sign) == \
+        (c.mantissa, c.exp2_sum, c.sign)
+    with pytest.raises(ValueError):
+        tn.prepare_sites([t.float() for t in dev])
