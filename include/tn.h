@@ -242,6 +242,54 @@ tn_status tn_double_layer(const tn_double_layer_site* sites, int32_t n, void* hi
 tn_status tn_observables(const tn_result* results, int32_t rows, int32_t cols, double* mx,
                          double* mz, double* czz);
 
+/* ------------------------------------------------------------ cached environments
+ * Families of networks that equal one base network except at a few sites
+ * (§5: the observable networks equal the norm network except where the
+ * operator acts), contracted with the column sweep of §4 and its boundaries
+ * kept: the boundary after columns 0..c-1 of the base network (left
+ * environment) and the one after columns cols-1..c (right environment, the
+ * same sweep run from the right edge) are computed once per run.  A network
+ * whose substituted sites lie in columns [c0, c1) then costs the absorption
+ * of those columns, started from the left environment at c0, and one dot
+ * with the right environment at c1 (none when c1 = cols: that network is the
+ * full sweep's own arithmetic), instead of a full contraction.  Every value
+ * is the exact contraction of its network up to rounding, with the exact
+ * power-of-two rescaling of the sweep.
+ *
+ * Network k substitutes subst_site[o_k .. o_k + n_subst[k]) (row-major site
+ * indices r * cols + c, distinct within a network; o_k = n_subst[0] + ... +
+ * n_subst[k-1]); n_subst[k] = 0 is the base network itself.  The set copies
+ * the grid and the lists.  Precision as tn_contract_grid (the last column of
+ * every sweep and every environment dot accumulate in float64).             */
+typedef struct tn_envset tn_envset;
+
+/* Workspace bytes for this family in `precision`: the 2 (cols - 1) column
+ * environments, one region the networks take in turn, and small tables.
+ * Errors: TN_EINVAL (bad grid, counts, a site index outside the lattice or
+ * repeated in one network), TN_EOVERFLOW.                                   */
+tn_status tn_envset_workspace(const tn_grid* grid, int32_t precision, int32_t n,
+                              const int32_t* n_subst, const int32_t* subst_site, size_t* bytes);
+
+/* Build the plans; `workspace` (>= tn_envset_workspace bytes, 256-byte
+ * aligned, device memory owned by the caller) is reserved for this set until
+ * destroy.  Errors: as tn_envset_workspace, TN_ENOMEM (workspace too small). */
+tn_status tn_envset_create(const tn_grid* grid, int32_t precision, int32_t n,
+                           const int32_t* n_subst, const int32_t* subst_site, void* workspace,
+                           size_t ws_bytes, tn_envset** out);
+
+/* Contract the base network and every network of the set.  base: rows*cols
+ * DEVICE pointers to the base sites (float64, canonical legs); subst: one
+ * DEVICE pointer per entry of subst_site, the replacing site (same shape as
+ * the site it replaces).  All borrowed for the call.  outs[0] is the base
+ * network, outs[1 + k] network k.  Enqueued on hip_stream; blocks until the
+ * results are copied back.  Errors: TN_EINVAL (NULL pointer), TN_EDEVICE,
+ * TN_ENONFINITE (a network met a non-finite value: its outs[] status says
+ * so, the other results are valid).                                         */
+tn_status tn_envset_run(tn_envset* set, const double* const* base, const double* const* subst,
+                        void* hip_stream, tn_result* outs);
+
+tn_status tn_envset_destroy(tn_envset* set);
+
 /* ------------------------------------------------------------ serving
  * A request loop that admits contractions of different sizes and precisions
  * as they arrive.  A scheduler thread admits queued requests first-come-

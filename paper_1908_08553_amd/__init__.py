@@ -16,7 +16,7 @@ from ._native import (  # noqa: F401
     TN_OPT_KERNEL_IMPL, TN_OPT_BATCH_THREADS, TN_OPT_FUSE_STEPS, TN_OPT_CHUNK_SCHEDULE,
     TN_OPT_QUADRANT_STREAMS, TN_OPT_CHAIN_STEPS,
     tn_profile_enable, tn_profile_read,
-    Batch, tn_batch_workspace, tn_contract_batch, Server,
+    Batch, tn_batch_workspace, tn_contract_batch, Server, EnvSet,
     plan_grid, contract_grid, device_sites, workspace_for,
     tn_double_layer, tn_double_layer_prepare, tn_observables, Sites, prepare_sites,
 )

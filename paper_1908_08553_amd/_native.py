@@ -401,6 +401,96 @@ def tn_contract_batch(plans, site_lists, precision="f32", workspace=None, stream
     return [Result.from_c(o) for o in outs]
 
 
+# ------------------------------------------------------- cached environments
+lib.tn_envset_workspace.argtypes = [C.POINTER(tn_grid), C.c_int32, C.c_int32,
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_size_t)]
+lib.tn_envset_workspace.restype = C.c_int32
+lib.tn_envset_create.argtypes = [C.POINTER(tn_grid), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32), _P, C.c_size_t, C.POINTER(_P)]
+lib.tn_envset_create.restype = C.c_int32
+lib.tn_envset_run.argtypes = [_P, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), _P,
+                              C.POINTER(tn_result)]
+lib.tn_envset_run.restype = C.c_int32
+lib.tn_envset_destroy.argtypes = [_P]
+lib.tn_envset_destroy.restype = C.c_int32
+
+
+class EnvSet:
+    """A tn_envset: networks equal to a base network except at a few sites,
+    contracted with cached left and right column environments.
+
+    networks: one list of row-major site indices per network (the sites it
+    replaces).  run(base, subst) takes the base network's rows*cols device
+    sites and, per network, the replacing device sites in the same order;
+    it returns [base result] + one result per network."""
+
+    def __init__(self, rows, cols, D=2, hdim=None, vdim=None, networks=(), precision="f64",
+                 device="cuda"):
+        import torch
+        if isinstance(precision, str):
+            precision = _PRECS[precision]
+        self.rows, self.cols, self.precision = rows, cols, precision
+        self.networks = [list(map(int, n)) for n in networks]
+        h = _int_array(hdim)
+        v = _int_array(vdim)
+        self._dims = (h, v)
+        self._grid = tn_grid(rows, cols, D,
+                             C.cast(h, C.POINTER(C.c_int32)) if h is not None else None,
+                             C.cast(v, C.POINTER(C.c_int32)) if v is not None else None)
+        counts = [len(n) for n in self.networks]
+        flat = [i for n in self.networks for i in n]
+        self._counts = (C.c_int32 * max(len(counts), 1))(*counts)
+        self._flat = (C.c_int32 * max(len(flat), 1))(*flat)
+        self.n_subst = len(flat)
+        nbytes = C.c_size_t()
+        _check(lib.tn_envset_workspace(C.byref(self._grid), precision, len(counts), self._counts,
+                                       self._flat, C.byref(nbytes)))
+        self.workspace = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=device)
+        hd = C.c_void_p()
+        _check(lib.tn_envset_create(C.byref(self._grid), precision, len(counts), self._counts,
+                                    self._flat, C.c_void_p(self.workspace.data_ptr()),
+                                    self.workspace.numel(), C.byref(hd)))
+        self._h = hd
+
+    def prepare(self, base, subst):
+        """Pointer tables of (base, subst) for repeated runs over the same
+        tensors (keeps them alive)."""
+        import torch
+        base, subst = list(base), list(subst)
+        if len(base) != self.rows * self.cols:
+            raise ValueError("one base site per lattice site")
+        if len(subst) != self.n_subst:
+            raise ValueError("one replacing site per substitution")
+        for t in base + subst:
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                    and t.is_contiguous()):
+                raise ValueError("sites must be contiguous float64 device tensors")
+        b = (C.c_void_p * len(base))(*[t.data_ptr() for t in base])
+        s = (C.c_void_p * max(len(subst), 1))(*[t.data_ptr() for t in subst])
+        return b, s, (base, subst)
+
+    def run(self, base=None, subst=None, stream=None, prepared=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        b, s, keep = prepared if prepared is not None else self.prepare(base, subst)
+        outs = (tn_result * (len(self.networks) + 1))()
+        status = lib.tn_envset_run(self._h, b, s, C.c_void_p(stream.cuda_stream), outs)
+        if status not in (TN_OK, TN_ENONFINITE):
+            _check(status)
+        del keep
+        return [Result.from_c(o) for o in outs]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.tn_envset_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
 # ------------------------------------------------------------------ PEPS
 def tn_double_layer_prepare(pairs):
     """Checked descriptor array of (A, op, E) triples for repeated calls over

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "batch.hpp"
+#include "envset.hpp"
 #include "exec.hpp"
 #include "server.hpp"
 #include "kernels.hpp"
@@ -26,6 +27,10 @@ struct tn_batch {
 
 struct tn_server {
   tn::ServerImpl* impl;
+};
+
+struct tn_envset {
+  tn::EnvSetImpl* impl;
 };
 
 namespace {
@@ -220,6 +225,60 @@ tn_status tn_contract_batch(const tn_plan* const* plans, const double* const* co
   tn_batch_destroy(b);
   g_err = keep;
   return s;
+}
+
+tn_status tn_envset_workspace(const tn_grid* grid, int32_t precision, int32_t n,
+                              const int32_t* n_subst, const int32_t* subst_site, size_t* bytes) {
+  try {
+    if (!grid || !bytes) return fail(TN_EINVAL, "null argument");
+    if (precision < TN_PREC_F64 || precision > TN_PREC_BF16X3) return fail(TN_EINVAL, "unknown precision");
+    std::string err;
+    const tn_status s = tn::envset_workspace(*grid, precision, n, n_subst, subst_site, bytes, err);
+    return s == TN_OK ? s : fail(s, err);
+  } catch (...) {
+    return fail(TN_EINVAL, "tn_envset_workspace failed");
+  }
+}
+
+tn_status tn_envset_create(const tn_grid* grid, int32_t precision, int32_t n,
+                           const int32_t* n_subst, const int32_t* subst_site, void* workspace,
+                           size_t ws_bytes, tn_envset** out) {
+  try {
+    if (!grid || !out || !workspace) return fail(TN_EINVAL, "null argument");
+    *out = nullptr;
+    if (precision < TN_PREC_F64 || precision > TN_PREC_BF16X3) return fail(TN_EINVAL, "unknown precision");
+    std::string err;
+    tn::EnvSetImpl* impl = nullptr;
+    const tn_status s = tn::envset_create(*grid, precision, n, n_subst, subst_site, workspace,
+                                          ws_bytes, &impl, err);
+    if (s != TN_OK) return fail(s, err);
+    *out = new tn_envset{impl};
+    return TN_OK;
+  } catch (const std::exception& e) {
+    return fail(TN_EINVAL, e.what());
+  } catch (...) {
+    return fail(TN_EINVAL, "tn_envset_create failed");
+  }
+}
+
+tn_status tn_envset_run(tn_envset* set, const double* const* base, const double* const* subst,
+                        void* hip_stream, tn_result* outs) {
+  try {
+    if (!set || !base || !outs) return fail(TN_EINVAL, "null argument");
+    std::string err;
+    const tn_status s = tn::envset_run(set->impl, base, subst,
+                                       static_cast<hipStream_t>(hip_stream), outs, err);
+    return s == TN_OK ? s : fail(s, err);
+  } catch (...) {
+    return fail(TN_EDEVICE, "tn_envset_run failed");
+  }
+}
+
+tn_status tn_envset_destroy(tn_envset* set) {
+  if (!set) return TN_OK;
+  tn::envset_destroy(set->impl);
+  delete set;
+  return TN_OK;
 }
 
 tn_status tn_server_create(void* arena, size_t arena_bytes, int32_t max_slots,

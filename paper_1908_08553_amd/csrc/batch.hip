@@ -284,7 +284,7 @@ tn_status layout_batch(BatchImpl& b, std::string& err) {
   int32_t steps = 0;
   for (int32_t i = 0; i < n; ++i) {
     const Plan& p = *b.plans[i];
-    if (p.order != TN_ORDER_COLSWEEP) {
+    if (p.order != TN_ORDER_COLSWEEP || p.is_cut) {
       err = "batched contraction needs column-sweep plans";
       return TN_EINVAL;
     }

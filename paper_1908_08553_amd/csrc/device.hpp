@@ -34,8 +34,18 @@ struct DevState {
   int32_t n_slots;
   int32_t n_steps;
   int32_t pad;
-  double ring_scalar;
+  int64_t e_bias;           // exponent carried in by a supplied boundary (cut plans)
   // followed by: int32 slot_exp[n_slots], int32 site_exp[n_steps], int32 site_bad[n_steps]
+};
+
+// A boundary kept between launches (cached environment) and its scale: the
+// exact boundary is buffer * 2^-e * 2^(bias + e), with e the exponent of its
+// largest magnitude as the rescale slots hold it (kExpZero: no shift and no
+// exponent, kExpBad: a non-finite value was seen on the way).
+struct EnvRec {
+  int64_t bias;
+  int32_t e;
+  int32_t pad;
 };
 
 }  // namespace tn

@@ -232,6 +232,7 @@ int64_t algorithmic_bytes(const Plan& p, int32_t prec) {
     const Step& s = p.steps[k];
     const int64_t eo = elem_bytes(L.out_type[k]);
     if (s.kind == STEP_INIT) { bytes += s.out * eo; continue; }
+    if (s.kind == STEP_SEED) { bytes += 2 * s.out * eo; continue; }
     const int64_t ei = elem_bytes(L.out_type[k - 1]);
     bytes += s.pre * s.K * s.post * ei + s.out * eo;
   }
@@ -308,8 +309,18 @@ size_t head_bytes(const Plan& p, const Layout& L) {
 tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                   void* ws, size_t ws_bytes, hipStream_t stream, HostKeep& keep,
                   LaunchTimer& timer, std::string& err, const SideStream* side,
-                  LaunchTimer* side_timer) {
+                  LaunchTimer* side_timer, const CutIO* io) {
   const Layout L = make_layout(p, prec);
+  const bool seeded = !p.steps.empty() && p.steps[0].kind == STEP_SEED;
+  const bool open_end = p.is_cut && p.cut_c1 < p.cols;
+  if (seeded && (!io || !io->seed || !io->seed_rec)) {
+    err = "cut plan needs a seed boundary";
+    return TN_EINVAL;
+  }
+  if (open_end && (!io || !((io->cap && io->cap_rec && io->partials) || (io->tap && io->tap_rec)))) {
+    err = "cut plan needs a cap boundary or a tap record";
+    return TN_EINVAL;
+  }
   if (ws_bytes < L.total) {
     err = "workspace too small: need " + std::to_string(L.total) + " bytes";
     return TN_ENOMEM;
@@ -382,6 +393,14 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
   TN_HIP(launch_stage(reinterpret_cast<const StageDesc*>(base + L.descs),
                       static_cast<int32_t>(nsteps), sa, tg, stream));
   timer.after("stage", 8.0 * 2 * static_cast<double>(p.total_site_entries), 0.0);
+  if (seeded) {
+    const Step& s0 = p.steps[0];
+    const int32_t f64 = L.out_type[0] == EL_F64;
+    timer.before();
+    TN_HIP(launch_env_seed(io->seed, base + L.buf[0][0], s0.out, f64, io->seed_rec,
+                           slot_exp + s0.rescale, state, stream));
+    timer.after("env_seed", 2.0 * static_cast<double>(s0.out) * (f64 ? 8.0 : 4.0), 0.0);
+  }
 
   const int32_t arith = prec == TN_PREC_F64 ? AR_F64 : (prec == TN_PREC_F32 ? AR_F32 : AR_BF16X3);
   // Steps of different units are independent: walk step index t across the
@@ -613,10 +632,36 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
   // slot stays "zero" and scales by 2^0
   for (size_t u = 0; u < nu; ++u) final_buf[u] = cur[u];
 
-  if (!p.has_ring) {
+  tn_result* copy = io ? io->result : nullptr;
+  if (open_end) {
+    const size_t kl = p.steps.size() - 1;
+    const Step& sl = p.steps[kl];
+    const char* fin = base + L.buf[0][final_buf[0]];
+    if (sl.rescale < 0) {
+      err = "cut plan ends without a rescale point";
+      return TN_EINVAL;
+    }
+    const int32_t* slot_last = slot_exp + sl.rescale;
+    if (io->cap) {
+      const int32_t f64 = L.out_type[kl] == EL_F64;
+      timer.before();
+      TN_HIP(launch_env_cap(fin, io->cap, sl.out, f64, slot_last, io->cap_rec, io->partials, state,
+                            stream));
+      timer.after("env_cap", 2.0 * static_cast<double>(sl.out) * (f64 ? 8.0 : 4.0),
+                  2.0 * static_cast<double>(sl.out));
+      timer.before();
+      TN_HIP(launch_finalize(state, nullptr, copy, io->partials, env_cap_blocks(sl.out), stream));
+      timer.after("finalize", 0.0, 0.0);
+    } else {
+      *io->tap = fin;
+      timer.before();
+      TN_HIP(launch_env_tap(state, slot_last, io->tap_rec, stream));
+      timer.after("env_tap", 0.0, 0.0);
+    }
+  } else if (!p.has_ring) {
     const double* scalar = reinterpret_cast<const double*>(base + L.buf[0][final_buf[0]]);
     timer.before();
-    TN_HIP(launch_finalize(state, scalar, nullptr, nullptr, 0, stream));
+    TN_HIP(launch_finalize(state, scalar, copy, nullptr, 0, stream));
     timer.after("finalize", 0.0, 0.0);
   } else {
     const Ring& g = p.ring;
@@ -719,7 +764,7 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
                   2.0 * static_cast<double>(g.m * g.n * g.ky) + 2.0 * static_cast<double>(g.m * g.n));
     }
     timer.before();
-    TN_HIP(launch_finalize(state, nullptr, nullptr, partials, n_part, stream));
+    TN_HIP(launch_finalize(state, nullptr, copy, partials, n_part, stream));
     timer.after("finalize", 0.0, 0.0);
   }
 #undef TN_HIP

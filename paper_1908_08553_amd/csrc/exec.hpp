@@ -109,6 +109,24 @@ extern int32_t g_chain_steps;
 constexpr int64_t kChainEntries = 16384;   // largest step input / output of a chain
 extern int32_t g_quadrant_streams;
 
+// Ends of a cut plan (Plan::is_cut): the boundary its SEED step starts from,
+// and either the boundary its last column is closed against (cap: the
+// mirrored sweep's boundary at the same column cut, same leg order) or the
+// record of the boundary it ends in (tap).  All pointers are device memory
+// except `tap`, which receives the address of the ending boundary (inside
+// the plan's workspace).  `partials` holds env_cap_blocks(entries) doubles.
+// With `result` the result record is also written there.
+struct CutIO {
+  const void* seed = nullptr;
+  const EnvRec* seed_rec = nullptr;
+  const void* cap = nullptr;
+  const EnvRec* cap_rec = nullptr;
+  EnvRec* tap_rec = nullptr;
+  const void** tap = nullptr;
+  double* partials = nullptr;
+  tn_result* result = nullptr;
+};
+
 // Issue every copy and launch of one contraction on `stream` without waiting;
 // the result record lands in the workspace's DevState (offset Layout.state).
 // With `side` (and `side_timer` for its launches) quadrant plans also use
@@ -116,7 +134,7 @@ extern int32_t g_quadrant_streams;
 tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                   void* ws, size_t ws_bytes, hipStream_t stream, HostKeep& keep,
                   LaunchTimer& timer, std::string& err, const SideStream* side = nullptr,
-                  LaunchTimer* side_timer = nullptr);
+                  LaunchTimer* side_timer = nullptr, const CutIO* io = nullptr);
 
 tn_status contract(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                    void* ws, size_t ws_bytes, hipStream_t stream, tn_result* out,

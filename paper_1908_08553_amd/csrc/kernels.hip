@@ -10,6 +10,7 @@
 // permuted, so reads and writes stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -272,7 +273,8 @@ __global__ __launch_bounds__(kBlock) void ring_generic(
 
 // --------------------------------------------------------------- finalize
 __global__ __launch_bounds__(kBlock) void finalize_kernel(DevState* state, const double* scalar,
-                                                          const double* partials, int64_t np) {
+                                                          const double* partials, int64_t np,
+                                                          tn_result* copy) {
   __shared__ double red[kBlock];
   __shared__ int64_t red_e[kBlock];
   __shared__ int32_t red_bad[kBlock];
@@ -310,8 +312,116 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(DevState* state, const
   }
   if (threadIdx.x != 0) return;
   const double mval = partials ? red[0] : *scalar;
-  const tn_result r = dev::assemble_result(mval, red_e[0], red_bad[0] | (state->flags & 1));
+  const tn_result r = dev::assemble_result(mval, red_e[0] + state->e_bias,
+                                           red_bad[0] | (state->flags & 1));
   state->result = r;
+  if (copy) *copy = r;
+}
+
+// ------------------------------------------------------------ environments
+__global__ __launch_bounds__(kBlock) void env_seed_kernel(const void* __restrict__ src,
+                                                          void* __restrict__ dst, int64_t n,
+                                                          int32_t f64, const EnvRec* rec,
+                                                          int32_t* slot, DevState* state) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f64) {
+    const double* s = static_cast<const double*>(src);
+    double* d = static_cast<double*>(dst);
+    for (int64_t i = i0; i < n; i += stride) d[i] = s[i];
+  } else {
+    const float* s = static_cast<const float*>(src);
+    float* d = static_cast<float*>(dst);
+    for (int64_t i = i0; i < n; i += stride) d[i] = s[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *slot = rec->e;
+    state->e_bias = rec->bias;
+  }
+}
+
+constexpr int64_t kCapChunk = 8192;   // entries per block of the cap dot
+constexpr int64_t kCapBlocks = 1024;
+
+__global__ __launch_bounds__(kBlock) void env_cap_kernel(const void* __restrict__ B,
+                                                         const void* __restrict__ Rv, int64_t n,
+                                                         int64_t chunk, int32_t f64,
+                                                         const int32_t* slot_b, const EnvRec* rec,
+                                                         double* __restrict__ partials,
+                                                         DevState* state) {
+  __shared__ double red[kBlock];
+  const int32_t er_raw = rec->e;
+  const int32_t er = (er_raw == kExpZero || er_raw == kExpBad) ? 0 : er_raw;
+  const double sb = ldexp(1.0, -shift_of(slot_b));
+  const double sr = ldexp(1.0, -er);
+  const int64_t lo = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  double s = 0.0;
+  if (f64) {
+    const double* b = static_cast<const double*>(B);
+    const double* r = static_cast<const double*>(Rv);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += (b[i] * sb) * (r[i] * sr);
+  } else {
+    const float* b = static_cast<const float*>(B);
+    const float* r = static_cast<const float*>(Rv);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
+      s += (static_cast<double>(b[i]) * sb) * (static_cast<double>(r[i]) * sr);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (static_cast<int>(threadIdx.x) < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = red[0];
+    if (blockIdx.x == 0) {
+      state->e_bias += rec->bias + er;
+      if (er_raw == kExpBad) state->flags |= 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void env_tap_kernel(DevState* state, const int32_t* slot_last,
+                                                         EnvRec* rec) {
+  __shared__ int64_t red_e[kBlock];
+  __shared__ int32_t red_bad[kBlock];
+  const int32_t* slot_exp = reinterpret_cast<const int32_t*>(state + 1);
+  const int32_t* site_exp = slot_exp + state->n_slots;
+  const int32_t* site_bad = site_exp + state->n_steps;
+  int64_t E = 0;
+  int32_t bad = 0;
+  for (int i = threadIdx.x; i < state->n_slots; i += blockDim.x) {
+    const int32_t e = slot_exp[i];
+    if (e == kExpBad) bad = 1;
+    else if (e != kExpZero) E += e;
+  }
+  for (int i = threadIdx.x; i < state->n_steps; i += blockDim.x) {
+    E += site_exp[i];
+    bad |= site_bad[i];
+  }
+  red_e[threadIdx.x] = E;
+  red_bad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (static_cast<int>(threadIdx.x) < st) {
+      red_e[threadIdx.x] += red_e[threadIdx.x + st];
+      red_bad[threadIdx.x] |= red_bad[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const int32_t e = *slot_last;
+  EnvRec out;
+  out.pad = 0;
+  if (red_bad[0] || (state->flags & 1) || e == kExpBad) {
+    out.bias = 0;
+    out.e = kExpBad;
+  } else {
+    out.e = e;
+    out.bias = red_e[0] + state->e_bias - (e == kExpZero ? 0 : e);
+  }
+  *rec = out;
 }
 
 }  // namespace
@@ -411,10 +521,39 @@ hipError_t launch_ring(const RingArgs& a, hipStream_t stream, const char** kname
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(DevState* state, const double* scalar, const float*,
+hipError_t launch_finalize(DevState* state, const double* scalar, tn_result* copy,
                            const double* partials, int64_t n_partials, hipStream_t stream) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kBlock), 0, stream, state, scalar, partials,
-                     n_partials);
+                     n_partials, copy);
+  return hipGetLastError();
+}
+
+hipError_t launch_env_seed(const void* src, void* dst, int64_t n, int32_t f64, const EnvRec* rec,
+                           int32_t* slot, DevState* state, hipStream_t stream) {
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>((n + kBlock - 1) / kBlock, 1), 2048);
+  hipLaunchKernelGGL(env_seed_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, stream,
+                     src, dst, n, f64, rec, slot, state);
+  return hipGetLastError();
+}
+
+int64_t env_cap_blocks(int64_t n) {
+  const int64_t chunk = std::max<int64_t>(kCapChunk, (n + kCapBlocks - 1) / kCapBlocks);
+  return std::max<int64_t>((n + chunk - 1) / chunk, 1);
+}
+
+hipError_t launch_env_cap(const void* B, const void* Rv, int64_t n, int32_t f64,
+                          const int32_t* slot_b, const EnvRec* rec, double* partials,
+                          DevState* state, hipStream_t stream) {
+  const int64_t chunk = std::max<int64_t>(kCapChunk, (n + kCapBlocks - 1) / kCapBlocks);
+  const int64_t blocks = env_cap_blocks(n);
+  hipLaunchKernelGGL(env_cap_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, stream,
+                     B, Rv, n, chunk, f64, slot_b, rec, partials, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_env_tap(DevState* state, const int32_t* slot_last, EnvRec* rec,
+                          hipStream_t stream) {
+  hipLaunchKernelGGL(env_tap_kernel, dim3(1), dim3(kBlock), 0, stream, state, slot_last, rec);
   return hipGetLastError();
 }
 

@@ -206,8 +206,26 @@ bool double_layer_ok(const DoubleLayerSite& s);
 hipError_t launch_double_layer(const DoubleLayerSite* sites, int32_t n, hipStream_t stream);
 
 // Writes state->result from the final scalar (or the sum of `n_partials`
-// partials), the site exponents and the rescale slots.
-hipError_t launch_finalize(DevState* state, const double* scalar, const float* scalar_f,
+// partials), the site exponents, the rescale slots and state->e_bias; with
+// `copy` the record is also written there.
+hipError_t launch_finalize(DevState* state, const double* scalar, tn_result* copy,
                            const double* partials, int64_t n_partials, hipStream_t stream);
+
+// Cut plans (cached environments).  Seed: copy the supplied boundary `src`
+// (n entries, float64 if f64 else float32) into `dst`, put rec->e in the
+// SEED step's rescale slot and rec->bias in state->e_bias.
+hipError_t launch_env_seed(const void* src, void* dst, int64_t n, int32_t f64, const EnvRec* rec,
+                           int32_t* slot, DevState* state, hipStream_t stream);
+// Cap: partial sums of sum_i (B[i] 2^-eb)(Rv[i] 2^-er) with eb = *slot_b and
+// er = rec->e, one per block of env_cap_blocks(n) blocks (fixed order), and
+// rec's exponent added to state->e_bias; finalize then sums the partials.
+int64_t env_cap_blocks(int64_t n);
+hipError_t launch_env_cap(const void* B, const void* Rv, int64_t n, int32_t f64,
+                          const int32_t* slot_b, const EnvRec* rec, double* partials,
+                          DevState* state, hipStream_t stream);
+// Tap: the record of the boundary a cut plan ends in, whose largest-magnitude
+// exponent is *slot_last (one block; the exponent sums of finalize).
+hipError_t launch_env_tap(DevState* state, const int32_t* slot_last, EnvRec* rec,
+                          hipStream_t stream);
 
 }  // namespace tn

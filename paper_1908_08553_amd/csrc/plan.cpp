@@ -328,6 +328,67 @@ tn_status build_plan(const tn_grid& grid, int32_t order, int32_t quad_h, int32_t
   return TN_OK;
 }
 
+tn_status build_cut_plan(const tn_grid& grid, int32_t mirror, int32_t c0, int32_t c1, Plan& out,
+                         std::string& err) {
+  Plan p;
+  const tn_status st = build_plan(grid, TN_ORDER_COLSWEEP, 0, 0, p, err);
+  if (st != TN_OK) return st;
+  const int32_t R = p.rows, C = p.cols;
+  if (c0 < 0 || c1 > C || c0 >= c1) { err = "cut columns out of range"; return TN_EINVAL; }
+  Lattice L{R, C, &p.hdim, &p.vdim};
+  const int32_t frame = mirror ? FRAME_MH : FRAME_ID;
+  std::vector<Step> all;
+  int32_t slot = 0;
+  try {
+    sweep(L, 0, frame, R, C, false, slot, all);
+    std::vector<Step> head;
+    int32_t unused = 0;
+    p.cut_legs = sweep(L, 0, frame, R, c1, false, unused, head);
+  } catch (Overflow&) {
+    err = "plan integers overflow int64";
+    return TN_EOVERFLOW;
+  }
+  // every local column holds R steps; its rescale slot is its column index
+  const int32_t off = c0 > 0 ? c0 - 1 : 0;
+  p.steps.clear();
+  if (c0 > 0) {
+    const Step& last = all[static_cast<size_t>(c0) * R - 1];
+    Step s;
+    s.unit = 0; s.r = last.r; s.c = last.c; s.kind = STEP_SEED;
+    s.pre = s.K = s.post = 1;
+    s.N = s.out = last.out;
+    s.col = c0 - 1; s.last_col = 0;
+    s.site_entries = 0;
+    s.rescale = 0;
+    p.steps.push_back(s);
+  }
+  for (size_t k = static_cast<size_t>(c0) * R; k < static_cast<size_t>(c1) * R; ++k) {
+    Step s = all[k];
+    s.scale_in = -1;
+    if (s.rescale >= 0) s.rescale -= off;
+    p.steps.push_back(s);
+  }
+  p.slots = 0;
+  for (const Step& s : p.steps) p.slots = std::max(p.slots, s.rescale + 1);
+  p.units.clear();
+  Unit U;
+  U.frame = frame; U.rows = R; U.cols = c1 - c0; U.result = p.steps.back().out;
+  U.first_step = 0; U.n_steps = static_cast<int32_t>(p.steps.size());
+  p.units.push_back(U);
+  p.is_cut = true;
+  p.cut_mirror = mirror ? 1 : 0;
+  p.cut_c0 = c0;
+  p.cut_c1 = c1;
+  try {
+    finish(p);
+  } catch (Overflow&) {
+    err = "plan integers overflow int64";
+    return TN_EOVERFLOW;
+  }
+  out = std::move(p);
+  return TN_OK;
+}
+
 namespace {
 void ints(std::ostringstream& os, const std::vector<int32_t>& v) {
   if (v.empty()) { os << "-"; return; }
@@ -350,7 +411,8 @@ std::string plan_text(const Plan& p) {
   for (size_t k = 0; k < p.steps.size(); ++k) {
     const Step& s = p.steps[k];
     os << "step " << k << " unit=" << s.unit << " site=" << s.r << "," << s.c
-       << " kind=" << (s.kind == STEP_INIT ? "INIT" : "ABSORB") << " pre=" << s.pre
+       << " kind=" << (s.kind == STEP_INIT ? "INIT" : (s.kind == STEP_SEED ? "SEED" : "ABSORB"))
+       << " pre=" << s.pre
        << " K=" << s.K << " N=" << s.N << " post=" << s.post << " perm=";
     if (s.nperm == 0) os << "-";
     for (int32_t a = 0; a < s.nperm; ++a) os << (a ? "." : "") << s.perm[a];

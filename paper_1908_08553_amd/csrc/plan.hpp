@@ -18,11 +18,14 @@ namespace tn {
 
 enum : int32_t { LEG_LEFT = 0, LEG_UP = 1, LEG_RIGHT = 2, LEG_DOWN = 3 };
 enum : int32_t { FRAME_ID = 0, FRAME_T = 1, FRAME_MH = 2, FRAME_MHV = 3, FRAME_MV = 4 };
-enum : int32_t { STEP_INIT = 0, STEP_ABSORB = 1 };
+enum : int32_t { STEP_INIT = 0, STEP_ABSORB = 1, STEP_SEED = 2 };
 
 // One pairwise step: out[pre][N][post] = sum_k in[pre][k][post] * S[k][n], where
 // S is the site tensor folded to (K legs, N legs) by the axis permutation perm.
 // An INIT step copies the folded site into the unit's boundary (pre=K=post=1).
+// A SEED step (first step of a cut plan) stands for a boundary supplied from
+// outside: out = N = its entries, no site, its rescale slot holds the
+// supplied boundary's exponent.
 struct Step {
   int32_t unit = 0, r = 0, c = 0, kind = STEP_INIT;
   int64_t pre = 1, K = 1, N = 1, post = 1, out = 1, flops = 0;
@@ -63,11 +66,24 @@ struct Plan {
   int32_t slots = 0;
   int64_t peak = 0, flops = 0, moved = 0;
   int64_t total_site_entries = 0;
+  // Cut plans: local columns [cut_c0, cut_c1) of a full-lattice column sweep,
+  // left to right (cut_mirror 0) or right to left (1).  They start with a SEED
+  // step when cut_c0 > 0 and end in the boundary after column cut_c1 - 1 when
+  // cut_c1 < cols (the column-sweep scalar otherwise).
+  bool is_cut = false;
+  int32_t cut_mirror = 0, cut_c0 = 0, cut_c1 = 0;
+  std::vector<int32_t> cut_legs;   // bond ids of the ending boundary, slowest first
 };
 
 // Builds a plan.  Returns TN_OK, TN_EINVAL or TN_EOVERFLOW (message in err).
 tn_status build_plan(const tn_grid& grid, int32_t order, int32_t quad_h,
                      int32_t quad_w, Plan& out, std::string& err);
+
+// Cut plan of the column sweep (see Plan::is_cut): same steps, site folds and
+// rescale points as the full sweep over those columns.  TN_EINVAL unless
+// 0 <= c0 < c1 <= cols.
+tn_status build_cut_plan(const tn_grid& grid, int32_t mirror, int32_t c0, int32_t c1, Plan& out,
+                         std::string& err);
 
 // Canonical text: identical bytes for identical plans.
 std::string plan_text(const Plan& p);

@@ -4,15 +4,20 @@ of O|Psi> against <Psi|, L^2 + 2L(L-1) of them per evaluation, which is where
 the paper's run time goes).
 
 Every arithmetic step runs in the library: ``tn_double_layer`` builds the
-single-layer sites (norm, S^x and S^z at every site) in one call, one
-captured batch launch contracts all networks of the evaluation, and
-``tn_observables`` forms the ratios.  This module only allocates the buffers
-and lists which site tensor each network uses.
+single-layer sites (norm, S^x and S^z at every site) in one call, the
+networks of the evaluation are contracted either by one captured batch
+launch (``mode="batch"``: one workgroup per network, every network a full
+sweep; suited to small lattices) or with cached column environments
+(``mode="env"``: the norm network's left and right sweeps are kept, and each
+observable network absorbs only the one or two columns holding its operator
+sites and closes against the right environment), and ``tn_observables``
+forms the ratios.  This module only allocates the buffers and lists which
+site tensor each network uses.
 """
 from __future__ import annotations
 
-from ._native import (TN_ORDER_SWEEP_AUTO, Batch, tn_double_layer, tn_double_layer_prepare,
-                      tn_observables, tn_plan_grid)
+from ._native import (TN_ORDER_SWEEP_AUTO, Batch, EnvSet, tn_double_layer,
+                      tn_double_layer_prepare, tn_observables, tn_plan_grid)
 
 
 def pairs(rows: int, cols: int):
@@ -29,16 +34,15 @@ class ObservableSet:
     S^z S^z on every pair, contracted as one batch in ``precision``."""
 
     def __init__(self, rows: int, cols: int, chi: int, d: int = 2, precision: str = "f64",
-                 threads: int = 0, device: str = "cuda"):
+                 threads: int = 0, device: str = "cuda", mode: str = "batch"):
         import torch
-        self.rows, self.cols, self.chi, self.d = rows, cols, chi, d
+        if mode not in ("batch", "env"):
+            raise ValueError("mode must be 'batch' or 'env'")
+        self.rows, self.cols, self.chi, self.d, self.mode = rows, cols, chi, d, mode
         self.n = rows * cols
         self.pairs = pairs(rows, cols)
-        self.plan = tn_plan_grid(rows, cols, chi * chi, order=TN_ORDER_SWEEP_AUTO)
         self.count = 1 + 2 * self.n + len(self.pairs)
         self.precision, self.device = precision, device
-        self.batch = Batch([self.plan] * self.count, precision=precision, threads=threads,
-                           device=device)
         self.E = [[None] * self.n for _ in range(3)]   # norm, S^x, S^z sites
         for r in range(rows):
             for c in range(cols):
@@ -46,7 +50,19 @@ class ObservableSet:
                 for k in range(3):
                     self.E[k][r * cols + c] = torch.empty((chi * chi,) * legs,
                                                           dtype=torch.float64, device=device)
-        self.table = self.batch.prepare(self.networks())   # the buffers never move
+        self.batch = self.env = None
+        if mode == "batch":
+            self.plan = tn_plan_grid(rows, cols, chi * chi, order=TN_ORDER_SWEEP_AUTO)
+            self.batch = Batch([self.plan] * self.count, precision=precision, threads=threads,
+                               device=device)
+            self.table = self.batch.prepare(self.networks())   # the buffers never move
+        else:
+            subst = [[k] for k in range(self.n)] * 2 + [[i, j] for i, j in self.pairs]
+            self.env = EnvSet(rows, cols, chi * chi, networks=subst, precision=precision,
+                              device=device)
+            _, sx, sz = self.E
+            repl = sx + sz + [sz[t] for ij in self.pairs for t in ij]
+            self.table = self.env.prepare(self.E[0], repl)
 
     def networks(self):
         """Site lists of every network, in the documented order."""
@@ -72,7 +88,10 @@ class ObservableSet:
                 work += [(A, None, norm[k]), (A, sx, ex[k]), (A, sz, ez[k])]
             self._dl, self._dl_key = tn_double_layer_prepare(work), key
         tn_double_layer(None, stream, prepared=self._dl)
-        results = self.batch.run(None, stream, prepared=self.table)
+        if self.env is not None:
+            results = self.env.run(stream=stream, prepared=self.table)
+        else:
+            results = self.batch.run(None, stream, prepared=self.table)
         mx, mz, czz = tn_observables(results, self.rows, self.cols)
         return {"results": results, "mx": mx, "mz": mz, "czz": czz}
 
@@ -81,6 +100,8 @@ class ObservableSet:
         networks (the candidates must agree bit for bit) and rebuild the
         batch with it; returns the autotuner's report."""
         from . import autotune
+        if self.batch is None:
+            raise ValueError("tune applies to the batch mode")
         self.run(peps, sx, sz)   # builds the double-layer sites the networks point to
         report = autotune.tune_batch([self.plan] * self.count, self.networks(), self.precision,
                                      reps=reps)
@@ -91,4 +112,6 @@ class ObservableSet:
         return report
 
     def close(self):
-        self.batch.close()
+        for h in (self.batch, self.env):
+            if h is not None:
+                h.close()

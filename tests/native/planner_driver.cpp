@@ -1,6 +1,7 @@
 // Drives the C++ planner over every lattice shape 1..12 x 1..12, bond
 // dimensions 1..5 (uniform and mixed), every order and every quadrant split,
-// checking the plan's bookkeeping on the way.  Built with AddressSanitizer and
+// checking the plan's bookkeeping on the way, and every column-sweep cut plan
+// of those shapes.  Built with AddressSanitizer and
 // UndefinedBehaviorSanitizer by tests/test_host_sanitized.py (host code only).
 #include <cstdio>
 #include <cstdlib>
@@ -46,6 +47,76 @@ void run(int r, int c, int D, const int32_t* h, const int32_t* v, int order, int
   check(t.rfind("tnplan v1", 0) == 0, "plan text", r, c, D, order);
 }
 
+// Cut plans of the column sweep (cached environments): the same steps as the
+// full sweep over their columns, a SEED step exactly when they start inside
+// the lattice, rescale slots renumbered from the seed, and left and right
+// cuts at the same column ending in the same bonds in the same order.
+void run_cuts(int r, int c, int D, const int32_t* h, const int32_t* v, long& plans) {
+  tn_grid g{r, c, D, h, v};
+  tn::Plan full;
+  std::string err;
+  if (tn::build_plan(g, TN_ORDER_COLSWEEP, 0, 0, full, err) != TN_OK) return;
+  for (int mirror = 0; mirror < 2; ++mirror)
+    for (int c0 = 0; c0 < c; ++c0)
+      for (int c1 = c0 + 1; c1 <= c; ++c1) {
+        tn::Plan p;
+        if (tn::build_cut_plan(g, mirror, c0, c1, p, err) != TN_OK) {
+          check(false, "cut plan error", r, c, D, 100 + mirror);
+          continue;
+        }
+        ++plans;
+        // entries of the boundary after `cols` local columns: its h bonds
+        auto bnd = [&](int cols) {
+          int64_t e = 1;
+          const int bc = mirror ? c - 1 - cols : cols - 1;
+          for (int rr = 0; rr < r; ++rr) e *= h ? h[rr * (c - 1) + bc] : D;
+          return e;
+        };
+        const int seed = c0 > 0 ? 1 : 0;
+        check(static_cast<int>(p.steps.size()) == seed + (c1 - c0) * r, "cut step count", r, c, D, 100);
+        check(p.is_cut && p.cut_c0 == c0 && p.cut_c1 == c1, "cut fields", r, c, D, 100);
+        if (seed) {
+          check(p.steps[0].kind == tn::STEP_SEED && p.steps[0].rescale == 0 &&
+                    p.steps[0].out == bnd(c0) &&
+                    (mirror || p.steps[0].out == full.steps[static_cast<size_t>(c0) * r - 1].out),
+                "seed step", r, c, D, 100 + mirror);
+        }
+        const int off = c0 > 0 ? c0 - 1 : 0;
+        for (size_t k = seed; k < p.steps.size(); ++k) {
+          const tn::Step& s = p.steps[k];
+          const int j = c0 + static_cast<int>(k - seed) / r;        // local column
+          const int i = static_cast<int>(k - seed) % r;             // local row
+          const int cc = mirror ? c - 1 - j : j;
+          check(s.r == i && s.c == cc, "cut step site", r, c, D, 100 + mirror);
+          const bool resc = (i == r - 1) && j < c - 1;
+          check((s.rescale >= 0) == resc && (!resc || s.rescale == j - off), "cut rescale", r, c,
+                D, 100 + mirror);
+          if (k > 0 && s.kind == tn::STEP_ABSORB)
+            check(s.scale_in == p.steps[k - 1].rescale, "cut scale_in", r, c, D, 100 + mirror);
+          if (!mirror) {
+            const tn::Step& f = full.steps[static_cast<size_t>(c0) * r + (k - seed)];
+            bool same = f.kind == s.kind && f.pre == s.pre && f.K == s.K && f.N == s.N &&
+                        f.post == s.post && f.nperm == s.nperm;
+            for (int a = 0; a < f.nperm; ++a) same = same && f.perm[a] == s.perm[a];
+            check(same, "cut step differs from the full sweep", r, c, D, 100);
+          }
+        }
+        if (c1 < c) check(p.steps.back().out == bnd(c1), "cut boundary entries", r, c, D, 100 + mirror);
+        else check(p.steps.back().out == 1, "cut scalar end", r, c, D, 100 + mirror);
+      }
+  // a left cut ending at column cut q meets the right cut ending there
+  for (int q = 1; q < c; ++q) {
+    tn::Plan a, b;
+    if (tn::build_cut_plan(g, 0, q - 1, q, a, err) != TN_OK ||
+        tn::build_cut_plan(g, 1, c - 1 - q, c - q, b, err) != TN_OK) {
+      check(false, "cut pair error", r, c, D, 102);
+      continue;
+    }
+    check(a.cut_legs == b.cut_legs && static_cast<int>(a.cut_legs.size()) == r, "cut legs differ",
+          r, c, D, 102);
+  }
+}
+
 }  // namespace
 
 int main() {
@@ -66,6 +137,8 @@ int main() {
       for (int order = 0; order < 4; ++order)
         run(r, c, 1, h.empty() ? nullptr : h.data(), v.empty() ? nullptr : v.data(), order, 0, 0,
             plans);
+      for (int D = 1; D <= 3; ++D) run_cuts(r, c, D, nullptr, nullptr, plans);
+      run_cuts(r, c, 1, h.empty() ? nullptr : h.data(), v.empty() ? nullptr : v.data(), plans);
     }
   // invalid grids are rejected, not crashed on
   std::string err;

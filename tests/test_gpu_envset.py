@@ -1,0 +1,161 @@
+"""Cached column environments on the GPU (paper §4: the column sweep passes
+one boundary from column to column; §5: the observable networks equal the
+norm network except at the operator sites), through the C ABI.
+
+Every network of a set is checked against the oracle's full contraction of
+the same network (the base sites with its substitutions), FP64 within 1e-12
+relative in Z, FP32 within 1e-5 in log Z:
+* single sites everywhere, vertical and horizontal pairs, a span over the
+  whole lattice, the empty substitution, on square, wide, tall, one-row,
+  one-column and mixed-dimension lattices;
+* networks whose sites lie in the last column are the full sweep's own
+  arithmetic: bitwise equal to tn_contract_grid's column sweep;
+* a zero site gives Z = 0, a NaN site flags only its network, repeat runs
+  are bitwise equal.
+"""
+import numpy as np
+import pytest
+
+import lattice_inputs as li
+from oracle import contract as OC
+from oracle import plan as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tn():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1908_08553_amd as tn
+    tn.tn_set_option(tn.TN_OPT_KERNEL_IMPL, 0)
+    return tn
+
+
+def dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).cuda()
+
+
+def family(rows, cols, seed, extra=()):
+    """Single sites (every site, or a sample on big lattices), vertical and
+    horizontal pairs, a corner-to-corner span and the empty network."""
+    rng = np.random.default_rng(seed)
+    n = rows * cols
+    singles = list(range(n)) if n <= 40 else sorted(rng.choice(n, 24, replace=False).tolist())
+    nets = [[k] for k in singles]
+    for r in range(rows - 1):
+        c = int(rng.integers(cols))
+        nets.append([r * cols + c, (r + 1) * cols + c])
+    for c in range(cols - 1):
+        r = int(rng.integers(rows))
+        nets.append([r * cols + c + 1, r * cols + c])     # listed right to left on purpose
+    if n > 1:
+        nets.append([0, n - 1])
+    nets.append([])
+    return nets + [list(x) for x in extra]
+
+
+def run_family(tn, rows, cols, D, seed, prec="f64", hdim=None, vdim=None, nets=None):
+    base = li.uniform(rows, cols, D, seed, hdim=hdim, vdim=vdim)
+    repl = li.uniform(rows, cols, D, seed + 1000, hdim=hdim, vdim=vdim)
+    nets = family(rows, cols, seed) if nets is None else nets
+    es = tn.EnvSet(rows, cols, D, hdim=hdim, vdim=vdim, networks=nets, precision=prec)
+    print(f"[gpu] envset {rows}x{cols} D={D} {prec}: {len(nets)} networks", flush=True)
+    got = es.run([dev(s) for s in base], [dev(repl[i]) for n in nets for i in n])
+    es.close()
+    return base, repl, nets, got
+
+
+def expected(base, repl, rows, cols, net):
+    sites = list(base)
+    for i in net:
+        sites[i] = repl[i]
+    return OC.contract_grid(sites, rows, cols, P.COLSWEEP)
+
+
+def check(got, ref, prec):
+    assert got.status == 0 and got.sign == ref.sign
+    if prec == "f64":
+        assert abs(got.log_abs - ref.log_abs) <= 1e-12 * max(1.0, abs(ref.log_abs)), (got, ref)
+    else:
+        assert abs(got.log_abs - ref.log_abs) <= 1e-5 * max(1.0, abs(ref.log_abs)), (got, ref)
+
+
+@pytest.mark.parametrize("rows,cols,D", [(4, 5, 3), (6, 6, 4), (3, 8, 2), (8, 3, 2), (1, 6, 3),
+                                         (6, 1, 3), (1, 1, 4), (2, 2, 2), (5, 4, 1)])
+def test_envset_matches_oracle(tn, rows, cols, D):
+    base, repl, nets, got = run_family(tn, rows, cols, D, rows * 10 + cols)
+    ref0 = OC.contract_grid(base, rows, cols, P.COLSWEEP)
+    check(got[0], ref0, "f64")
+    for net, g in zip(nets, got[1:]):
+        check(g, expected(base, repl, rows, cols, net), "f64")
+
+
+def test_envset_mixed_dimensions(tn):
+    rows, cols = 5, 6
+    rng = np.random.default_rng(4)
+    h = rng.integers(1, 5, size=(rows, cols - 1))
+    v = rng.integers(1, 5, size=(rows - 1, cols))
+    base, repl, nets, got = run_family(tn, rows, cols, 0, 4, hdim=h, vdim=v)
+    for net, g in zip(nets, got[1:]):
+        check(g, expected(base, repl, rows, cols, net), "f64")
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_envset_reduced_precision(tn, prec):
+    rows, cols, D = 6, 6, 4
+    base, repl, nets, got = run_family(tn, rows, cols, D, 8, prec=prec)
+    check(got[0], OC.contract_grid(base, rows, cols, P.COLSWEEP), prec)
+    for net, g in zip(nets, got[1:]):
+        check(g, expected(base, repl, rows, cols, net), prec)
+
+
+def test_last_column_networks_equal_full_sweep_bitwise(tn):
+    # with every substituted site in the last column a network is the full
+    # column sweep's own arithmetic
+    rows, cols, D = 6, 7, 4
+    nets = [[r * cols + cols - 1] for r in range(rows)] + [[cols - 1, 2 * cols - 1], []]
+    for prec in ("f64", "f32"):
+        base, repl, nets_, got = run_family(tn, rows, cols, D, 3, prec=prec, nets=nets)
+        plan = tn.tn_plan_grid(rows, cols, D, order=P.COLSWEEP)
+        for net, g in zip([[]] + nets, got):
+            sites = list(base)
+            for i in net:
+                sites[i] = repl[i]
+            full = tn.contract_grid(plan, [dev(s) for s in sites], prec)
+            assert (g.mantissa, g.exp2_sum, g.sign) == (full.mantissa, full.exp2_sum, full.sign)
+
+
+def test_zero_nan_and_repeat(tn):
+    import torch
+    rows, cols, D = 4, 5, 3
+    base = li.uniform(rows, cols, D, 11)
+    repl = li.uniform(rows, cols, D, 12)
+    repl[6] = np.zeros_like(repl[6])
+    repl[13] = repl[13].copy()
+    repl[13].flat[1] = np.nan
+    nets = [[6], [13], [2], [6, 7], [0, 19]]
+    es = tn.EnvSet(rows, cols, D, networks=nets)
+    prep = es.prepare([dev(s) for s in base], [dev(repl[i]) for n in nets for i in n])
+    a = es.run(prepared=prep)
+    b = es.run(prepared=prep)
+    es.close()
+    assert a[1].sign == 0 and a[1].status == 0
+    assert a[2].status == tn.TN_ENONFINITE
+    assert a[4].sign == 0
+    for net, g in zip([[2], [0, 19]], [a[3], a[5]]):
+        check(g, expected(base, repl, rows, cols, net), "f64")
+    for x, y in zip(a, b):
+        assert (x.status, x.sign, x.mantissa, x.exp2_sum) == (y.status, y.sign, y.mantissa, y.exp2_sum)
+    torch.cuda.synchronize()
+
+
+def test_envset_larger_lattice_sampled(tn):
+    # 10 x 10, D = 4 (boundaries of 4^11 entries, the column-chunk kernels):
+    # a sample of networks against the oracle
+    rows, cols, D = 10, 10, 4
+    nets = [[0], [55], [99], [44, 54], [72, 73], [9, 90]]
+    base, repl, nets, got = run_family(tn, rows, cols, D, 21, nets=nets)
+    for net, g in zip(nets, got[1:]):
+        check(g, expected(base, repl, rows, cols, net), "f64")

@@ -113,3 +113,25 @@ def test_observable_set_tuned_matches_default(tn, tmp_path, monkeypatch):
     obs.close()
     assert report["best"] in (256, 512, 1024)
     assert a["mx"] == b["mx"] and a["mz"] == b["mz"] and a["czz"] == b["czz"]
+
+
+@pytest.mark.parametrize("rows,cols,chi,seed", [(3, 3, 2, 0), (4, 4, 2, 1), (3, 5, 2, 2),
+                                                (5, 3, 2, 5), (6, 6, 2, 3), (4, 4, 3, 4)])
+def test_observable_set_env_mode_matches_oracle(tn, rows, cols, chi, seed):
+    # cached column environments: each observable network absorbs the one or
+    # two columns of its operator sites and closes against the right
+    # environment; same values as full contractions
+    from paper_1908_08553_amd.peps import ObservableSet
+    peps = li.peps(rows, cols, chi, seed)
+    want = Q.expectation_values(peps, rows, cols, SX, SZ, P.COLSWEEP)
+    obs = ObservableSet(rows, cols, chi, precision="f64", mode="env")
+    print(f"[gpu] env observables {rows}x{cols} chi={chi}: {obs.count} networks", flush=True)
+    got = obs.run([dev(A) for A in peps], dev(SX), dev(SZ))
+    again = obs.run([dev(A) for A in peps], dev(SX), dev(SZ))
+    obs.close()
+    norm = got["results"][0]
+    assert norm.status == 0 and norm.sign == want["norm"].sign
+    assert abs(norm.log_abs - want["norm"].log_abs) <= 1e-12 * abs(want["norm"].log_abs)
+    for key in ("mx", "mz", "czz"):
+        np.testing.assert_allclose(got[key], want[key], rtol=0, atol=1e-11, err_msg=key)
+        assert got[key] == again[key]

@@ -2,8 +2,10 @@
 with g++, no device code):
 
 * the C++ planner: every lattice 1..12 x 1..12, bond dimensions 1..5 and
-  mixed, every order and quadrant split, with the plan's bookkeeping checked
-  (tests/native/planner_driver.cpp);
+  mixed, every order and quadrant split, with the plan's bookkeeping checked,
+  and every column-sweep cut plan (cached environments: same steps as the
+  full sweep, seed and rescale slots, left and right cuts ending in the same
+  bonds) (tests/native/planner_driver.cpp);
 * the served loop's admission arena (first fit with coalescing): randomized
   alloc/release against a brute-force model (tests/native/arena_driver.cpp).
 """
