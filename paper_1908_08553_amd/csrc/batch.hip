@@ -205,7 +205,8 @@ __global__ __launch_bounds__(kChainThreads) void chain_kernel(ChainLaunch a) {
     s.scale_in = x.scale_slot >= 0;
     double mx = 0.0;
     int b = 0;
-    run_step(s, c.buf[cur], c.buf[cur ^ 1], shift, a.arith, a.st, wave, nw, mx, b);
+    const void* in = (j == 0 && c.in0) ? c.in0 : c.buf[cur];
+    run_step(s, in, c.buf[cur ^ 1], shift, a.arith, a.st, wave, nw, mx, b);
     if (x.rescale_slot >= 0) {
       for (int off = 32; off > 0; off >>= 1) {
         mx = fmax(mx, __shfl_xor(mx, off));

@@ -390,23 +390,22 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
   tg.site_bad = tg.site_exp + nsteps;
   tg.flags = &state->flags;
   tg.counter = nullptr;
+  if (seeded) {
+    tg.seed_rec = io->seed_rec;
+    tg.seed_slot = p.steps[0].rescale;
+    tg.e_bias = &state->e_bias;
+  }
   TN_HIP(launch_stage(reinterpret_cast<const StageDesc*>(base + L.descs),
                       static_cast<int32_t>(nsteps), sa, tg, stream));
   timer.after("stage", 8.0 * 2 * static_cast<double>(p.total_site_entries), 0.0);
-  if (seeded) {
-    const Step& s0 = p.steps[0];
-    const int32_t f64 = L.out_type[0] == EL_F64;
-    timer.before();
-    TN_HIP(launch_env_seed(io->seed, base + L.buf[0][0], s0.out, f64, io->seed_rec,
-                           slot_exp + s0.rescale, state, stream));
-    timer.after("env_seed", 2.0 * static_cast<double>(s0.out) * (f64 ? 8.0 : 4.0), 0.0);
-  }
 
   const int32_t arith = prec == TN_PREC_F64 ? AR_F64 : (prec == TN_PREC_F32 ? AR_F32 : AR_BF16X3);
   // Steps of different units are independent: walk step index t across the
   // units and launch same-kind steps of several units together.
   const size_t nu = p.units.size();
   std::vector<int32_t> final_buf(nu, 0), cur(nu, 0);
+  // a seeded cut plan's first absorption reads the supplied boundary in place
+  const void* first_in = seeded ? io->seed : nullptr;
   auto args_of = [&](size_t u, int32_t k) {
     const Step& s = p.steps[k];
     AbsorbArgs a;
@@ -501,11 +500,14 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
     for (size_t u : units) {
       if (t >= acts[u].size()) continue;
       const Action& ac = acts[u][t];
-      const AbsorbArgs a = args_of(u, ac.k);
+      AbsorbArgs a = args_of(u, ac.k);
+      const void* in0 = (u == 0 && t == 0) ? first_in : nullptr;
+      if (in0) a.in = in0;
       if (ac.kind == ACT_CHAIN) {
         ChainUnit& x = chains[nch++];
         x.buf[0] = base + L.buf[u][0];
         x.buf[1] = base + L.buf[u][1];
+        x.in0 = in0;
         x.cur = cur[u];
         x.n = ac.len;
         for (int32_t j = 0; j < ac.len; ++j) {
@@ -645,12 +647,13 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
     if (io->cap) {
       const int32_t f64 = L.out_type[kl] == EL_F64;
       timer.before();
-      TN_HIP(launch_env_cap(fin, io->cap, sl.out, f64, slot_last, io->cap_rec, io->partials, state,
+      TN_HIP(launch_env_cap(fin, io->cap, sl.out, f64, slot_last, io->cap_rec, io->partials,
                             stream));
       timer.after("env_cap", 2.0 * static_cast<double>(sl.out) * (f64 ? 8.0 : 4.0),
                   2.0 * static_cast<double>(sl.out));
       timer.before();
-      TN_HIP(launch_finalize(state, nullptr, copy, io->partials, env_cap_blocks(sl.out), stream));
+      TN_HIP(launch_finalize(state, nullptr, copy, io->partials, env_cap_blocks(sl.out), stream,
+                             io->cap_rec));
       timer.after("finalize", 0.0, 0.0);
     } else {
       *io->tap = fin;

@@ -87,6 +87,13 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageDesc* __restri
       if (tg.flags) *tg.flags = 0;
       if (tg.counter) *tg.counter = 0;
     }
+    if (tg.seed_rec) {
+      __syncthreads();   // the slot initialisation above is complete
+      if (threadIdx.x == 0) {
+        tg.slot_exp[tg.seed_slot] = tg.seed_rec->e;
+        *tg.e_bias = tg.seed_rec->bias;
+      }
+    }
   }
   double m = 0.0;
   int bad = 0;
@@ -272,17 +279,17 @@ __global__ __launch_bounds__(kBlock) void ring_generic(
 }
 
 // --------------------------------------------------------------- finalize
-__global__ __launch_bounds__(kBlock) void finalize_kernel(DevState* state, const double* scalar,
-                                                          const double* partials, int64_t np,
-                                                          tn_result* copy) {
+// Block-wide totals, valid in thread 0: the fixed-order sum of `np` partials
+// (strided per thread, then a tree), the exponent sum over the rescale slots
+// and step exponents, and the non-finite flag.
+__device__ void block_totals(const DevState* state, const double* partials, int64_t np,
+                             double& sum, int64_t& E_out, int32_t& bad_out) {
   __shared__ double red[kBlock];
   __shared__ int64_t red_e[kBlock];
   __shared__ int32_t red_bad[kBlock];
   const int32_t* slot_exp = reinterpret_cast<const int32_t*>(state + 1);
   const int32_t* site_exp = slot_exp + state->n_slots;
   const int32_t* site_bad = site_exp + state->n_steps;
-  // every thread takes a strided share of the partials, rescale slots and
-  // step exponents; the double sums keep one fixed order (strided, then a tree)
   double s = 0.0;
   if (partials) {
     for (int64_t i = threadIdx.x; i < np; i += blockDim.x) s += partials[i];
@@ -310,45 +317,41 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(DevState* state, const
     }
     __syncthreads();
   }
+  sum = red[0];
+  E_out = red_e[0];
+  bad_out = red_bad[0];
+}
+
+__global__ __launch_bounds__(kBlock) void finalize_kernel(DevState* state, const double* scalar,
+                                                          const double* partials, int64_t np,
+                                                          const EnvRec* cap, tn_result* copy) {
+  double sum;
+  int64_t E;
+  int32_t bad;
+  block_totals(state, partials, np, sum, E, bad);
   if (threadIdx.x != 0) return;
-  const double mval = partials ? red[0] : *scalar;
-  const tn_result r = dev::assemble_result(mval, red_e[0] + state->e_bias,
-                                           red_bad[0] | (state->flags & 1));
+  const double mval = partials ? sum : *scalar;
+  E += state->e_bias;
+  if (cap) {
+    // the boundary the cap dot closed against, scaled by 2^-e in the dot
+    const int32_t e = cap->e;
+    if (e == kExpBad) bad = 1;
+    E += cap->bias + ((e == kExpZero || e == kExpBad) ? 0 : e);
+  }
+  const tn_result r = dev::assemble_result(mval, E, bad | (state->flags & 1));
   state->result = r;
   if (copy) *copy = r;
 }
 
 // ------------------------------------------------------------ environments
-__global__ __launch_bounds__(kBlock) void env_seed_kernel(const void* __restrict__ src,
-                                                          void* __restrict__ dst, int64_t n,
-                                                          int32_t f64, const EnvRec* rec,
-                                                          int32_t* slot, DevState* state) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (f64) {
-    const double* s = static_cast<const double*>(src);
-    double* d = static_cast<double*>(dst);
-    for (int64_t i = i0; i < n; i += stride) d[i] = s[i];
-  } else {
-    const float* s = static_cast<const float*>(src);
-    float* d = static_cast<float*>(dst);
-    for (int64_t i = i0; i < n; i += stride) d[i] = s[i];
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *slot = rec->e;
-    state->e_bias = rec->bias;
-  }
-}
-
-constexpr int64_t kCapChunk = 8192;   // entries per block of the cap dot
-constexpr int64_t kCapBlocks = 1024;
+constexpr int64_t kCapChunk = 1024;   // least entries per block of the cap dot
+constexpr int64_t kCapBlocks = 2048;  // most blocks
 
 __global__ __launch_bounds__(kBlock) void env_cap_kernel(const void* __restrict__ B,
                                                          const void* __restrict__ Rv, int64_t n,
                                                          int64_t chunk, int32_t f64,
                                                          const int32_t* slot_b, const EnvRec* rec,
-                                                         double* __restrict__ partials,
-                                                         DevState* state) {
+                                                         double* __restrict__ partials) {
   __shared__ double red[kBlock];
   const int32_t er_raw = rec->e;
   const int32_t er = (er_raw == kExpZero || er_raw == kExpBad) ? 0 : er_raw;
@@ -373,53 +376,25 @@ __global__ __launch_bounds__(kBlock) void env_cap_kernel(const void* __restrict_
     if (static_cast<int>(threadIdx.x) < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    partials[blockIdx.x] = red[0];
-    if (blockIdx.x == 0) {
-      state->e_bias += rec->bias + er;
-      if (er_raw == kExpBad) state->flags |= 1;
-    }
-  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
 __global__ __launch_bounds__(kBlock) void env_tap_kernel(DevState* state, const int32_t* slot_last,
                                                          EnvRec* rec) {
-  __shared__ int64_t red_e[kBlock];
-  __shared__ int32_t red_bad[kBlock];
-  const int32_t* slot_exp = reinterpret_cast<const int32_t*>(state + 1);
-  const int32_t* site_exp = slot_exp + state->n_slots;
-  const int32_t* site_bad = site_exp + state->n_steps;
-  int64_t E = 0;
-  int32_t bad = 0;
-  for (int i = threadIdx.x; i < state->n_slots; i += blockDim.x) {
-    const int32_t e = slot_exp[i];
-    if (e == kExpBad) bad = 1;
-    else if (e != kExpZero) E += e;
-  }
-  for (int i = threadIdx.x; i < state->n_steps; i += blockDim.x) {
-    E += site_exp[i];
-    bad |= site_bad[i];
-  }
-  red_e[threadIdx.x] = E;
-  red_bad[threadIdx.x] = bad;
-  __syncthreads();
-  for (int st = kBlock / 2; st > 0; st >>= 1) {
-    if (static_cast<int>(threadIdx.x) < st) {
-      red_e[threadIdx.x] += red_e[threadIdx.x + st];
-      red_bad[threadIdx.x] |= red_bad[threadIdx.x + st];
-    }
-    __syncthreads();
-  }
+  double unused;
+  int64_t E;
+  int32_t bad;
+  block_totals(state, nullptr, 0, unused, E, bad);
   if (threadIdx.x != 0) return;
   const int32_t e = *slot_last;
   EnvRec out;
   out.pad = 0;
-  if (red_bad[0] || (state->flags & 1) || e == kExpBad) {
+  if (bad || (state->flags & 1) || e == kExpBad) {
     out.bias = 0;
     out.e = kExpBad;
   } else {
     out.e = e;
-    out.bias = red_e[0] + state->e_bias - (e == kExpZero ? 0 : e);
+    out.bias = E + state->e_bias - (e == kExpZero ? 0 : e);
   }
   *rec = out;
 }
@@ -522,17 +497,10 @@ hipError_t launch_ring(const RingArgs& a, hipStream_t stream, const char** kname
 }
 
 hipError_t launch_finalize(DevState* state, const double* scalar, tn_result* copy,
-                           const double* partials, int64_t n_partials, hipStream_t stream) {
+                           const double* partials, int64_t n_partials, hipStream_t stream,
+                           const EnvRec* cap) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kBlock), 0, stream, state, scalar, partials,
-                     n_partials, copy);
-  return hipGetLastError();
-}
-
-hipError_t launch_env_seed(const void* src, void* dst, int64_t n, int32_t f64, const EnvRec* rec,
-                           int32_t* slot, DevState* state, hipStream_t stream) {
-  const int64_t blocks = std::min<int64_t>(std::max<int64_t>((n + kBlock - 1) / kBlock, 1), 2048);
-  hipLaunchKernelGGL(env_seed_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, stream,
-                     src, dst, n, f64, rec, slot, state);
+                     n_partials, cap, copy);
   return hipGetLastError();
 }
 
@@ -543,11 +511,11 @@ int64_t env_cap_blocks(int64_t n) {
 
 hipError_t launch_env_cap(const void* B, const void* Rv, int64_t n, int32_t f64,
                           const int32_t* slot_b, const EnvRec* rec, double* partials,
-                          DevState* state, hipStream_t stream) {
+                          hipStream_t stream) {
   const int64_t chunk = std::max<int64_t>(kCapChunk, (n + kCapBlocks - 1) / kCapBlocks);
   const int64_t blocks = env_cap_blocks(n);
   hipLaunchKernelGGL(env_cap_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, stream,
-                     B, Rv, n, chunk, f64, slot_b, rec, partials, state);
+                     B, Rv, n, chunk, f64, slot_b, rec, partials);
   return hipGetLastError();
 }
 

@@ -30,6 +30,11 @@ struct StageTargets {
   int32_t n_slots;
   int32_t* flags;       // nullable
   int32_t* counter;     // nullable (work counter of the batched kernel)
+  // A cut plan's supplied boundary: slot_exp[seed_slot] = seed_rec->e and
+  // *e_bias = seed_rec->bias (seed_rec nullable).
+  const EnvRec* seed_rec = nullptr;
+  int32_t seed_slot = 0;
+  int64_t* e_bias = nullptr;
 };
 
 hipError_t launch_stage(const StageDesc* descs, int32_t n_steps, StagedArrays st,
@@ -184,6 +189,7 @@ struct ChainStep {
 };
 struct ChainUnit {
   void* buf[2];
+  const void* in0;      // input of the first step instead of buf[cur] (nullable)
   int32_t cur, n;
   ChainStep s[kChainMax];
 };
@@ -206,23 +212,21 @@ bool double_layer_ok(const DoubleLayerSite& s);
 hipError_t launch_double_layer(const DoubleLayerSite* sites, int32_t n, hipStream_t stream);
 
 // Writes state->result from the final scalar (or the sum of `n_partials`
-// partials), the site exponents, the rescale slots and state->e_bias; with
-// `copy` the record is also written there.
+// partials), the site exponents, the rescale slots and state->e_bias, plus
+// the exponent of `cap` (the boundary a cap dot closed against; nullable);
+// with `copy` the record is also written there.
 hipError_t launch_finalize(DevState* state, const double* scalar, tn_result* copy,
-                           const double* partials, int64_t n_partials, hipStream_t stream);
+                           const double* partials, int64_t n_partials, hipStream_t stream,
+                           const EnvRec* cap = nullptr);
 
-// Cut plans (cached environments).  Seed: copy the supplied boundary `src`
-// (n entries, float64 if f64 else float32) into `dst`, put rec->e in the
-// SEED step's rescale slot and rec->bias in state->e_bias.
-hipError_t launch_env_seed(const void* src, void* dst, int64_t n, int32_t f64, const EnvRec* rec,
-                           int32_t* slot, DevState* state, hipStream_t stream);
-// Cap: partial sums of sum_i (B[i] 2^-eb)(Rv[i] 2^-er) with eb = *slot_b and
-// er = rec->e, one per block of env_cap_blocks(n) blocks (fixed order), and
-// rec's exponent added to state->e_bias; finalize then sums the partials.
+// Cut plans (cached environments).  Cap: partial sums of
+// sum_i (B[i] 2^-eb)(Rv[i] 2^-er) with eb = *slot_b and er = rec->e, one per
+// block of env_cap_blocks(n) blocks; launch_finalize(..., cap = rec) sums
+// them in a fixed order.
 int64_t env_cap_blocks(int64_t n);
 hipError_t launch_env_cap(const void* B, const void* Rv, int64_t n, int32_t f64,
                           const int32_t* slot_b, const EnvRec* rec, double* partials,
-                          DevState* state, hipStream_t stream);
+                          hipStream_t stream);
 // Tap: the record of the boundary a cut plan ends in, whose largest-magnitude
 // exponent is *slot_last (one block; the exponent sums of finalize).
 hipError_t launch_env_tap(DevState* state, const int32_t* slot_last, EnvRec* rec,
