@@ -431,7 +431,7 @@ def main():
             log(f"served: {json.dumps(legs['served'])}")
     head_kernels = head.pop("kernels")
     line = {
-        "metric": "exact contraction GFLOP/s (12x12 D=4, paper's heuristic order)",
+        "metric": "exact contraction GFLOP/s + contractions/s, p50/p99 latency; FP64 vs split-prec",
         "value": head["gflops"],
         "unit": "GFLOP/s",
         "n_gpus": 1,
