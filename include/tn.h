@@ -281,8 +281,9 @@ tn_status tn_envset_create(const tn_grid* grid, int32_t precision, int32_t n,
  * DEVICE pointers to the base sites (float64, canonical legs); subst: one
  * DEVICE pointer per entry of subst_site, the replacing site (same shape as
  * the site it replaces).  All borrowed for the call.  outs[0] is the base
- * network, outs[1 + k] network k.  Enqueued on hip_stream; blocks until the
- * results are copied back.  Errors: TN_EINVAL (NULL pointer), TN_EDEVICE,
+ * network, outs[1 + k] network k.  Issued on hip_stream and on the set's own
+ * streams (TN_OPT_ENV_STREAMS), which are joined back into hip_stream;
+ * blocks until the results are copied back.  Errors: TN_EINVAL (NULL pointer), TN_EDEVICE,
  * TN_ENONFINITE (a network met a non-finite value: its outs[] status says
  * so, the other results are valid).                                         */
 tn_status tn_envset_run(tn_envset* set, const double* const* base, const double* const* subst,
@@ -383,6 +384,16 @@ tn_status tn_server_destroy(tn_server* server);
  *                        per-step arithmetic as one launch per step
  *                        (bitwise-identical results); 0 = one launch each. */
 #define TN_OPT_CHAIN_STEPS 5
+/*   TN_OPT_ENV_STREAMS : streams a tn_envset uses, 1..4 (default 4), read
+ *                        when its workspace is sized and when it is created:
+ *                        with 2 or more the right environments are swept on a
+ *                        second stream concurrently with the left ones, and
+ *                        the networks are dealt round-robin over all of them,
+ *                        each stream with its own region of the workspace;
+ *                        the set creates the extra streams (each takes one
+ *                        of the process's hardware queues while the set
+ *                        lives) and joins them into the caller's stream.   */
+#define TN_OPT_ENV_STREAMS 6
 tn_status tn_set_option(int32_t option, int64_t value);
 
 /* ------------------------------------------------------------ profiling

@@ -353,6 +353,11 @@ tn_status tn_set_option(int32_t option, int64_t value) {
     tn::set_absorb_policy(static_cast<int32_t>(value));
     return TN_OK;
   }
+  if (option == TN_OPT_ENV_STREAMS) {
+    if (value < 1 || value > 4) return fail(TN_EINVAL, "TN_OPT_ENV_STREAMS must be 1..4");
+    tn::set_env_streams(static_cast<int32_t>(value));
+    return TN_OK;
+  }
   if (option == TN_OPT_CHAIN_STEPS) {
     if (value < 0 || value > 1) return fail(TN_EINVAL, "TN_OPT_CHAIN_STEPS must be 0 or 1");
     tn::set_chain_steps(static_cast<int32_t>(value));

@@ -13,11 +13,12 @@
 // sweep up to column c1-1, then one boundary contraction instead of the
 // remaining columns.  With c1 = cols it is the full sweep's own arithmetic.
 //
-// Everything is issued on the caller's stream without waiting, except the
-// final result copy: the left and right environment sweeps (one cut plan per
-// column, each in its own workspace region, which keeps its ending boundary
-// for the rest of the run), the base network, then every network in turn
-// through one shared region.
+// Everything is issued without waiting, except the final result copy: the
+// left and right environment sweeps (one cut plan per column, each in its own
+// workspace region, which keeps its ending boundary for the rest of the run)
+// on the caller's stream and a side stream, then the base network and every
+// network, dealt round-robin over S streams (each with its own region), all
+// joined back into the caller's stream.
 #include "envset.hpp"
 
 #include <hip/hip_runtime.h>
@@ -43,12 +44,24 @@ struct EnvSetImpl {
   std::vector<int32_t> net_plan;            // n + 1 entries (0: base network)
   std::vector<int32_t> sub_first, sub_count, sub_site;
   std::vector<size_t> left_off, right_off;
-  size_t shared_off = 0, shared_bytes = 0, recs_off = 0, partials_off = 0, results_off = 0;
+  int32_t S = 1;                            // streams the networks are spread over
+  size_t shared_off = 0, shared_bytes = 0, recs_off = 0, partials_off = 0, partials_bytes = 0,
+         results_off = 0;
   size_t total = 0;
   char* ws = nullptr;
   std::vector<std::unique_ptr<HostKeep>> keeps;
   std::vector<const double*> sites;         // scratch site table of one network
+  std::vector<hipStream_t> side;            // S - 1 streams beside the caller's
+  std::vector<hipEvent_t> ev;               // start, left done, right done, S stream ends
+
+  ~EnvSetImpl() {
+    for (hipStream_t st : side) (void)hipStreamDestroy(st);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
 };
+
+int32_t g_env_streams = 4;
+void set_env_streams(int32_t n) { g_env_streams = n; }
 
 namespace {
 
@@ -132,6 +145,7 @@ tn_status layout(EnvSetImpl& es, const tn_grid& grid, int32_t n, const int32_t* 
       return TN_EINVAL;
     }
   }
+  es.S = g_env_streams;
   size_t off = 0;
   for (const Plan& p : es.left) { es.left_off.push_back(off); off += align_up(make_layout(p, es.prec).total); }
   for (const Plan& p : es.right) { es.right_off.push_back(off); off += align_up(make_layout(p, es.prec).total); }
@@ -142,11 +156,12 @@ tn_status layout(EnvSetImpl& es, const tn_grid& grid, int32_t n, const int32_t* 
     es.shared_bytes = std::max(es.shared_bytes, align_up(make_layout(p, es.prec).total));
     if (p.cut_c1 < C) parts = std::max(parts, env_cap_blocks(p.steps.back().out));
   }
-  off += es.shared_bytes;
+  off += es.shared_bytes * es.S;
   es.recs_off = off;
   off = align_up(off + sizeof(EnvRec) * static_cast<size_t>(std::max(2 * (C - 1), 1)));
   es.partials_off = off;
-  off = align_up(off + sizeof(double) * static_cast<size_t>(parts));
+  es.partials_bytes = align_up(sizeof(double) * static_cast<size_t>(parts));
+  off += es.partials_bytes * es.S;
   es.results_off = off;
   off = align_up(off + sizeof(tn_result) * static_cast<size_t>(n + 1));
   es.total = off;
@@ -181,6 +196,22 @@ tn_status envset_create(const tn_grid& grid, int32_t prec, int32_t n, const int3
     return TN_ENOMEM;
   }
   es->ws = static_cast<char*>(ws);
+  for (int32_t i = 0; i + 1 < es->S; ++i) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      err = "hipStreamCreateWithFlags failed";
+      return TN_EDEVICE;
+    }
+    es->side.push_back(st);
+  }
+  for (int32_t i = 0; es->S > 1 && i < 3 + es->S; ++i) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      err = "hipEventCreateWithFlags failed";
+      return TN_EDEVICE;
+    }
+    es->ev.push_back(e);
+  }
   const size_t calls = es->left.size() + es->right.size() + static_cast<size_t>(n) + 1;
   for (size_t i = 0; i < calls; ++i) es->keeps.push_back(std::make_unique<HostKeep>());
   es->keeps.push_back(std::make_unique<HostKeep>());   // result records
@@ -200,60 +231,96 @@ tn_status envset_run(EnvSetImpl* es, const double* const* base, const double* co
 
   char* ws = es->ws;
   EnvRec* recs = reinterpret_cast<EnvRec*>(ws + es->recs_off);
-  double* partials = reinterpret_cast<double*>(ws + es->partials_off);
   tn_result* results = reinterpret_cast<tn_result*>(ws + es->results_off);
-  LaunchTimer timer(stream);
+  const int32_t S = es->S;
+  std::vector<hipStream_t> streams{stream};
+  for (hipStream_t st : es->side) streams.push_back(st);
+  std::vector<std::unique_ptr<LaunchTimer>> timers;
+  for (hipStream_t st : streams) timers.push_back(std::make_unique<LaunchTimer>(st));
+  // one stream needs no events: stream order alone serialises the work
+  const bool multi = S > 1;
+  hipEvent_t ev_start = multi ? es->ev[0] : nullptr, ev_left = multi ? es->ev[1] : nullptr,
+             ev_right = multi ? es->ev[2] : nullptr;
   size_t call = 0;
   const int32_t ne = C - 1;
   std::vector<const void*> ltap(ne, nullptr), rtap(ne, nullptr);
-
-  // environments: left to right and right to left, one column per call
-  for (int32_t side = 0; side < 2; ++side) {
-    const std::vector<Plan>& plans = side ? es->right : es->left;
-    const std::vector<size_t>& offs = side ? es->right_off : es->left_off;
-    std::vector<const void*>& taps = side ? rtap : ltap;
-    for (int32_t j = 0; j < ne; ++j) {
-      CutIO io;
-      if (j > 0) { io.seed = taps[j - 1]; io.seed_rec = recs + side * ne + j - 1; }
-      io.tap = &taps[j];
-      io.tap_rec = recs + side * ne + j;
-      const Plan& p = plans[j];
-      const tn_status s = enqueue(p, base, true, es->prec, ws + offs[j],
-                                  make_layout(p, es->prec).total, stream, *es->keeps[call++],
-                                  timer, err, nullptr, nullptr, &io);
-      if (s != TN_OK) return s;
-    }
-  }
-  // the base network, then every network, through the shared region
-  for (int32_t k = 0; k <= n; ++k) {
-    const Plan& p = es->cuts[es->net_plan[k]];
-    for (int32_t s = 0; s < R * C; ++s) es->sites[s] = base[s];
-    if (k > 0) {
-      const int32_t f = es->sub_first[k - 1];
-      for (int32_t i = 0; i < es->sub_count[k - 1]; ++i) es->sites[es->sub_site[f + i]] = subst[f + i];
-    }
-    CutIO io;
-    if (p.cut_c0 > 0) { io.seed = ltap[p.cut_c0 - 1]; io.seed_rec = recs + p.cut_c0 - 1; }
-    if (p.cut_c1 < C) {
-      const int32_t j = C - 1 - p.cut_c1;
-      io.cap = rtap[j];
-      io.cap_rec = recs + ne + j;
-      io.partials = partials;
-    }
-    io.result = results + k;
-    const tn_status s = enqueue(p, es->sites.data(), true, es->prec, ws + es->shared_off,
-                                es->shared_bytes, stream, *es->keeps[call++], timer, err, nullptr,
-                                nullptr, &io);
-    if (s != TN_OK) return s;
-  }
   hipError_t e = hipSuccess;
+  tn_status status = TN_OK;
+
+  // Left environments on the caller's stream, right ones on the first side
+  // stream (one column per call); the networks wait for both and are dealt
+  // round-robin over the streams, each stream with its own region.
+  auto issue = [&]() -> tn_status {
+    if (multi) e = hipEventRecord(ev_start, stream);
+    for (int32_t i = 1; i < S && e == hipSuccess; ++i) e = hipStreamWaitEvent(streams[i], ev_start, 0);
+    if (e != hipSuccess) { err = hipGetErrorString(e); return TN_EDEVICE; }
+    for (int32_t side = 0; side < 2; ++side) {
+      const std::vector<Plan>& plans = side ? es->right : es->left;
+      const std::vector<size_t>& offs = side ? es->right_off : es->left_off;
+      std::vector<const void*>& taps = side ? rtap : ltap;
+      const int32_t si = (side && S > 1) ? 1 : 0;
+      for (int32_t j = 0; j < ne; ++j) {
+        CutIO io;
+        if (j > 0) { io.seed = taps[j - 1]; io.seed_rec = recs + side * ne + j - 1; }
+        io.tap = &taps[j];
+        io.tap_rec = recs + side * ne + j;
+        const Plan& p = plans[j];
+        const tn_status st = enqueue(p, base, true, es->prec, ws + offs[j],
+                                     make_layout(p, es->prec).total, streams[si],
+                                     *es->keeps[call++], *timers[si], err, nullptr, nullptr, &io);
+        if (st != TN_OK) return st;
+      }
+      if (multi) e = hipEventRecord(side ? ev_right : ev_left, streams[si]);
+      if (e != hipSuccess) { err = hipGetErrorString(e); return TN_EDEVICE; }
+    }
+    for (int32_t i = 0; multi && i < S && e == hipSuccess; ++i) {
+      e = hipStreamWaitEvent(streams[i], ev_left, 0);
+      if (e == hipSuccess) e = hipStreamWaitEvent(streams[i], ev_right, 0);
+    }
+    if (e != hipSuccess) { err = hipGetErrorString(e); return TN_EDEVICE; }
+    for (int32_t k = 0; k <= n; ++k) {
+      const int32_t si = k % S;
+      const Plan& p = es->cuts[es->net_plan[k]];
+      for (int32_t t = 0; t < R * C; ++t) es->sites[t] = base[t];
+      if (k > 0) {
+        const int32_t f = es->sub_first[k - 1];
+        for (int32_t i = 0; i < es->sub_count[k - 1]; ++i) es->sites[es->sub_site[f + i]] = subst[f + i];
+      }
+      CutIO io;
+      if (p.cut_c0 > 0) { io.seed = ltap[p.cut_c0 - 1]; io.seed_rec = recs + p.cut_c0 - 1; }
+      if (p.cut_c1 < C) {
+        const int32_t j = C - 1 - p.cut_c1;
+        io.cap = rtap[j];
+        io.cap_rec = recs + ne + j;
+        io.partials = reinterpret_cast<double*>(ws + es->partials_off + es->partials_bytes * si);
+      }
+      io.result = results + k;
+      const tn_status st = enqueue(p, es->sites.data(), true, es->prec,
+                                   ws + es->shared_off + es->shared_bytes * si, es->shared_bytes,
+                                   streams[si], *es->keeps[call++], *timers[si], err, nullptr,
+                                   nullptr, &io);
+      if (st != TN_OK) return st;
+    }
+    return TN_OK;
+  };
+  status = issue();
+  // join every side stream back into the caller's stream, also after an error
+  for (int32_t i = 1; i < S; ++i) {
+    hipError_t e2 = hipEventRecord(es->ev[3 + i], streams[i]);
+    if (e2 == hipSuccess) e2 = hipStreamWaitEvent(stream, es->ev[3 + i], 0);
+    if (e2 != hipSuccess && status == TN_OK) { err = hipGetErrorString(e2); status = TN_EDEVICE; }
+  }
+  if (status != TN_OK) {
+    (void)hipStreamSynchronize(stream);
+    return status;
+  }
   HostKeep& rk = *es->keeps[call];
   tn_result* staged = reinterpret_cast<tn_result*>(rk.block(sizeof(tn_result) * (n + 1), &e));
   if (!staged) { err = std::string("hipHostMalloc: ") + hipGetErrorString(e); return TN_ENOMEM; }
   e = hipMemcpyAsync(staged, results, sizeof(tn_result) * (n + 1), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) { err = hipGetErrorString(e); return TN_EDEVICE; }
-  timer.flush();
+  for (auto& t : timers) t->flush();
   std::memcpy(outs, staged, sizeof(tn_result) * (n + 1));
   for (int32_t k = 0; k <= n; ++k)
     if (outs[k].status != TN_OK) {

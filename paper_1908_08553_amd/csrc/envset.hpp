@@ -26,4 +26,9 @@ tn_status envset_run(EnvSetImpl* es, const double* const* base, const double* co
                      hipStream_t stream, tn_result* outs, std::string& err);
 void envset_destroy(EnvSetImpl* es);
 
+// Streams an environment set spreads its networks over (1..4), read by
+// envset_workspace and envset_create.
+void set_env_streams(int32_t n);
+extern int32_t g_env_streams;
+
 }  // namespace tn

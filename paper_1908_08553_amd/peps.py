@@ -20,10 +20,11 @@ from ._native import (TN_ORDER_SWEEP_AUTO, Batch, EnvSet, tn_double_layer,
                       tn_double_layer_prepare, tn_observables, tn_plan_grid)
 
 
-# Boundary entries above which mode "auto" uses cached environments: 8 x 8 at
-# chi = 2 (4^9 entries) measures 10.0 ms per evaluation batched and 11.0 ms
-# with environments, 10 x 10 (4^11) 459 ms and 40 ms.
-AUTO_ENV_ENTRIES = 4 ** 9
+# Boundary entries above which mode "auto" uses cached environments (four
+# streams): 6 x 6 at chi = 2 (4^7 entries) measures 0.65 ms per evaluation
+# batched and 3.1 ms with environments, 8 x 8 (4^9) 10.0 ms and 6.6 ms,
+# 10 x 10 (4^11) 459 ms and 25 ms.
+AUTO_ENV_ENTRIES = 4 ** 8
 
 
 def pairs(rows: int, cols: int):

@@ -61,6 +61,15 @@ def test_bad_grid_and_arguments_rejected():
 
 
 def test_create_checks_workspace_without_touching_it():
+    # one stream: create makes no streams or events, so it runs without a device
+    lib.tn_set_option(tn.TN_OPT_ENV_STREAMS, 1)
+    try:
+        check_create()
+    finally:
+        lib.tn_set_option(tn.TN_OPT_ENV_STREAMS, 4)
+
+
+def check_create():
     rows, cols, D = 3, 5, 2
     nets = [[0], [7], [2, 3]]
     st, need = workspace(rows, cols, D, nets)
@@ -80,3 +89,18 @@ def test_create_checks_workspace_without_touching_it():
     assert h.value
     assert lib.tn_envset_destroy(h) == tn.TN_OK
     assert lib.tn_envset_destroy(None) == tn.TN_OK
+
+
+def test_stream_option_range_and_workspace():
+    assert lib.tn_set_option(tn.TN_OPT_ENV_STREAMS, 0) == tn.TN_EINVAL
+    assert lib.tn_set_option(tn.TN_OPT_ENV_STREAMS, 5) == tn.TN_EINVAL
+    try:
+        sizes = []
+        for s in (1, 2, 4):
+            assert lib.tn_set_option(tn.TN_OPT_ENV_STREAMS, s) == tn.TN_OK
+            sizes.append(workspace(4, 5, 3, [[0], [6]])[1])
+        # each further stream adds one network region
+        assert sizes[0] < sizes[1] < sizes[2]
+        assert sizes[2] - sizes[1] == 2 * (sizes[1] - sizes[0])
+    finally:
+        lib.tn_set_option(tn.TN_OPT_ENV_STREAMS, 4)

@@ -159,3 +159,25 @@ def test_envset_larger_lattice_sampled(tn):
     base, repl, nets, got = run_family(tn, rows, cols, D, 21, nets=nets)
     for net, g in zip(nets, got[1:]):
         check(g, expected(base, repl, rows, cols, net), "f64")
+
+
+@pytest.mark.parametrize("streams", [1, 2, 3])
+def test_stream_count_does_not_change_results(tn, streams):
+    # networks dealt over 1..4 streams (each with its own region): every
+    # result bitwise equal to the default four-stream set
+    rows, cols, D = 5, 6, 3
+    base = [dev(s) for s in li.uniform(rows, cols, D, 31)]
+    repl_h = li.uniform(rows, cols, D, 32)
+    nets = family(rows, cols, 31)
+    repl = [dev(repl_h[i]) for n in nets for i in n]
+    ref = tn.EnvSet(rows, cols, D, networks=nets).run(base, repl)
+    tn.tn_set_option(tn.TN_OPT_ENV_STREAMS, streams)
+    try:
+        es = tn.EnvSet(rows, cols, D, networks=nets)
+    finally:
+        tn.tn_set_option(tn.TN_OPT_ENV_STREAMS, 4)
+    print(f"[gpu] envset over {streams} streams", flush=True)
+    got = es.run(base, repl)
+    es.close()
+    for a, b in zip(ref, got):
+        assert (a.status, a.sign, a.mantissa, a.exp2_sum) == (b.status, b.sign, b.mantissa, b.exp2_sum)
