@@ -252,7 +252,9 @@ tn_status tn_observables(const tn_result* results, int32_t rows, int32_t cols, d
  * whose substituted sites lie in columns [c0, c1) then costs the absorption
  * of those columns, started from the left environment at c0, and one dot
  * with the right environment at c1 (none when c1 = cols: that network is the
- * full sweep's own arithmetic), instead of a full contraction.  Every value
+ * full sweep's own arithmetic), instead of a full contraction; with the
+ * environments inside columns (TN_OPT_ENV_ROWS) only the sweep steps from
+ * its first to its last substituted site are absorbed.  Every value
  * is the exact contraction of its network up to rounding, with the exact
  * power-of-two rescaling of the sweep.
  *
@@ -394,6 +396,18 @@ tn_status tn_server_destroy(tn_server* server);
  *                        of the process's hardware queues while the set
  *                        lives) and joins them into the caller's stream.   */
 #define TN_OPT_ENV_STREAMS 6
+/*   TN_OPT_ENV_ROWS    : the most GiB (0..1024, default 32) that
+ *                        environments inside columns may add to a tn_envset's
+ *                        workspace.  Within that budget the set also keeps the
+ *                        norm network's boundary before every sweep step and
+ *                        the boundary of all sites after every step (built
+ *                        from the right environment by reverse steps in the
+ *                        sweep's leg order), so a network whose changed sites
+ *                        are sweep steps k0..k1 absorbs only those steps;
+ *                        beyond it (or with 0) whole columns between column
+ *                        environments.  Read when the workspace is sized and
+ *                        when the set is created.                          */
+#define TN_OPT_ENV_ROWS 7
 tn_status tn_set_option(int32_t option, int64_t value);
 
 /* ------------------------------------------------------------ profiling

@@ -214,6 +214,7 @@ TN_OPT_CHUNK_SCHEDULE = 3
 TN_OPT_QUADRANT_STREAMS = 4
 TN_OPT_CHAIN_STEPS = 5
 TN_OPT_ENV_STREAMS = 6
+TN_OPT_ENV_ROWS = 7
 
 
 class tn_kernel_stat(C.Structure):

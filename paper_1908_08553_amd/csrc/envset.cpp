@@ -13,12 +13,20 @@
 // sweep up to column c1-1, then one boundary contraction instead of the
 // remaining columns.  With c1 = cols it is the full sweep's own arithmetic.
 //
+// Inside a column the same holds row by row: the norm network's boundary just
+// before sweep step k is the seed of every network whose first changed site
+// is step k, and the boundary of all sites after step k, built from the right
+// environment by reverse steps that keep the sweep's leg order, closes every
+// network whose last changed site is step k.  A single site then costs one
+// absorption step and a dot.
+//
 // Everything is issued without waiting, except the final result copy: the
 // left and right environment sweeps (one cut plan per column, each in its own
 // workspace region, which keeps its ending boundary for the rest of the run)
-// on the caller's stream and a side stream, then the base network and every
-// network, dealt round-robin over S streams (each with its own region), all
-// joined back into the caller's stream.
+// on the caller's stream and a side stream; then the forward and reverse
+// chains inside every column, dealt over S streams; then the base network and
+// every network, dealt round-robin over the S streams (each with its own
+// region), all joined back into the caller's stream.
 #include "envset.hpp"
 
 #include <hip/hip_runtime.h>
@@ -40,10 +48,16 @@ namespace tn {
 struct EnvSetImpl {
   int32_t R = 0, C = 0, prec = 0, n = 0;
   std::vector<Plan> left, right;            // cut [j, j+1), left to right / right to left
-  std::vector<Plan> cuts;                   // distinct network plans (left to right)
+  // Inside columns (rows_on): fwd[k] = sweep step k alone, for rows 0..R-2 of
+  // each column (its boundary is the one before step k+1); rev[k] = the
+  // reverse step at site k, for rows 1..R-1 (its boundary is all sites after
+  // step k-1).  Indexed by sweep step k = c * R + r; unused entries empty.
+  bool rows_on = false;
+  std::vector<Plan> fwd, rev;
+  std::vector<Plan> cuts;                   // distinct network plans
   std::vector<int32_t> net_plan;            // n + 1 entries (0: base network)
   std::vector<int32_t> sub_first, sub_count, sub_site;
-  std::vector<size_t> left_off, right_off;
+  std::vector<size_t> left_off, right_off, fwd_off, rev_off;
   int32_t S = 1;                            // streams the networks are spread over
   size_t shared_off = 0, shared_bytes = 0, recs_off = 0, partials_off = 0, partials_bytes = 0,
          results_off = 0;
@@ -52,16 +66,21 @@ struct EnvSetImpl {
   std::vector<std::unique_ptr<HostKeep>> keeps;
   std::vector<const double*> sites;         // scratch site table of one network
   std::vector<hipStream_t> side;            // S - 1 streams beside the caller's
-  std::vector<hipEvent_t> ev;               // start, left done, right done, S stream ends
+  std::vector<hipEvent_t> ev;               // start, then S per barrier (two) and S for the join
 
   ~EnvSetImpl() {
     for (hipStream_t st : side) (void)hipStreamDestroy(st);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
+  // exponent records: 2 (C-1) column environments, then R C forward and R C
+  // reverse ones indexed by sweep step
+  size_t n_recs() const { return static_cast<size_t>(2 * (C - 1) + 2 * R * C); }
 };
 
 int32_t g_env_streams = 4;
 void set_env_streams(int32_t n) { g_env_streams = n; }
+int32_t g_env_rows = 32;
+void set_env_rows(int32_t gib) { g_env_rows = gib; }
 
 namespace {
 
@@ -74,6 +93,7 @@ tn_status layout(EnvSetImpl& es, const tn_grid& grid, int32_t n, const int32_t* 
   tn_status s = build_plan(grid, TN_ORDER_COLSWEEP, 0, 0, full, err);
   if (s != TN_OK) return s;
   const int32_t R = full.rows, C = full.cols;
+  const int64_t total_steps = static_cast<int64_t>(R) * C;
   es.R = R; es.C = C; es.n = n;
   if (n < 0) { err = "negative network count"; return TN_EINVAL; }
   if (n > 0 && !n_subst) { err = "null substitution counts"; return TN_EINVAL; }
@@ -97,25 +117,53 @@ tn_status layout(EnvSetImpl& es, const tn_grid& grid, int32_t n, const int32_t* 
       (m ? es.right : es.left).push_back(std::move(p));
     }
   }
-  std::map<std::pair<int32_t, int32_t>, int32_t> index;
-  auto plan_for = [&](int32_t c0, int32_t c1, int32_t* out) -> tn_status {
-    const auto key = std::make_pair(c0, c1);
+  // environments inside columns, if their regions fit the budget
+  es.rows_on = false;
+  es.fwd.clear();
+  es.rev.clear();
+  if (g_env_rows && R > 1) {
+    es.fwd.resize(static_cast<size_t>(total_steps));
+    es.rev.resize(static_cast<size_t>(total_steps));
+    size_t bytes = 0;
+    for (int32_t c = 0; c < C; ++c)
+      for (int32_t r = 0; r < R; ++r) {
+        const int64_t k = static_cast<int64_t>(c) * R + r;
+        if (r < R - 1) {
+          s = build_sweep_cut(grid, 0, k, k + 1, es.fwd[k], err);
+          if (s != TN_OK) return s;
+          bytes += align_up(make_layout(es.fwd[k], es.prec).total);
+        }
+        if (r >= 1) {
+          s = build_rev_step(grid, r, c, es.rev[k], err);
+          if (s != TN_OK) return s;
+          bytes += align_up(make_layout(es.rev[k], es.prec).total);
+        }
+      }
+    es.rows_on = bytes <= (static_cast<size_t>(g_env_rows) << 30);
+    if (!es.rows_on) { es.fwd.clear(); es.rev.clear(); }
+  }
+
+  std::map<std::pair<int64_t, int64_t>, int32_t> index;
+  auto plan_for = [&](int64_t k0, int64_t k1, int32_t* out) -> tn_status {
+    const auto key = std::make_pair(k0, k1);
     auto it = index.find(key);
     if (it != index.end()) { *out = it->second; return TN_OK; }
     Plan p;
-    const tn_status st = build_cut_plan(grid, 0, c0, c1, p, err);
+    const tn_status st = build_sweep_cut(grid, 0, k0, k1, p, err);
     if (st != TN_OK) return st;
     es.cuts.push_back(std::move(p));
     *out = index[key] = static_cast<int32_t>(es.cuts.size() - 1);
     return TN_OK;
   };
   es.net_plan.assign(n + 1, 0);
-  s = plan_for(C - 1, C, &es.net_plan[0]);
+  // the base network: the last column from the left environment (the full
+  // sweep's own arithmetic)
+  s = plan_for(total_steps - R, total_steps, &es.net_plan[0]);
   if (s != TN_OK) return s;
   for (int32_t k = 0; k < n; ++k) {
-    int32_t c0 = C - 1, c1 = C;
+    int64_t k0 = total_steps - R, k1 = total_steps - 1;   // no substitution: the base network
     if (es.sub_count[k] > 0) {
-      c0 = C; c1 = 0;
+      k0 = total_steps; k1 = -1;
       std::vector<int32_t> seen;
       for (int32_t i = 0; i < es.sub_count[k]; ++i) {
         const int32_t site = es.sub_site[es.sub_first[k] + i];
@@ -125,40 +173,60 @@ tn_status layout(EnvSetImpl& es, const tn_grid& grid, int32_t n, const int32_t* 
           return TN_EINVAL;
         }
         seen.push_back(site);
-        c0 = std::min(c0, site % C);
-        c1 = std::max(c1, site % C + 1);
+        const int64_t step = static_cast<int64_t>(site % C) * R + site / C;   // sweep order
+        k0 = std::min(k0, step);
+        k1 = std::max(k1, step);
+      }
+      if (!es.rows_on) {   // whole columns between column environments
+        k0 = k0 / R * R;
+        k1 = k1 / R * R + R - 1;
       }
     }
-    s = plan_for(c0, c1, &es.net_plan[k + 1]);
+    s = plan_for(k0, k1 + 1, &es.net_plan[k + 1]);
     if (s != TN_OK) return s;
   }
 
-  // a network's seed and cap are the environments at its column cuts: same
-  // bonds in the same order (a planner invariant, checked once here)
+  // a network's seed and cap are the environments at its cuts: same bonds in
+  // the same order (a planner invariant, checked once here)
   for (const Plan& p : es.cuts) {
-    if (p.cut_c0 > 0) {
-      const Plan& l = es.left[p.cut_c0 - 1];
-      if (l.steps.back().out != p.steps[0].out) { err = "seed does not match its environment"; return TN_EINVAL; }
+    if (p.cut_k0 > 0) {
+      const int64_t k = p.cut_k0;
+      const Plan& l = (k % R == 0) ? es.left[k / R - 1] : es.fwd[k - 1];
+      if (l.cut_legs.empty() || l.steps.back().out != p.steps[0].out) {
+        err = "seed does not match its environment";
+        return TN_EINVAL;
+      }
     }
-    if (p.cut_c1 < C && p.cut_legs != es.right[C - 1 - p.cut_c1].cut_legs) {
-      err = "cap does not match its environment";
-      return TN_EINVAL;
+    if (p.cut_open_end) {
+      const int64_t k = p.cut_k1 - 1;
+      const Plan& r = (k % R == R - 1) ? es.right[C - 2 - k / R] : es.rev[k + 1];
+      if (p.cut_legs != r.cut_legs) { err = "cap does not match its environment"; return TN_EINVAL; }
     }
   }
   es.S = g_env_streams;
   size_t off = 0;
-  for (const Plan& p : es.left) { es.left_off.push_back(off); off += align_up(make_layout(p, es.prec).total); }
-  for (const Plan& p : es.right) { es.right_off.push_back(off); off += align_up(make_layout(p, es.prec).total); }
+  auto place = [&](const std::vector<Plan>& plans, std::vector<size_t>& offs) {
+    offs.assign(plans.size(), 0);
+    for (size_t i = 0; i < plans.size(); ++i) {
+      if (plans[i].steps.empty()) continue;
+      offs[i] = off;
+      off += align_up(make_layout(plans[i], es.prec).total);
+    }
+  };
+  place(es.left, es.left_off);
+  place(es.right, es.right_off);
+  place(es.fwd, es.fwd_off);
+  place(es.rev, es.rev_off);
   es.shared_off = off;
   es.shared_bytes = 0;
   int64_t parts = 1;
   for (const Plan& p : es.cuts) {
     es.shared_bytes = std::max(es.shared_bytes, align_up(make_layout(p, es.prec).total));
-    if (p.cut_c1 < C) parts = std::max(parts, env_cap_blocks(p.steps.back().out));
+    if (p.cut_open_end) parts = std::max(parts, env_cap_blocks(p.steps.back().out));
   }
   off += es.shared_bytes * es.S;
   es.recs_off = off;
-  off = align_up(off + sizeof(EnvRec) * static_cast<size_t>(std::max(2 * (C - 1), 1)));
+  off = align_up(off + sizeof(EnvRec) * std::max<size_t>(es.n_recs(), 1));
   es.partials_off = off;
   es.partials_bytes = align_up(sizeof(double) * static_cast<size_t>(parts));
   off += es.partials_bytes * es.S;
@@ -204,7 +272,7 @@ tn_status envset_create(const tn_grid& grid, int32_t prec, int32_t n, const int3
     }
     es->side.push_back(st);
   }
-  for (int32_t i = 0; es->S > 1 && i < 3 + es->S; ++i) {
+  for (int32_t i = 0; es->S > 1 && i < 1 + 3 * es->S; ++i) {
     hipEvent_t e = nullptr;
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
       err = "hipEventCreateWithFlags failed";
@@ -212,7 +280,9 @@ tn_status envset_create(const tn_grid& grid, int32_t prec, int32_t n, const int3
     }
     es->ev.push_back(e);
   }
-  const size_t calls = es->left.size() + es->right.size() + static_cast<size_t>(n) + 1;
+  size_t calls = es->left.size() + es->right.size() + static_cast<size_t>(n) + 1;
+  for (const Plan& p : es->fwd) calls += p.steps.empty() ? 0 : 1;
+  for (const Plan& p : es->rev) calls += p.steps.empty() ? 0 : 1;
   for (size_t i = 0; i < calls; ++i) es->keeps.push_back(std::make_unique<HostKeep>());
   es->keeps.push_back(std::make_unique<HostKeep>());   // result records
   es->sites.resize(static_cast<size_t>(es->R) * es->C);
@@ -233,51 +303,103 @@ tn_status envset_run(EnvSetImpl* es, const double* const* base, const double* co
   EnvRec* recs = reinterpret_cast<EnvRec*>(ws + es->recs_off);
   tn_result* results = reinterpret_cast<tn_result*>(ws + es->results_off);
   const int32_t S = es->S;
+  const int64_t total_steps = static_cast<int64_t>(R) * C;
   std::vector<hipStream_t> streams{stream};
   for (hipStream_t st : es->side) streams.push_back(st);
   std::vector<std::unique_ptr<LaunchTimer>> timers;
   for (hipStream_t st : streams) timers.push_back(std::make_unique<LaunchTimer>(st));
   // one stream needs no events: stream order alone serialises the work
   const bool multi = S > 1;
-  hipEvent_t ev_start = multi ? es->ev[0] : nullptr, ev_left = multi ? es->ev[1] : nullptr,
-             ev_right = multi ? es->ev[2] : nullptr;
   size_t call = 0;
   const int32_t ne = C - 1;
+  EnvRec* lrec = recs;                              // column environments
+  EnvRec* rrec = recs + ne;
+  EnvRec* frec = recs + 2 * ne;                     // inside columns, by sweep step
+  EnvRec* vrec = frec + total_steps;
   std::vector<const void*> ltap(ne, nullptr), rtap(ne, nullptr);
+  std::vector<const void*> ftap(es->rows_on ? total_steps : 0, nullptr);
+  std::vector<const void*> vtap(es->rows_on ? total_steps : 0, nullptr);
   hipError_t e = hipSuccess;
   tn_status status = TN_OK;
 
-  // Left environments on the caller's stream, right ones on the first side
-  // stream (one column per call); the networks wait for both and are dealt
-  // round-robin over the streams, each stream with its own region.
-  auto issue = [&]() -> tn_status {
-    if (multi) e = hipEventRecord(ev_start, stream);
-    for (int32_t i = 1; i < S && e == hipSuccess; ++i) e = hipStreamWaitEvent(streams[i], ev_start, 0);
+  // every stream waits for what every stream has issued so far
+  auto barrier = [&](int32_t first_event) -> tn_status {
+    if (!multi) return TN_OK;
+    for (int32_t i = 0; i < S && e == hipSuccess; ++i) e = hipEventRecord(es->ev[first_event + i], streams[i]);
+    for (int32_t i = 0; i < S && e == hipSuccess; ++i)
+      for (int32_t j = 0; j < S && e == hipSuccess; ++j)
+        if (i != j) e = hipStreamWaitEvent(streams[i], es->ev[first_event + j], 0);
     if (e != hipSuccess) { err = hipGetErrorString(e); return TN_EDEVICE; }
+    return TN_OK;
+  };
+  auto run_env = [&](const Plan& p, size_t off, int32_t si, const void* seed, const EnvRec* seed_rec,
+                     const void** tap, EnvRec* tap_rec) -> tn_status {
+    CutIO io;
+    io.seed = seed;
+    io.seed_rec = seed_rec;
+    io.tap = tap;
+    io.tap_rec = tap_rec;
+    return enqueue(p, base, true, es->prec, ws + off, make_layout(p, es->prec).total, streams[si],
+                   *es->keeps[call++], *timers[si], err, nullptr, nullptr, &io);
+  };
+  // the boundary before sweep step k (seed) and after it (cap)
+  auto seed_of = [&](int64_t k, const void** ptr, const EnvRec** rec) {
+    if (k % R == 0) { *ptr = ltap[k / R - 1]; *rec = lrec + k / R - 1; }
+    else { *ptr = ftap[k - 1]; *rec = frec + k - 1; }
+  };
+  auto cap_of = [&](int64_t k, const void** ptr, const EnvRec** rec) {
+    if (k % R == R - 1) {
+      const int64_t j = C - 2 - k / R;
+      *ptr = rtap[j]; *rec = rrec + j;
+    } else {
+      *ptr = vtap[k + 1]; *rec = vrec + k + 1;
+    }
+  };
+
+  auto issue = [&]() -> tn_status {
+    if (multi) e = hipEventRecord(es->ev[0], stream);
+    for (int32_t i = 1; i < S && e == hipSuccess; ++i) e = hipStreamWaitEvent(streams[i], es->ev[0], 0);
+    if (e != hipSuccess) { err = hipGetErrorString(e); return TN_EDEVICE; }
+    // column environments: left on the caller's stream, right on a side stream
     for (int32_t side = 0; side < 2; ++side) {
-      const std::vector<Plan>& plans = side ? es->right : es->left;
-      const std::vector<size_t>& offs = side ? es->right_off : es->left_off;
-      std::vector<const void*>& taps = side ? rtap : ltap;
       const int32_t si = (side && S > 1) ? 1 : 0;
       for (int32_t j = 0; j < ne; ++j) {
-        CutIO io;
-        if (j > 0) { io.seed = taps[j - 1]; io.seed_rec = recs + side * ne + j - 1; }
-        io.tap = &taps[j];
-        io.tap_rec = recs + side * ne + j;
-        const Plan& p = plans[j];
-        const tn_status st = enqueue(p, base, true, es->prec, ws + offs[j],
-                                     make_layout(p, es->prec).total, streams[si],
-                                     *es->keeps[call++], *timers[si], err, nullptr, nullptr, &io);
+        const tn_status st = side
+            ? run_env(es->right[j], es->right_off[j], si, j > 0 ? rtap[j - 1] : nullptr,
+                      j > 0 ? rrec + j - 1 : nullptr, &rtap[j], rrec + j)
+            : run_env(es->left[j], es->left_off[j], si, j > 0 ? ltap[j - 1] : nullptr,
+                      j > 0 ? lrec + j - 1 : nullptr, &ltap[j], lrec + j);
         if (st != TN_OK) return st;
       }
-      if (multi) e = hipEventRecord(side ? ev_right : ev_left, streams[si]);
-      if (e != hipSuccess) { err = hipGetErrorString(e); return TN_EDEVICE; }
     }
-    for (int32_t i = 0; multi && i < S && e == hipSuccess; ++i) {
-      e = hipStreamWaitEvent(streams[i], ev_left, 0);
-      if (e == hipSuccess) e = hipStreamWaitEvent(streams[i], ev_right, 0);
+    tn_status st = barrier(1);
+    if (st != TN_OK) return st;
+    // inside columns: per column a forward chain down from the left
+    // environment and a reverse chain up from the right one, dealt over the
+    // streams
+    if (es->rows_on) {
+      for (int32_t c = 0; c < C; ++c) {
+        const int32_t sf = (2 * c) % S, sr = (2 * c + 1) % S;
+        for (int32_t r = 0; r + 1 < R; ++r) {
+          const int64_t k = static_cast<int64_t>(c) * R + r;
+          const void* sp = nullptr;
+          const EnvRec* sq = nullptr;
+          if (k > 0) seed_of(k, &sp, &sq);
+          st = run_env(es->fwd[k], es->fwd_off[k], sf, sp, sq, &ftap[k], frec + k);
+          if (st != TN_OK) return st;
+        }
+        for (int32_t r = R - 1; r >= 1; --r) {
+          const int64_t k = static_cast<int64_t>(c) * R + r;
+          const void* sp = nullptr;
+          const EnvRec* sq = nullptr;
+          if (!(c == C - 1 && r == R - 1)) cap_of(k, &sp, &sq);
+          st = run_env(es->rev[k], es->rev_off[k], sr, sp, sq, &vtap[k], vrec + k);
+          if (st != TN_OK) return st;
+        }
+      }
+      st = barrier(1 + S);
+      if (st != TN_OK) return st;
     }
-    if (e != hipSuccess) { err = hipGetErrorString(e); return TN_EDEVICE; }
     for (int32_t k = 0; k <= n; ++k) {
       const int32_t si = k % S;
       const Plan& p = es->cuts[es->net_plan[k]];
@@ -287,18 +409,15 @@ tn_status envset_run(EnvSetImpl* es, const double* const* base, const double* co
         for (int32_t i = 0; i < es->sub_count[k - 1]; ++i) es->sites[es->sub_site[f + i]] = subst[f + i];
       }
       CutIO io;
-      if (p.cut_c0 > 0) { io.seed = ltap[p.cut_c0 - 1]; io.seed_rec = recs + p.cut_c0 - 1; }
-      if (p.cut_c1 < C) {
-        const int32_t j = C - 1 - p.cut_c1;
-        io.cap = rtap[j];
-        io.cap_rec = recs + ne + j;
+      if (p.cut_k0 > 0) seed_of(p.cut_k0, &io.seed, &io.seed_rec);
+      if (p.cut_open_end) {
+        cap_of(p.cut_k1 - 1, &io.cap, &io.cap_rec);
         io.partials = reinterpret_cast<double*>(ws + es->partials_off + es->partials_bytes * si);
       }
       io.result = results + k;
-      const tn_status st = enqueue(p, es->sites.data(), true, es->prec,
-                                   ws + es->shared_off + es->shared_bytes * si, es->shared_bytes,
-                                   streams[si], *es->keeps[call++], *timers[si], err, nullptr,
-                                   nullptr, &io);
+      st = enqueue(p, es->sites.data(), true, es->prec,
+                   ws + es->shared_off + es->shared_bytes * si, es->shared_bytes, streams[si],
+                   *es->keeps[call++], *timers[si], err, nullptr, nullptr, &io);
       if (st != TN_OK) return st;
     }
     return TN_OK;
@@ -306,8 +425,8 @@ tn_status envset_run(EnvSetImpl* es, const double* const* base, const double* co
   status = issue();
   // join every side stream back into the caller's stream, also after an error
   for (int32_t i = 1; i < S; ++i) {
-    hipError_t e2 = hipEventRecord(es->ev[3 + i], streams[i]);
-    if (e2 == hipSuccess) e2 = hipStreamWaitEvent(stream, es->ev[3 + i], 0);
+    hipError_t e2 = hipEventRecord(es->ev[1 + 2 * S + i], streams[i]);
+    if (e2 == hipSuccess) e2 = hipStreamWaitEvent(stream, es->ev[1 + 2 * S + i], 0);
     if (e2 != hipSuccess && status == TN_OK) { err = hipGetErrorString(e2); status = TN_EDEVICE; }
   }
   if (status != TN_OK) {

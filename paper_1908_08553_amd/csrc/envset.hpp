@@ -30,5 +30,9 @@ void envset_destroy(EnvSetImpl* es);
 // envset_workspace and envset_create.
 void set_env_streams(int32_t n);
 extern int32_t g_env_streams;
+// Most GiB the environments inside columns may add to a set's workspace
+// (0: none, only column environments).
+void set_env_rows(int32_t gib);
+extern int32_t g_env_rows;
 
 }  // namespace tn

@@ -177,7 +177,11 @@ Layout make_layout(const Plan& p, int32_t prec) {
       mx = std::max(mx, static_cast<size_t>(p.steps[k].out) * elem_bytes(L.out_type[k]));
     L.buf_bytes[u] = align_up(mx);
     L.buf[u][0] = off; off += L.buf_bytes[u];
-    L.buf[u][1] = off; off += L.buf_bytes[u];
+    // a seeded single absorption reads the seed in place and writes only the
+    // second buffer: one buffer serves both
+    const bool one_out = p.is_cut && p.steps.size() == 2 && p.steps[0].kind == STEP_SEED;
+    L.buf[u][1] = one_out ? L.buf[u][0] : off;
+    if (!one_out) off += L.buf_bytes[u];
   }
   if (p.has_ring) {
     const int32_t t = prec == TN_PREC_F64 ? EL_F64 : EL_F32;
@@ -312,7 +316,7 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
                   LaunchTimer* side_timer, const CutIO* io) {
   const Layout L = make_layout(p, prec);
   const bool seeded = !p.steps.empty() && p.steps[0].kind == STEP_SEED;
-  const bool open_end = p.is_cut && p.cut_c1 < p.cols;
+  const bool open_end = p.is_cut && p.cut_open_end;
   if (seeded && (!io || !io->seed || !io->seed_rec)) {
     err = "cut plan needs a seed boundary";
     return TN_EINVAL;
@@ -639,11 +643,8 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
     const size_t kl = p.steps.size() - 1;
     const Step& sl = p.steps[kl];
     const char* fin = base + L.buf[0][final_buf[0]];
-    if (sl.rescale < 0) {
-      err = "cut plan ends without a rescale point";
-      return TN_EINVAL;
-    }
-    const int32_t* slot_last = slot_exp + sl.rescale;
+    // inside a column there is no rescale point: no shift, no exponent
+    const int32_t* slot_last = sl.rescale >= 0 ? slot_exp + sl.rescale : nullptr;
     if (io->cap) {
       const int32_t f64 = L.out_type[kl] == EL_F64;
       timer.before();

@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void env_tap_kernel(DevState* state, const 
   int32_t bad;
   block_totals(state, nullptr, 0, unused, E, bad);
   if (threadIdx.x != 0) return;
-  const int32_t e = *slot_last;
+  const int32_t e = slot_last ? *slot_last : kExpZero;
   EnvRec out;
   out.pad = 0;
   if (bad || (state->flags & 1) || e == kExpBad) {

@@ -228,7 +228,8 @@ hipError_t launch_env_cap(const void* B, const void* Rv, int64_t n, int32_t f64,
                           const int32_t* slot_b, const EnvRec* rec, double* partials,
                           hipStream_t stream);
 // Tap: the record of the boundary a cut plan ends in, whose largest-magnitude
-// exponent is *slot_last (one block; the exponent sums of finalize).
+// exponent is *slot_last (null inside a column: no shift), from the exponent
+// sums of finalize (one block).
 hipError_t launch_env_tap(DevState* state, const int32_t* slot_last, EnvRec* rec,
                           hipStream_t stream);
 

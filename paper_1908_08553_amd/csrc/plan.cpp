@@ -97,7 +97,8 @@ struct Lattice {
 // final boundary legs.
 std::vector<int32_t> sweep(const Lattice& L, int32_t unit, int32_t frame, int32_t nh,
                            int32_t nw, bool rescale_last, int32_t& slot,
-                           std::vector<Step>& steps) {
+                           std::vector<Step>& steps,
+                           std::vector<std::vector<int32_t>>* legs_after = nullptr) {
   std::vector<int32_t> bnd;
   const int32_t* fl = kFrameLegs[frame];
   for (int32_t j = 0; j < nw; ++j) {
@@ -129,6 +130,7 @@ std::vector<int32_t> sweep(const Lattice& L, int32_t unit, int32_t frame, int32_
         s.flops = 0;
         steps.push_back(s);
         if (nh == 1 && (j < nw - 1 || rescale_last)) steps.back().rescale = slot++;
+        if (legs_after) legs_after->push_back(bnd);
         continue;
       }
       // locate the shared bonds in the boundary; they must be adjacent
@@ -164,6 +166,7 @@ std::vector<int32_t> sweep(const Lattice& L, int32_t unit, int32_t frame, int32_
       s.flops = mul(mul(s.out, K), 2);
       steps.push_back(s);
       if (i == nh - 1 && (j < nw - 1 || rescale_last)) steps.back().rescale = slot++;
+      if (legs_after) legs_after->push_back(bnd);
     }
   }
   return bnd;
@@ -328,57 +331,187 @@ tn_status build_plan(const tn_grid& grid, int32_t order, int32_t quad_h, int32_t
   return TN_OK;
 }
 
-tn_status build_cut_plan(const tn_grid& grid, int32_t mirror, int32_t c0, int32_t c1, Plan& out,
-                         std::string& err) {
+tn_status build_sweep_cut(const tn_grid& grid, int32_t mirror, int64_t k0, int64_t k1, Plan& out,
+                          std::string& err) {
   Plan p;
   const tn_status st = build_plan(grid, TN_ORDER_COLSWEEP, 0, 0, p, err);
   if (st != TN_OK) return st;
   const int32_t R = p.rows, C = p.cols;
-  if (c0 < 0 || c1 > C || c0 >= c1) { err = "cut columns out of range"; return TN_EINVAL; }
+  const int64_t total = static_cast<int64_t>(R) * C;
+  if (k0 < 0 || k1 > total || k0 >= k1) { err = "cut steps out of range"; return TN_EINVAL; }
   Lattice L{R, C, &p.hdim, &p.vdim};
   const int32_t frame = mirror ? FRAME_MH : FRAME_ID;
   std::vector<Step> all;
+  std::vector<std::vector<int32_t>> legs;
   int32_t slot = 0;
   try {
-    sweep(L, 0, frame, R, C, false, slot, all);
-    std::vector<Step> head;
-    int32_t unused = 0;
-    p.cut_legs = sweep(L, 0, frame, R, c1, false, unused, head);
+    sweep(L, 0, frame, R, C, false, slot, all, &legs);
   } catch (Overflow&) {
     err = "plan integers overflow int64";
     return TN_EOVERFLOW;
   }
-  // every local column holds R steps; its rescale slot is its column index
-  const int32_t off = c0 > 0 ? c0 - 1 : 0;
   p.steps.clear();
-  if (c0 > 0) {
-    const Step& last = all[static_cast<size_t>(c0) * R - 1];
+  if (k0 > 0) {
+    const Step& last = all[k0 - 1];
     Step s;
     s.unit = 0; s.r = last.r; s.c = last.c; s.kind = STEP_SEED;
     s.pre = s.K = s.post = 1;
     s.N = s.out = last.out;
-    s.col = c0 - 1; s.last_col = 0;
+    s.col = last.col; s.last_col = last.last_col;
     s.site_entries = 0;
     s.rescale = 0;
     p.steps.push_back(s);
   }
-  for (size_t k = static_cast<size_t>(c0) * R; k < static_cast<size_t>(c1) * R; ++k) {
+  // rescale slots renumbered in order of appearance, after the seed's slot 0
+  int32_t next = k0 > 0 ? 1 : 0, prev_old = -1;
+  for (int64_t k = k0; k < k1; ++k) {
     Step s = all[k];
     s.scale_in = -1;
-    if (s.rescale >= 0) s.rescale -= off;
+    if (s.rescale >= 0) {
+      if (s.rescale != prev_old) { prev_old = s.rescale; ++next; }
+      s.rescale = next - 1;
+    }
     p.steps.push_back(s);
   }
   p.slots = 0;
   for (const Step& s : p.steps) p.slots = std::max(p.slots, s.rescale + 1);
   p.units.clear();
   Unit U;
-  U.frame = frame; U.rows = R; U.cols = c1 - c0; U.result = p.steps.back().out;
+  U.frame = frame; U.rows = R; U.cols = static_cast<int32_t>((k1 - k0 + R - 1) / R);
+  U.result = p.steps.back().out;
   U.first_step = 0; U.n_steps = static_cast<int32_t>(p.steps.size());
   p.units.push_back(U);
   p.is_cut = true;
   p.cut_mirror = mirror ? 1 : 0;
-  p.cut_c0 = c0;
-  p.cut_c1 = c1;
+  p.cut_k0 = k0;
+  p.cut_k1 = k1;
+  p.cut_c0 = static_cast<int32_t>(k0 / R);
+  p.cut_c1 = static_cast<int32_t>((k1 + R - 1) / R);
+  p.cut_open_end = k1 < total;
+  p.cut_legs = legs[k1 - 1];
+  try {
+    finish(p);
+  } catch (Overflow&) {
+    err = "plan integers overflow int64";
+    return TN_EOVERFLOW;
+  }
+  out = std::move(p);
+  return TN_OK;
+}
+
+tn_status build_cut_plan(const tn_grid& grid, int32_t mirror, int32_t c0, int32_t c1, Plan& out,
+                         std::string& err) {
+  if (grid.rows < 1 || c0 < 0 || c1 < c0) { err = "cut columns out of range"; return TN_EINVAL; }
+  return build_sweep_cut(grid, mirror, static_cast<int64_t>(c0) * grid.rows,
+                         static_cast<int64_t>(c1) * grid.rows, out, err);
+}
+
+static std::vector<int32_t> rev_input_legs(const Plan& g, int32_t r, int32_t c) {
+  const int32_t R = g.rows, C = g.cols;
+  Lattice L{R, C, &g.hdim, &g.vdim};
+  std::vector<int32_t> b;
+  if (r == R - 1) {
+    if (c < C - 1)
+      for (int32_t i = 0; i < R; ++i) b.push_back(L.hid(i, c));
+    return b;
+  }
+  for (int32_t i = 0; i <= r; ++i)
+    if (c < C - 1) b.push_back(L.hid(i, c));
+  b.push_back(L.vid(r, c));
+  for (int32_t i = r + 1; i < R; ++i)
+    if (c > 0) b.push_back(L.hid(i, c - 1));
+  return b;
+}
+
+tn_status build_rev_step(const tn_grid& grid, int32_t r, int32_t c, Plan& out, std::string& err) {
+  Plan p;
+  const tn_status st = build_plan(grid, TN_ORDER_COLSWEEP, 0, 0, p, err);
+  if (st != TN_OK) return st;
+  const int32_t R = p.rows, C = p.cols;
+  if (r < 1 || r >= R || c < 0 || c >= C) { err = "reverse step out of range"; return TN_EINVAL; }
+  Lattice L{R, C, &p.hdim, &p.vdim};
+  try {
+    std::vector<int32_t> bnd = rev_input_legs(p, r, c);
+    std::vector<int32_t> k_legs, n_legs;
+    for (int32_t leg : {LEG_RIGHT, LEG_DOWN})
+      if (L.has(r, c, leg)) k_legs.push_back(leg);
+    for (int32_t leg : {LEG_UP, LEG_LEFT})
+      if (L.has(r, c, leg)) n_legs.push_back(leg);
+    p.steps.clear();
+    Step s;
+    s.unit = 0; s.r = r; s.c = c; s.col = c; s.last_col = (c == C - 1);
+    s.site_entries = 1;
+    for (int32_t leg = 0; leg < 4; ++leg)
+      if (L.has(r, c, leg)) s.site_entries = mul(s.site_entries, L.dim(L.bond(r, c, leg)));
+    if (!bnd.empty()) {
+      Step seed;
+      seed.unit = 0; seed.r = r; seed.c = c; seed.kind = STEP_SEED;
+      seed.pre = seed.K = seed.post = 1;
+      int64_t n = 1;
+      for (int32_t b : bnd) n = mul(n, L.dim(b));
+      seed.N = seed.out = n;
+      seed.col = c; seed.last_col = s.last_col;
+      seed.site_entries = 0;
+      seed.rescale = 0;
+      p.steps.push_back(seed);
+    }
+    if (k_legs.empty()) {
+      s.kind = STEP_INIT;
+      int64_t n = 1;
+      for (int32_t leg : n_legs) {
+        s.perm[s.nperm++] = L.axis(r, c, leg);
+        n = mul(n, L.dim(L.bond(r, c, leg)));
+        bnd.push_back(L.bond(r, c, leg));
+      }
+      s.pre = s.K = s.post = 1;
+      s.N = s.out = n;
+      s.flops = 0;
+    } else {
+      // the contracted legs (right, then down) sit side by side in the boundary
+      const auto it = std::find(bnd.begin(), bnd.end(), L.bond(r, c, k_legs[0]));
+      const size_t k0 = static_cast<size_t>(it - bnd.begin());
+      if (it == bnd.end() || k0 + k_legs.size() > bnd.size())
+        throw std::runtime_error("reverse step legs not found");
+      for (size_t a = 0; a < k_legs.size(); ++a)
+        if (bnd[k0 + a] != L.bond(r, c, k_legs[a])) throw std::runtime_error("reverse step legs not adjacent");
+      int64_t pre = 1, post = 1, K = 1, N = 1;
+      for (size_t a = 0; a < k0; ++a) pre = mul(pre, L.dim(bnd[a]));
+      for (size_t a = k0 + k_legs.size(); a < bnd.size(); ++a) post = mul(post, L.dim(bnd[a]));
+      for (int32_t leg : k_legs) {
+        s.perm[s.nperm++] = L.axis(r, c, leg);
+        K = mul(K, L.dim(L.bond(r, c, leg)));
+      }
+      std::vector<int32_t> nb(bnd.begin(), bnd.begin() + k0);
+      for (int32_t leg : n_legs) {
+        s.perm[s.nperm++] = L.axis(r, c, leg);
+        N = mul(N, L.dim(L.bond(r, c, leg)));
+        nb.push_back(L.bond(r, c, leg));
+      }
+      nb.insert(nb.end(), bnd.begin() + k0 + k_legs.size(), bnd.end());
+      bnd.swap(nb);
+      s.kind = STEP_ABSORB;
+      s.pre = pre; s.K = K; s.N = N; s.post = post;
+      s.out = mul(mul(pre, N), post);
+      s.flops = mul(mul(s.out, K), 2);
+    }
+    p.steps.push_back(s);
+    p.cut_legs = bnd;
+  } catch (Overflow&) {
+    err = "plan integers overflow int64";
+    return TN_EOVERFLOW;
+  } catch (const std::runtime_error& e) {
+    err = e.what();
+    return TN_EINVAL;
+  }
+  p.slots = p.steps.size() > 1 ? 1 : 0;
+  p.units.clear();
+  Unit U;
+  U.frame = FRAME_ID; U.rows = 1; U.cols = 1; U.result = p.steps.back().out;
+  U.first_step = 0; U.n_steps = static_cast<int32_t>(p.steps.size());
+  p.units.push_back(U);
+  p.is_cut = true;
+  p.cut_mirror = 2;
+  p.cut_open_end = true;
   try {
     finish(p);
   } catch (Overflow&) {

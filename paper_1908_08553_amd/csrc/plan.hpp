@@ -71,7 +71,9 @@ struct Plan {
   // step when cut_c0 > 0 and end in the boundary after column cut_c1 - 1 when
   // cut_c1 < cols (the column-sweep scalar otherwise).
   bool is_cut = false;
+  bool cut_open_end = false;       // ends in a boundary (else in the sweep's scalar)
   int32_t cut_mirror = 0, cut_c0 = 0, cut_c1 = 0;
+  int64_t cut_k0 = 0, cut_k1 = 0;  // sweep steps [cut_k0, cut_k1)
   std::vector<int32_t> cut_legs;   // bond ids of the ending boundary, slowest first
 };
 
@@ -79,11 +81,24 @@ struct Plan {
 tn_status build_plan(const tn_grid& grid, int32_t order, int32_t quad_h,
                      int32_t quad_w, Plan& out, std::string& err);
 
-// Cut plan of the column sweep (see Plan::is_cut): same steps, site folds and
-// rescale points as the full sweep over those columns.  TN_EINVAL unless
-// 0 <= c0 < c1 <= cols.
+// Cut plans of the column sweep (see Plan::is_cut): same steps, site folds and
+// rescale points as the full sweep over sweep steps [k0, k1) (step k absorbs
+// local site (k mod rows, k / rows)), or over local columns [c0, c1).
+// TN_EINVAL unless 0 <= k0 < k1 <= rows*cols (0 <= c0 < c1 <= cols).
+tn_status build_sweep_cut(const tn_grid& grid, int32_t mirror, int64_t k0, int64_t k1, Plan& out,
+                          std::string& err);
 tn_status build_cut_plan(const tn_grid& grid, int32_t mirror, int32_t c0, int32_t c1, Plan& out,
                          std::string& err);
+
+// One reverse step in column c (cached environments inside a column): the
+// boundary of all sites after (r, c) in the left-to-right sweep order (the
+// right environment at column c+1 with rows r+1..rows-1 of column c absorbed
+// from the bottom), in the sweep's own leg order, absorbs site (r, c) by its
+// right and down legs and puts its up and left legs in their place; the
+// result is the boundary of all sites after (r-1, c), in the leg order the
+// sweep has after absorbing (r-1, c).  A SEED step supplies the input, except
+// at the bottom-right site, which starts the boundary (INIT).  1 <= r < rows.
+tn_status build_rev_step(const tn_grid& grid, int32_t r, int32_t c, Plan& out, std::string& err);
 
 // Canonical text: identical bytes for identical plans.
 std::string plan_text(const Plan& p);

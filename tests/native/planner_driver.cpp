@@ -3,6 +3,7 @@
 // checking the plan's bookkeeping on the way, and every column-sweep cut plan
 // of those shapes.  Built with AddressSanitizer and
 // UndefinedBehaviorSanitizer by tests/test_host_sanitized.py (host code only).
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -104,6 +105,66 @@ void run_cuts(int r, int c, int D, const int32_t* h, const int32_t* v, long& pla
         if (c1 < c) check(p.steps.back().out == bnd(c1), "cut boundary entries", r, c, D, 100 + mirror);
         else check(p.steps.back().out == 1, "cut scalar end", r, c, D, 100 + mirror);
       }
+  // step-granular cuts: the full sweep's steps from any step k0, to the next
+  // step, the end of a column or the end of the sweep
+  const int64_t total = static_cast<int64_t>(r) * c;
+  for (int64_t k0 = 0; k0 < total; ++k0) {
+    for (int64_t k1 : {k0 + 1, std::min<int64_t>(total, k0 + r), total}) {
+      tn::Plan p;
+      if (tn::build_sweep_cut(g, 0, k0, k1, p, err) != TN_OK) {
+        check(false, "step cut error", r, c, D, 103);
+        continue;
+      }
+      ++plans;
+      const int seed = k0 > 0 ? 1 : 0;
+      bool same = static_cast<int64_t>(p.steps.size()) == seed + (k1 - k0) &&
+                  p.cut_open_end == (k1 < total);
+      if (seed) same = same && p.steps[0].kind == tn::STEP_SEED && p.steps[0].out == full.steps[k0 - 1].out;
+      for (int64_t k = k0; same && k < k1; ++k) {
+        const tn::Step& f = full.steps[k];
+        const tn::Step& q = p.steps[seed + (k - k0)];
+        same = f.kind == q.kind && f.pre == q.pre && f.K == q.K && f.N == q.N && f.post == q.post &&
+               (f.rescale >= 0) == (q.rescale >= 0) && q.last_col == f.last_col;
+        if (k > k0 || seed) same = same && (q.kind != tn::STEP_ABSORB || q.scale_in ==
+                                            p.steps[seed + (k - k0) - 1].rescale);
+      }
+      check(same, "step cut differs from the full sweep", r, c, D, 103);
+    }
+  }
+  // reverse steps inside a column: each ends in the bonds the sweep has after
+  // the site above, and chains from the right environment (or the corner)
+  for (int cc = 0; cc < c; ++cc) {
+    std::vector<int32_t> prev;
+    if (cc < c - 1) {
+      tn::Plan e;
+      if (tn::build_cut_plan(g, 1, 0, c - 1 - cc, e, err) == TN_OK) prev = e.cut_legs;
+      else check(false, "right environment error", r, c, D, 104);
+    }
+    for (int rr = r - 1; rr >= 1; --rr) {
+      tn::Plan q, f;
+      if (tn::build_rev_step(g, rr, cc, q, err) != TN_OK ||
+          tn::build_sweep_cut(g, 0, 0, static_cast<int64_t>(cc) * r + rr, f, err) != TN_OK) {
+        check(false, "reverse step error", r, c, D, 104);
+        break;
+      }
+      ++plans;
+      const bool starts = rr == r - 1 && cc == c - 1;
+      bool ok = q.cut_legs == f.cut_legs && q.cut_open_end;
+      ok = ok && (starts ? (q.steps.size() == 1 && q.steps[0].kind == tn::STEP_INIT)
+                         : (q.steps.size() == 2 && q.steps[0].kind == tn::STEP_SEED &&
+                            q.steps[1].kind == tn::STEP_ABSORB && q.steps[1].scale_in == 0));
+      if (!starts) {
+        int64_t n = 1;
+        for (int32_t b : prev) {
+          const int nh = r * (c - 1);
+          n *= b < nh ? (h ? h[b] : D) : (v ? v[b - nh] : D);
+        }
+        ok = ok && q.steps[0].out == n;
+      }
+      check(ok, "reverse step legs", r, c, D, 104);
+      prev = q.cut_legs;
+    }
+  }
   // a left cut ending at column cut q meets the right cut ending there
   for (int q = 1; q < c; ++q) {
     tn::Plan a, b;

@@ -104,3 +104,22 @@ def test_stream_option_range_and_workspace():
         assert sizes[2] - sizes[1] == 2 * (sizes[1] - sizes[0])
     finally:
         lib.tn_set_option(tn.TN_OPT_ENV_STREAMS, 4)
+
+
+def test_in_column_environments_budget():
+    # environments inside columns add workspace only within the budget
+    try:
+        sizes = {}
+        for gib in (0, 32):
+            assert lib.tn_set_option(tn.TN_OPT_ENV_ROWS, gib) == tn.TN_OK
+            sizes[gib] = workspace(6, 6, 4, [[0], [7], [8, 14]])[1]
+        assert sizes[32] > sizes[0]
+        assert lib.tn_set_option(tn.TN_OPT_ENV_ROWS, -1) == tn.TN_EINVAL
+        assert lib.tn_set_option(tn.TN_OPT_ENV_ROWS, 2000) == tn.TN_EINVAL
+        # 12 x 12 at D = 4 in float64 would add about 140 GiB: over the budget
+        assert lib.tn_set_option(tn.TN_OPT_ENV_ROWS, 32) == tn.TN_OK
+        big = workspace(12, 12, 4, [[0]])[1]
+        assert lib.tn_set_option(tn.TN_OPT_ENV_ROWS, 0) == tn.TN_OK
+        assert workspace(12, 12, 4, [[0]])[1] == big
+    finally:
+        lib.tn_set_option(tn.TN_OPT_ENV_ROWS, 32)

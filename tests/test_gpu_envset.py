@@ -56,11 +56,15 @@ def family(rows, cols, seed, extra=()):
     return nets + [list(x) for x in extra]
 
 
-def run_family(tn, rows, cols, D, seed, prec="f64", hdim=None, vdim=None, nets=None):
+def run_family(tn, rows, cols, D, seed, prec="f64", hdim=None, vdim=None, nets=None, rows_env=32):
     base = li.uniform(rows, cols, D, seed, hdim=hdim, vdim=vdim)
     repl = li.uniform(rows, cols, D, seed + 1000, hdim=hdim, vdim=vdim)
     nets = family(rows, cols, seed) if nets is None else nets
-    es = tn.EnvSet(rows, cols, D, hdim=hdim, vdim=vdim, networks=nets, precision=prec)
+    tn.tn_set_option(tn.TN_OPT_ENV_ROWS, rows_env)
+    try:
+        es = tn.EnvSet(rows, cols, D, hdim=hdim, vdim=vdim, networks=nets, precision=prec)
+    finally:
+        tn.tn_set_option(tn.TN_OPT_ENV_ROWS, 32)
     print(f"[gpu] envset {rows}x{cols} D={D} {prec}: {len(nets)} networks", flush=True)
     got = es.run([dev(s) for s in base], [dev(repl[i]) for n in nets for i in n])
     es.close()
@@ -112,12 +116,12 @@ def test_envset_reduced_precision(tn, prec):
 
 
 def test_last_column_networks_equal_full_sweep_bitwise(tn):
-    # with every substituted site in the last column a network is the full
-    # column sweep's own arithmetic
+    # with column environments only, a network whose substituted sites are in
+    # the last column is the full column sweep's own arithmetic
     rows, cols, D = 6, 7, 4
     nets = [[r * cols + cols - 1] for r in range(rows)] + [[cols - 1, 2 * cols - 1], []]
     for prec in ("f64", "f32"):
-        base, repl, nets_, got = run_family(tn, rows, cols, D, 3, prec=prec, nets=nets)
+        base, repl, nets_, got = run_family(tn, rows, cols, D, 3, prec=prec, nets=nets, rows_env=0)
         plan = tn.tn_plan_grid(rows, cols, D, order=P.COLSWEEP)
         for net, g in zip([[]] + nets, got):
             sites = list(base)
@@ -181,3 +185,19 @@ def test_stream_count_does_not_change_results(tn, streams):
     es.close()
     for a, b in zip(ref, got):
         assert (a.status, a.sign, a.mantissa, a.exp2_sum) == (b.status, b.sign, b.mantissa, b.exp2_sum)
+
+
+@pytest.mark.parametrize("rows,cols,D,prec", [(6, 6, 4, "f64"), (5, 7, 3, "f64"), (7, 5, 2, "f32"),
+                                              (4, 4, 4, "bf16x3"), (2, 6, 3, "f64")])
+def test_column_and_in_column_environments_agree(tn, rows, cols, D, prec):
+    # the same family with environments inside columns and with whole
+    # columns only: both against the oracle, and against each other
+    a = run_family(tn, rows, cols, D, 40 + rows, prec=prec, rows_env=32)
+    b = run_family(tn, rows, cols, D, 40 + rows, prec=prec, rows_env=0)
+    base, repl, nets, _ = a
+    for net, x, y in zip([[]] + nets, a[3], b[3]):
+        ref = expected(base, repl, rows, cols, net)
+        check(x, ref, prec)
+        check(y, ref, prec)
+        tol = 1e-12 if prec == "f64" else 1e-5
+        assert abs(x.log_abs - y.log_abs) <= tol * max(1.0, abs(ref.log_abs))
