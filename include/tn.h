@@ -286,9 +286,10 @@ tn_status tn_envset_create(const tn_grid* grid, int32_t precision, int32_t n,
  * network, outs[1 + k] network k.  Issued on hip_stream and on the set's own
  * streams (TN_OPT_ENV_STREAMS), which are joined back into hip_stream;
  * blocks until the results are copied back.  One run at a time per set (a
- * run reuses the set's host tables and workspace regions).  Errors: TN_EINVAL
- * (NULL pointer), TN_EDEVICE, TN_ENONFINITE (a network met a non-finite value: its outs[] status says
- * so, the other results are valid).                                         */
+ * run reuses the set's host tables and workspace regions).  Errors:
+ * TN_EINVAL (NULL pointer), TN_EDEVICE, TN_ENONFINITE (a network met a
+ * non-finite value: its outs[] status says so, the other results are
+ * valid).                                                                   */
 tn_status tn_envset_run(tn_envset* set, const double* const* base, const double* const* subst,
                         void* hip_stream, tn_result* outs);
 
