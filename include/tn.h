@@ -410,6 +410,17 @@ tn_status tn_server_destroy(tn_server* server);
  *                        environments.  Read when the workspace is sized and
  *                        when the set is created.                          */
 #define TN_OPT_ENV_ROWS 7
+/*   TN_OPT_ENV_SITES   : 1 (default) = with environments inside columns, a
+ *                        network that replaces one site whose step boundary
+ *                        has at most 2^20 entries is the site environment
+ *                        (the boundary before the site's sweep step and the
+ *                        boundary of all sites after it, contracted over
+ *                        their common legs into a matrix over the site's
+ *                        legs, once per site) dotted with the replacing
+ *                        tensor; otherwise (and with 0) the site is absorbed
+ *                        and closed against the boundary after it.  Read
+ *                        when the set is created.                           */
+#define TN_OPT_ENV_SITES 8
 tn_status tn_set_option(int32_t option, int64_t value);
 
 /* ------------------------------------------------------------ profiling

@@ -15,6 +15,7 @@ from ._native import (  # noqa: F401
     tn_plan_grid, tn_plan_stats, tn_plan_text, tn_contract_grid, tn_set_option,
     TN_OPT_KERNEL_IMPL, TN_OPT_BATCH_THREADS, TN_OPT_FUSE_STEPS, TN_OPT_CHUNK_SCHEDULE,
     TN_OPT_QUADRANT_STREAMS, TN_OPT_CHAIN_STEPS, TN_OPT_ENV_STREAMS, TN_OPT_ENV_ROWS,
+    TN_OPT_ENV_SITES,
     tn_profile_enable, tn_profile_read,
     Batch, tn_batch_workspace, tn_contract_batch, Server, EnvSet,
     plan_grid, contract_grid, device_sites, workspace_for,

@@ -215,6 +215,7 @@ TN_OPT_QUADRANT_STREAMS = 4
 TN_OPT_CHAIN_STEPS = 5
 TN_OPT_ENV_STREAMS = 6
 TN_OPT_ENV_ROWS = 7
+TN_OPT_ENV_SITES = 8
 
 
 class tn_kernel_stat(C.Structure):

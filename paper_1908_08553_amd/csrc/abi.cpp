@@ -353,6 +353,11 @@ tn_status tn_set_option(int32_t option, int64_t value) {
     tn::set_absorb_policy(static_cast<int32_t>(value));
     return TN_OK;
   }
+  if (option == TN_OPT_ENV_SITES) {
+    if (value < 0 || value > 1) return fail(TN_EINVAL, "TN_OPT_ENV_SITES must be 0 or 1");
+    tn::set_env_sites(static_cast<int32_t>(value));
+    return TN_OK;
+  }
   if (option == TN_OPT_ENV_ROWS) {
     if (value < 0 || value > 1024) return fail(TN_EINVAL, "TN_OPT_ENV_ROWS must be 0..1024 (GiB)");
     tn::set_env_rows(static_cast<int32_t>(value));

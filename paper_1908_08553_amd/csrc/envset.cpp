@@ -55,7 +55,18 @@ struct EnvSetImpl {
   bool rows_on = false;
   std::vector<Plan> fwd, rev;
   std::vector<Plan> cuts;                   // distinct network plans
-  std::vector<int32_t> net_plan;            // n + 1 entries (0: base network)
+  std::vector<int32_t> net_plan;            // n + 1 entries (0: base network; -1: site path)
+  // Single-site networks through site environments (with rows_on): per site,
+  // the shapes around its sweep step and the networks (index, substitution)
+  // that replace it.
+  struct SiteWork {
+    int64_t k;
+    SiteEnvArgs args;                       // pointers and partials filled per run
+    SiteDot fold;                           // site pointer and output filled per run
+    std::vector<std::pair<int32_t, int32_t>> nets;
+  };
+  std::vector<SiteWork> sites_work;
+  size_t site_partials_off = 0, site_partials_bytes = 0;
   std::vector<int32_t> sub_first, sub_count, sub_site;
   std::vector<size_t> left_off, right_off, fwd_off, rev_off;
   int32_t S = 1;                            // streams the networks are spread over
@@ -81,6 +92,8 @@ int32_t g_env_streams = 4;
 void set_env_streams(int32_t n) { g_env_streams = n; }
 int32_t g_env_rows = 32;
 void set_env_rows(int32_t gib) { g_env_rows = gib; }
+int32_t g_env_sites = 1;
+void set_env_sites(int32_t on) { g_env_sites = on ? 1 : 0; }
 
 namespace {
 
@@ -160,7 +173,53 @@ tn_status layout(EnvSetImpl& es, const tn_grid& grid, int32_t n, const int32_t* 
   // sweep's own arithmetic)
   s = plan_for(total_steps - R, total_steps, &es.net_plan[0]);
   if (s != TN_OK) return s;
+  es.sites_work.clear();
+  std::map<int64_t, size_t> site_index;
   for (int32_t k = 0; k < n; ++k) {
+    if (es.rows_on && g_env_sites && es.sub_count[k] == 1) {
+      const int32_t site = es.sub_site[es.sub_first[k]];
+      if (site < 0 || site >= R * C) { err = "substituted site out of range"; return TN_EINVAL; }
+      const int64_t step = static_cast<int64_t>(site % C) * R + site / C;
+      const Step& st = full.steps[step];
+      // measured: a site environment beats absorbing and closing each
+      // single-site network while the boundary around the step stays within
+      // about 2^20 entries (8 x 8 at chi = 2), not at 4^11 (10 x 10)
+      if (st.K * st.N <= kSiteEnvMaxXY && st.pre * std::max(st.K, st.N) * st.post <= (1 << 20)) {
+        auto it = site_index.find(step);
+        if (it == site_index.end()) {
+          EnvSetImpl::SiteWork w;
+          w.k = step;
+          std::memset(&w.args, 0, sizeof(w.args));
+          w.args.P = st.pre; w.args.Q = st.post;
+          w.args.X = static_cast<int32_t>(st.K); w.args.Y = static_cast<int32_t>(st.N);
+          w.args.l_f64 = (es.prec == TN_PREC_F64 || (step > 0 && full.steps[step - 1].last_col)) ? 1 : 0;
+          w.args.r_f64 = (es.prec == TN_PREC_F64 || st.last_col) ? 1 : 0;
+          w.args.blocks = site_env_blocks(st.pre, st.post, w.args.X, w.args.Y);
+          // the site folded as the step folds it: canonical dims and strides
+          std::memset(&w.fold, 0, sizeof(w.fold));
+          int32_t cdims[4];
+          int64_t cstr[4];
+          int32_t nd = 0;
+          const int32_t r = st.r, c = st.c;
+          if (c > 0) cdims[nd++] = full.hdim[static_cast<size_t>(r) * (C - 1) + c - 1];
+          if (r > 0) cdims[nd++] = full.vdim[static_cast<size_t>(r - 1) * C + c];
+          if (c < C - 1) cdims[nd++] = full.hdim[static_cast<size_t>(r) * (C - 1) + c];
+          if (r < R - 1) cdims[nd++] = full.vdim[static_cast<size_t>(r) * C + c];
+          int64_t stride = 1;
+          for (int32_t a = nd - 1; a >= 0; --a) { cstr[a] = stride; stride *= cdims[a]; }
+          w.fold.ndim = st.nperm;
+          for (int32_t a = 0; a < st.nperm; ++a) {
+            w.fold.dims[a] = cdims[st.perm[a]];
+            w.fold.cstride[a] = cstr[st.perm[a]];
+          }
+          it = site_index.emplace(step, es.sites_work.size()).first;
+          es.sites_work.push_back(w);
+        }
+        es.sites_work[it->second].nets.push_back({k, es.sub_first[k]});
+        es.net_plan[k + 1] = -1;
+        continue;
+      }
+    }
     int64_t k0 = total_steps - R, k1 = total_steps - 1;   // no substitution: the base network
     if (es.sub_count[k] > 0) {
       k0 = total_steps; k1 = -1;
@@ -225,6 +284,13 @@ tn_status layout(EnvSetImpl& es, const tn_grid& grid, int32_t n, const int32_t* 
     if (p.cut_open_end) parts = std::max(parts, env_cap_blocks(p.steps.back().out));
   }
   off += es.shared_bytes * es.S;
+  es.site_partials_bytes = 0;
+  for (const auto& w : es.sites_work)
+    es.site_partials_bytes = std::max(es.site_partials_bytes,
+                                      align_up(sizeof(double) * static_cast<size_t>(w.args.blocks) *
+                                               w.args.X * w.args.Y));
+  es.site_partials_off = off;
+  off += es.site_partials_bytes * es.S;
   es.recs_off = off;
   off = align_up(off + sizeof(EnvRec) * std::max<size_t>(es.n_recs(), 1));
   es.partials_off = off;
@@ -400,8 +466,38 @@ tn_status envset_run(EnvSetImpl* es, const double* const* base, const double* co
       st = barrier(1 + S);
       if (st != TN_OK) return st;
     }
+    // single-site networks: one site environment per site, dotted with each
+    // replacing site
+    for (size_t w = 0; w < es->sites_work.size(); ++w) {
+      const int32_t si = static_cast<int32_t>(w % S);
+      EnvSetImpl::SiteWork& sw = es->sites_work[w];
+      SiteEnvArgs a = sw.args;
+      a.L = nullptr; a.l_rec = nullptr; a.Rv = nullptr; a.r_rec = nullptr;
+      if (sw.k > 0) seed_of(sw.k, &a.L, &a.l_rec);
+      if (sw.k < total_steps - 1) cap_of(sw.k, &a.Rv, &a.r_rec);
+      a.partials = reinterpret_cast<double*>(ws + es->site_partials_off + es->site_partials_bytes * si);
+      timers[si]->before();
+      e = launch_site_env(a, streams[si]);
+      timers[si]->after("site_env",
+                        8.0 * static_cast<double>(a.P * a.Q) * (a.X + a.Y), 2.0 * static_cast<double>(a.P * a.Q) * a.X * a.Y);
+      if (e != hipSuccess) { err = std::string("site environment: ") + hipGetErrorString(e); return TN_EDEVICE; }
+      for (size_t i0 = 0; i0 < sw.nets.size(); i0 += kSiteDotsMax) {
+        SiteDot dots[kSiteDotsMax];
+        const int32_t nd = static_cast<int32_t>(std::min<size_t>(kSiteDotsMax, sw.nets.size() - i0));
+        for (int32_t i = 0; i < nd; ++i) {
+          dots[i] = sw.fold;
+          dots[i].site = subst[sw.nets[i0 + i].second];
+          dots[i].out = results + sw.nets[i0 + i].first + 1;
+        }
+        timers[si]->before();
+        e = launch_site_dots(a, dots, nd, streams[si]);
+        timers[si]->after("site_dots", 0.0, 0.0);
+        if (e != hipSuccess) { err = std::string("site dots: ") + hipGetErrorString(e); return TN_EDEVICE; }
+      }
+    }
     for (int32_t k = 0; k <= n; ++k) {
       const int32_t si = k % S;
+      if (es->net_plan[k] < 0) continue;
       const Plan& p = es->cuts[es->net_plan[k]];
       for (int32_t t = 0; t < R * C; ++t) es->sites[t] = base[t];
       if (k > 0) {

@@ -34,5 +34,8 @@ extern int32_t g_env_streams;
 // (0: none, only column environments).
 void set_env_rows(int32_t gib);
 extern int32_t g_env_rows;
+// 1: single-site networks through site environments (with rows inside columns).
+void set_env_sites(int32_t on);
+extern int32_t g_env_sites;
 
 }  // namespace tn

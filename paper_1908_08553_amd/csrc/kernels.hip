@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstring>
 #include <cmath>
 
 #include "absorb_device.hpp"
@@ -399,6 +400,128 @@ __global__ __launch_bounds__(kBlock) void env_tap_kernel(DevState* state, const 
   *rec = out;
 }
 
+// ------------------------------------------------------- site environments
+constexpr int kSiteTMax = 128;                                // (p, q) positions per tile
+constexpr int kSiteLds = 48 * 1024;                           // LDS bytes for the two tiles
+constexpr int kSitePer = (kSiteEnvMaxXY + kBlock - 1) / kBlock;   // (x, y) pairs per thread
+
+__device__ inline double env_scale(const EnvRec* rec) {
+  if (!rec) return 1.0;
+  const int32_t e = rec->e;
+  return ldexp(1.0, (e == kExpZero || e == kExpBad) ? 0 : -e);
+}
+
+__device__ inline double load_any(const void* p, int64_t i, int32_t f64) {
+  return f64 ? static_cast<const double*>(p)[i] : static_cast<double>(static_cast<const float*>(p)[i]);
+}
+
+// positions per tile: as many as fit the LDS budget with one pad entry per row
+__host__ __device__ inline int site_tile(int rows) {
+  int t = kSiteLds / (8 * rows) - 1;
+  return t > kSiteTMax ? kSiteTMax : (t < 1 ? 1 : t);
+}
+
+__global__ __launch_bounds__(kBlock) void site_env_kernel(SiteEnvArgs a) {
+  extern __shared__ double sm[];
+  const int rows = a.X + a.Y;
+  const int T = site_tile(rows), ld = T + 1;   // padded row stride: rows fall in distinct banks
+  double* Ls = sm;                             // [X][ld]
+  double* Rs = sm + a.X * ld;                  // [Y][ld]
+  const int64_t n = a.P * a.Q;
+  const int32_t nxy = a.X * a.Y;
+  const double sl = env_scale(a.l_rec), sr = env_scale(a.r_rec);
+  double acc[kSitePer];
+  for (int i = 0; i < kSitePer; ++i) acc[i] = 0.0;
+  for (int64_t t0 = static_cast<int64_t>(blockIdx.x) * T; t0 < n;
+       t0 += static_cast<int64_t>(gridDim.x) * T) {
+    for (int idx = threadIdx.x; idx < rows * T; idx += blockDim.x) {
+      const int row = idx / T, t = idx % T;
+      const int64_t j = t0 + t;
+      double v = 0.0;
+      if (j < n) {
+        const int64_t p = j / a.Q, q = j % a.Q;
+        if (row < a.X) {
+          v = a.L ? load_any(a.L, (p * a.X + row) * a.Q + q, a.l_f64) * sl : 1.0;
+        } else {
+          const int y = row - a.X;
+          v = a.Rv ? load_any(a.Rv, (p * a.Y + y) * a.Q + q, a.r_f64) * sr : 1.0;
+        }
+      }
+      if (row < a.X) Ls[row * ld + t] = v;
+      else Rs[(row - a.X) * ld + t] = v;
+    }
+    __syncthreads();
+    for (int i = 0; i < kSitePer; ++i) {
+      const int xy = threadIdx.x + i * kBlock;
+      if (xy < nxy) {
+        const int x = xy / a.Y, y = xy % a.Y;
+        double s = 0.0;
+        for (int t = 0; t < T; ++t) s += Ls[x * ld + t] * Rs[y * ld + t];
+        acc[i] += s;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < kSitePer; ++i) {
+    const int xy = threadIdx.x + i * kBlock;
+    if (xy < nxy) a.partials[static_cast<int64_t>(blockIdx.x) * nxy + xy] = acc[i];
+  }
+}
+
+struct SiteDots {
+  SiteDot d[kSiteDotsMax];
+  int32_t n;
+};
+
+__global__ __launch_bounds__(kBlock) void site_dots_kernel(SiteEnvArgs a, SiteDots ds) {
+  extern __shared__ double env[];         // [X * Y]
+  __shared__ double red[kBlock];
+  __shared__ int red_bad[kBlock];
+  const int32_t nxy = a.X * a.Y;
+  for (int xy = threadIdx.x; xy < nxy; xy += blockDim.x) {
+    double s = 0.0;
+    for (int32_t b = 0; b < a.blocks; ++b) s += a.partials[static_cast<int64_t>(b) * nxy + xy];
+    env[xy] = s;
+  }
+  __syncthreads();
+  int64_t E = 0;
+  int bad0 = 0;
+  for (const EnvRec* rec : {a.l_rec, a.r_rec}) {
+    if (!rec) continue;
+    const int32_t e = rec->e;
+    if (e == kExpBad) bad0 = 1;
+    E += rec->bias + ((e == kExpZero || e == kExpBad) ? 0 : e);
+  }
+  for (int32_t k = 0; k < ds.n; ++k) {
+    const SiteDot& d = ds.d[k];
+    double s = 0.0;
+    int bad = 0;
+    for (int xy = threadIdx.x; xy < nxy; xy += blockDim.x) {
+      int64_t rem = xy, off = 0;
+      for (int ax = d.ndim - 1; ax >= 0; --ax) {
+        const int64_t i = rem % d.dims[ax];
+        rem /= d.dims[ax];
+        off += i * d.cstride[ax];
+      }
+      const double o = d.site[off];
+      bad |= !isfinite(o);
+      s += env[xy] * o;
+    }
+    red[threadIdx.x] = s;
+    red_bad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+      if (static_cast<int>(threadIdx.x) < st) {
+        red[threadIdx.x] += red[threadIdx.x + st];
+        red_bad[threadIdx.x] |= red_bad[threadIdx.x + st];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *d.out = dev::assemble_result(red[0], E, bad0 | red_bad[0]);
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 hipError_t launch_stage(const StageDesc* descs, int32_t n_steps, StagedArrays st, StageTargets t,
@@ -516,6 +639,40 @@ hipError_t launch_env_cap(const void* B, const void* Rv, int64_t n, int32_t f64,
   const int64_t blocks = env_cap_blocks(n);
   hipLaunchKernelGGL(env_cap_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, stream,
                      B, Rv, n, chunk, f64, slot_b, rec, partials);
+  return hipGetLastError();
+}
+
+int32_t site_env_blocks(int64_t P, int64_t Q, int32_t X, int32_t Y) {
+  const int64_t T = site_tile(X + Y);
+  const int64_t tiles = (P * Q + T - 1) / T;
+  return static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(tiles, 256)));
+}
+
+hipError_t launch_site_env(const SiteEnvArgs& a, hipStream_t stream) {
+  if (a.X < 1 || a.Y < 1 || a.X * a.Y > kSiteEnvMaxXY || a.P < 1 || a.Q < 1 ||
+      a.blocks != site_env_blocks(a.P, a.Q, a.X, a.Y))
+    return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * static_cast<size_t>(a.X + a.Y) * (site_tile(a.X + a.Y) + 1);
+  hipLaunchKernelGGL(site_env_kernel, dim3(static_cast<uint32_t>(a.blocks)), dim3(kBlock), lds,
+                     stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_site_dots(const SiteEnvArgs& a, const SiteDot* dots, int32_t n,
+                            hipStream_t stream) {
+  if (n < 1 || n > kSiteDotsMax || a.X * a.Y > kSiteEnvMaxXY) return hipErrorInvalidValue;
+  SiteDots ds;
+  std::memset(&ds, 0, sizeof(ds));
+  for (int32_t i = 0; i < n; ++i) {
+    int64_t entries = 1;
+    for (int32_t ax = 0; ax < dots[i].ndim; ++ax) entries *= dots[i].dims[ax];
+    if (dots[i].ndim < 0 || dots[i].ndim > 4 || entries != static_cast<int64_t>(a.X) * a.Y)
+      return hipErrorInvalidValue;
+    ds.d[i] = dots[i];
+  }
+  ds.n = n;
+  const size_t lds = sizeof(double) * static_cast<size_t>(a.X) * a.Y;
+  hipLaunchKernelGGL(site_dots_kernel, dim3(1), dim3(kBlock), lds, stream, a, ds);
   return hipGetLastError();
 }
 

@@ -227,6 +227,40 @@ int64_t env_cap_blocks(int64_t n);
 hipError_t launch_env_cap(const void* B, const void* Rv, int64_t n, int32_t f64,
                           const int32_t* slot_b, const EnvRec* rec, double* partials,
                           hipStream_t stream);
+// Site environment (cached environments): with L the boundary before sweep
+// step k, as [P][X][Q] (X: the legs step k contracts), and Rv the boundary of
+// all sites after step k, as [P][Y][Q] (Y: the legs step k writes), both in the
+// sweep's leg order, Env[x][y] = sum_{p,q} (L 2^-el)(Rv 2^-er) is the network
+// with site k removed.  A null L or Rv is the scalar 1 (nothing before the
+// first or after the last step).  launch_site_env writes `blocks` partial
+// matrices (fixed split of the P*Q range); launch_site_dots sums them in a
+// fixed order and dots Env with each listed site tensor, folded to [X][Y] by
+// the step's axis order, writing sign, exponent and log|Z| per site.
+constexpr int32_t kSiteEnvMaxXY = 6561;   // X * Y up to 81 * 81
+constexpr int32_t kSiteDotsMax = 8;
+struct SiteEnvArgs {
+  const void* L;
+  const void* Rv;
+  int32_t l_f64, r_f64;
+  int64_t P, Q;
+  int32_t X, Y;
+  const EnvRec* l_rec;   // nullable: exponent 0
+  const EnvRec* r_rec;
+  double* partials;      // [blocks][X * Y]
+  int32_t blocks;
+};
+struct SiteDot {
+  const double* site;    // canonical float64 site tensor (device)
+  int64_t cstride[4];    // canonical stride of each folded axis
+  int32_t dims[4];       // folded-order dims (X legs, then Y legs)
+  int32_t ndim;
+  tn_result* out;        // device
+};
+int32_t site_env_blocks(int64_t P, int64_t Q, int32_t X, int32_t Y);
+hipError_t launch_site_env(const SiteEnvArgs& a, hipStream_t stream);
+hipError_t launch_site_dots(const SiteEnvArgs& a, const SiteDot* dots, int32_t n,
+                            hipStream_t stream);
+
 // Tap: the record of the boundary a cut plan ends in, whose largest-magnitude
 // exponent is *slot_last (null inside a column: no shift), from the exponent
 // sums of finalize (one block).

@@ -56,15 +56,18 @@ def family(rows, cols, seed, extra=()):
     return nets + [list(x) for x in extra]
 
 
-def run_family(tn, rows, cols, D, seed, prec="f64", hdim=None, vdim=None, nets=None, rows_env=32):
+def run_family(tn, rows, cols, D, seed, prec="f64", hdim=None, vdim=None, nets=None, rows_env=32,
+               sites=1):
     base = li.uniform(rows, cols, D, seed, hdim=hdim, vdim=vdim)
     repl = li.uniform(rows, cols, D, seed + 1000, hdim=hdim, vdim=vdim)
     nets = family(rows, cols, seed) if nets is None else nets
     tn.tn_set_option(tn.TN_OPT_ENV_ROWS, rows_env)
+    tn.tn_set_option(tn.TN_OPT_ENV_SITES, sites)
     try:
         es = tn.EnvSet(rows, cols, D, hdim=hdim, vdim=vdim, networks=nets, precision=prec)
     finally:
         tn.tn_set_option(tn.TN_OPT_ENV_ROWS, 32)
+        tn.tn_set_option(tn.TN_OPT_ENV_SITES, 1)
     print(f"[gpu] envset {rows}x{cols} D={D} {prec}: {len(nets)} networks", flush=True)
     got = es.run([dev(s) for s in base], [dev(repl[i]) for n in nets for i in n])
     es.close()
@@ -190,17 +193,19 @@ def test_stream_count_does_not_change_results(tn, streams):
 @pytest.mark.parametrize("rows,cols,D,prec", [(6, 6, 4, "f64"), (5, 7, 3, "f64"), (7, 5, 2, "f32"),
                                               (4, 4, 4, "bf16x3"), (2, 6, 3, "f64")])
 def test_column_and_in_column_environments_agree(tn, rows, cols, D, prec):
-    # the same family with environments inside columns and with whole
-    # columns only: both against the oracle, and against each other
-    a = run_family(tn, rows, cols, D, 40 + rows, prec=prec, rows_env=32)
-    b = run_family(tn, rows, cols, D, 40 + rows, prec=prec, rows_env=0)
+    # the same family with site environments, with environments inside
+    # columns only, and with whole columns only: each against the oracle, and
+    # against each other
+    a = run_family(tn, rows, cols, D, 40 + rows, prec=prec, rows_env=32, sites=1)
+    b = run_family(tn, rows, cols, D, 40 + rows, prec=prec, rows_env=32, sites=0)
+    c = run_family(tn, rows, cols, D, 40 + rows, prec=prec, rows_env=0)
     base, repl, nets, _ = a
-    for net, x, y in zip([[]] + nets, a[3], b[3]):
+    for net, x, y, z in zip([[]] + nets, a[3], b[3], c[3]):
         ref = expected(base, repl, rows, cols, net)
-        check(x, ref, prec)
-        check(y, ref, prec)
         tol = 1e-12 if prec == "f64" else 1e-5
-        assert abs(x.log_abs - y.log_abs) <= tol * max(1.0, abs(ref.log_abs))
+        for g in (x, y, z):
+            check(g, ref, prec)
+            assert abs(g.log_abs - z.log_abs) <= tol * max(1.0, abs(ref.log_abs))
 
 
 @pytest.mark.skip(reason="graph capture of an environment-set run was taken out after its first "
