@@ -127,3 +127,48 @@ class ObservableSet:
         for h in (self.batch, self.env):
             if h is not None:
                 h.close()
+
+
+def main(argv=None):
+    """Time repeated observable evaluations of a random real PEPS (N(0,1)
+    tensors from a seed): python -m paper_1908_08553_amd.peps --rows 10
+    --cols 10 --chi 2 --mode env --reps 5."""
+    import argparse
+    import time
+
+    import numpy as np
+    import torch
+    p = argparse.ArgumentParser(description=main.__doc__)
+    p.add_argument("--rows", type=int, default=10)
+    p.add_argument("--cols", type=int, default=10)
+    p.add_argument("--chi", type=int, default=2)
+    p.add_argument("--mode", default="auto", choices=["auto", "batch", "env"])
+    p.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16x3"])
+    p.add_argument("--reps", type=int, default=5)
+    p.add_argument("--seed", type=int, default=1)
+    a = p.parse_args(argv)
+    rng = np.random.default_rng(a.seed)
+    peps = []
+    for r in range(a.rows):
+        for c in range(a.cols):
+            legs = (c > 0) + (r > 0) + (c < a.cols - 1) + (r < a.rows - 1)
+            peps.append(torch.as_tensor(rng.standard_normal((2,) + (a.chi,) * legs),
+                                        dtype=torch.float64).cuda())
+    sx = torch.tensor([[0.0, 0.5], [0.5, 0.0]], dtype=torch.float64).cuda()
+    sz = torch.tensor([[0.5, 0.0], [0.0, -0.5]], dtype=torch.float64).cuda()
+    obs = ObservableSet(a.rows, a.cols, a.chi, precision=a.precision, mode=a.mode)
+    out = obs.run(peps, sx, sz)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.reps):
+        out = obs.run(peps, sx, sz)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.reps
+    print(f"{a.rows}x{a.cols} chi={a.chi} mode={obs.mode} {a.precision}: {obs.count} networks, "
+          f"{1e3 * dt:.3f} ms per evaluation, log norm {out['results'][0].log_abs:.12f}, "
+          f"mean m^z {sum(out['mz']) / len(out['mz']):.6f}", flush=True)
+    obs.close()
+
+
+if __name__ == "__main__":
+    main()
