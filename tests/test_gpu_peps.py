@@ -135,3 +135,27 @@ def test_observable_set_env_mode_matches_oracle(tn, rows, cols, chi, seed):
     for key in ("mx", "mz", "czz"):
         np.testing.assert_allclose(got[key], want[key], rtol=0, atol=1e-11, err_msg=key)
         assert got[key] == again[key]
+
+
+def test_auto_mode_choice_and_agreement_8x8(tn):
+    # mode "auto" takes the batch for 6 x 6 (boundaries of 4^7 entries) and
+    # cached environments (with site environments) for 8 x 8 (4^9); at 8 x 8
+    # both modes give the same observables
+    from paper_1908_08553_amd.peps import ObservableSet
+    small = ObservableSet(6, 6, 2)
+    assert small.mode == "batch"
+    small.close()
+    peps = [dev(A) for A in li.peps(8, 8, 2, 17)]
+    auto = ObservableSet(8, 8, 2)
+    assert auto.mode == "env"
+    print("[gpu] 8x8 observables, environments", flush=True)
+    a = auto.run(peps, dev(SX), dev(SZ))
+    auto.close()
+    batch = ObservableSet(8, 8, 2, mode="batch")
+    print("[gpu] 8x8 observables, batch", flush=True)
+    b = batch.run(peps, dev(SX), dev(SZ))
+    batch.close()
+    na, nb = a["results"][0], b["results"][0]
+    assert na.sign == nb.sign and abs(na.log_abs - nb.log_abs) <= 1e-12 * abs(nb.log_abs)
+    for key in ("mx", "mz", "czz"):
+        np.testing.assert_allclose(a[key], b[key], rtol=0, atol=1e-12, err_msg=key)
