@@ -27,7 +27,10 @@ Modules (each function cites the passage of the paper it follows):
                        (paper §3 and §5): double-layer sites, the observable
                        set m^x, m^z, c_ij, and brute-force amplitudes.
 
-Parity status of every function is stated in its docstring; nothing here is
-"parity unpinned": each is pinned by brute force, a closed form, a textbook
-method or an invariant in ``tests/test_oracle_pins.py``.
+Parity status of every function is stated in its docstring.  Each is pinned
+in ``tests/test_oracle_pins.py`` (and ``tests/test_peps_oracle.py`` for
+``peps``) by brute force, a closed form, a textbook method or an invariant:
+contraction values by brute force over bonds and spins, the row transfer
+matrix and closed forms; every plan order, SWEEP_AUTO's orientation rule
+included, by closed forms for its bottleneck, flops and first steps.
 """

@@ -117,24 +117,3 @@ def contract_grid(sites, rows, cols, order=P.COLSWEEP, quad_h=0, quad_w=0) -> Re
                     quad_h=quad_h, quad_w=quad_w)
     return contract(sites, p)
 
-
-def run_prefix(sites: Sequence[np.ndarray], plan: P.Plan, n_steps: int) -> int:
-    """Run the first ``n_steps`` steps of unit 0 exactly as ``run_unit`` does
-    (used to time the oracle on a bounded part of a large contraction);
-    returns the plan flops of the steps run."""
-    B = None
-    flops = 0
-    for s in plan.steps[:n_steps]:
-        if s.unit != 0:
-            break
-        S = staged(sites[s.site[0] * plan.cols + s.site[1]], s)
-        if s.kind == "INIT":
-            B = S.reshape(-1).copy()
-        else:
-            X = B.reshape(s.pre, s.K, s.post)
-            Y = np.tensordot(X, S, axes=([1], [0]))
-            B = np.ascontiguousarray(Y.transpose(0, 2, 1)).reshape(-1)
-        if s.rescale >= 0:
-            B, _ = _rescale(B)
-        flops += s.flops
-    return flops

@@ -4,7 +4,7 @@ A thin ctypes binding over ``libtn.so`` (the C ABI in ``include/tn.h``): it
 only marshals arguments.  Every step of a contraction runs in the library's
 HIP kernels; PyTorch supplies device memory and the stream.  Importing this
 package fails loudly if the library has not been built
-(``python -m paper_1908_08553_amd.build``).
+(``python paper_1908_08553_amd/build.py``).
 """
 from ._native import (  # noqa: F401
     TN_OK, TN_PENDING, TN_EINVAL, TN_ENOMEM, TN_EBUSY, TN_EDEVICE, TN_ENOTFOUND,

@@ -12,7 +12,7 @@ library_path = os.path.join(_HERE, "libtn.so")
 
 if not os.path.exists(library_path):
     raise ImportError(
-        f"{library_path} is missing: build it with `python -m paper_1908_08553_amd.build`")
+        f"{library_path} is missing: build it with `python paper_1908_08553_amd/build.py`")
 
 # PyTorch bundles its own HIP runtime under the same soname
 # (libamdhip64.so.7).  Loading torch first makes libtn.so bind to that

@@ -1,6 +1,6 @@
 """Build step: compile the HIP/C++ sources into the in-tree shared library.
 
-    python -m paper_1908_08553_amd.build
+    python paper_1908_08553_amd/build.py
 
 produces ``paper_1908_08553_amd/libtn.so`` for gfx950 with hipcc.  Packed
 FP32 instructions are disabled for device code (``-packed-fp32-ops``).
@@ -11,6 +11,7 @@ import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -33,14 +34,21 @@ def sources():
 def build(verbose: bool = False) -> str:
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
+    cmds = []
     objs = []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [HIPCC, *COMMON, "-x", "hip", *DEVICE_FLAGS, "-c", src, "-o", obj]
+        cmds.append([HIPCC, *COMMON, "-x", "hip", *DEVICE_FLAGS, "-c", src, "-o", obj])
+        objs.append(obj)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1)), 16))
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    with ThreadPoolExecutor(jobs) as pool:
+        list(pool.map(compile_one, cmds))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-pthread", *DEVICE_FLAGS, "-o", tmp, *objs]
     if verbose:

@@ -126,7 +126,7 @@ def test_fused_ising_d4_13x13_f64(tn):
     for fuse, count in ((1, pair_launches), (2, chunk_launches)):
         got, names = run(tn, sites, 13, 13, P.COLSWEEP, "f64", fuse)
         assert count(names) > 0, names
-        assert got.sign == 1 and abs(got.log_abs - tm) <= 1e-12 * tm, (fuse, got.log_abs, tm)
+        assert got.sign == 1 and abs(got.log_abs - tm) <= 1e-12, (fuse, got.log_abs, tm)
 
 
 @pytest.fixture(scope="module")

@@ -84,7 +84,7 @@ def test_observable_set_matches_oracle(tn, rows, cols, chi, seed):
     obs.close()
     norm = got["results"][0]
     assert norm.status == 0 and norm.sign == want["norm"].sign
-    assert abs(norm.log_abs - want["norm"].log_abs) <= 1e-12 * abs(want["norm"].log_abs)
+    assert abs(norm.log_abs - want["norm"].log_abs) <= 1e-12
     for key in ("mx", "mz", "czz"):
         np.testing.assert_allclose(got[key], want[key], rtol=0, atol=1e-11, err_msg=key)
 
@@ -131,7 +131,7 @@ def test_observable_set_env_mode_matches_oracle(tn, rows, cols, chi, seed):
     obs.close()
     norm = got["results"][0]
     assert norm.status == 0 and norm.sign == want["norm"].sign
-    assert abs(norm.log_abs - want["norm"].log_abs) <= 1e-12 * abs(want["norm"].log_abs)
+    assert abs(norm.log_abs - want["norm"].log_abs) <= 1e-12
     for key in ("mx", "mz", "czz"):
         np.testing.assert_allclose(got[key], want[key], rtol=0, atol=1e-11, err_msg=key)
         assert got[key] == again[key]
@@ -156,6 +156,6 @@ def test_auto_mode_choice_and_agreement_8x8(tn):
     b = batch.run(peps, dev(SX), dev(SZ))
     batch.close()
     na, nb = a["results"][0], b["results"][0]
-    assert na.sign == nb.sign and abs(na.log_abs - nb.log_abs) <= 1e-12 * abs(nb.log_abs)
+    assert na.sign == nb.sign and abs(na.log_abs - nb.log_abs) <= 1e-12
     for key in ("mx", "mz", "czz"):
         np.testing.assert_allclose(a[key], b[key], rtol=0, atol=1e-12, err_msg=key)

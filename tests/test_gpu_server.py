@@ -43,7 +43,7 @@ def test_mixed_requests_match_the_transfer_matrix(tn):
     for t, want, prec, L, D in reqs:
         res, times = srv.wait(t)
         assert res.status == 0 and res.sign == 1
-        tol = 1e-12 * want if prec == "f64" else 1e-5 * want
+        tol = 1e-12 if prec == "f64" else 1e-5 * want
         assert abs(res.log_abs - want) <= tol, (L, D, prec, res.log_abs, want)
         assert times[0] <= times[1] <= times[2]
     st = srv.stats()
@@ -89,10 +89,10 @@ def test_small_requests_overtake_a_running_large_one(tn):
     done_small = []
     for t, w in small:
         res, times = srv.wait(t)
-        assert abs(res.log_abs - w) <= 1e-12 * w
+        assert abs(res.log_abs - w) <= 1e-12
         done_small.append(times[2])
     res, times_big = srv.wait(big)
-    assert abs(res.log_abs - big_want) <= 1e-12 * big_want
+    assert abs(res.log_abs - big_want) <= 1e-12
     # continuous batching: the small requests were admitted while the large
     # one ran and finished before it
     assert max(done_small) < times_big[2]
@@ -126,7 +126,7 @@ def test_error_paths(tn):
     small, want = ising_request(4, 2, 0.4)
     t = srv.submit(4, 4, small, D=2)
     res, _ = srv.wait(t)
-    assert abs(res.log_abs - want) < 1e-12 * want
+    assert abs(res.log_abs - want) <= 1e-12
     with pytest.raises(tn.TnError) as e:          # already retired
         srv.poll(t)
     assert e.value.status == tn.TN_ENOTFOUND

@@ -119,20 +119,20 @@ def test_ising_10x10_contract_equals_transfer_matrix(K):
     tm = nw.transfer_log_z(10, 10, K)
     for order in (P.COLSWEEP, P.QUADRANT):
         r = C.contract_grid(li.ising(10, 10, K), 10, 10, order)
-        assert r.sign == 1 and abs(r.log_abs - tm) < 1e-12 * tm
+        assert r.sign == 1 and abs(r.log_abs - tm) <= 1e-12
 
 
 def test_ising_replica_is_square_of_z():
     tm = nw.transfer_log_z(6, 7, 0.44)
     r = C.contract_grid(li.ising_d4(6, 7, 0.44), 6, 7, P.HEURISTIC)
-    assert abs(r.log_abs - 2 * tm) < 1e-12 * tm
+    assert abs(r.log_abs - 2 * tm) <= 1e-12
 
 
 def test_all_ones_closed_form_large():
     # the paper's timing inputs; Z = D^(#bonds) is exact in the mantissa
     for (L, D) in [(8, 2), (6, 4), (5, 3)]:
         r = C.contract_grid(li.ones(L, L, D), L, L, P.HEURISTIC)
-        assert abs(r.log_abs - cf.all_ones_log(L, L, D)) < 1e-12 * r.log_abs
+        assert abs(r.log_abs - cf.all_ones_log(L, L, D)) <= 1e-12
         if D in (2, 4):
             assert r.mantissa == 0.5
 
@@ -212,6 +212,28 @@ def test_colsweep_closed_forms(R, C_, D):
     assert p.flops == _colsweep_flops(R, C_, D)
     assert len(p.steps) == R * C_
     assert p.slots == C_ - 1
+
+
+@pytest.mark.parametrize("R,C_", [(r, c) for r in range(3, 11) for c in range(3, 11)])
+def test_sweep_auto_closed_forms(R, C_):
+    # §4: the sequential row scheme keeps a boundary of one bond per lattice
+    # line it crosses, so sweeping along the longer side keeps the smaller
+    # boundary; SWEEP_AUTO must pick that orientation (untransposed on ties).
+    for D in (2, 3):
+        p = P.plan_grid(R, C_, D, order=P.SWEEP_AUTO)
+        short, long_ = min(R, C_), max(R, C_)
+        assert p.order == P.COLSWEEP and p.requested == P.SWEEP_AUTO
+        assert p.transpose == (1 if R > C_ else 0)
+        assert p.peak == D ** (short + 1)
+        assert p.flops == _colsweep_flops(short, long_, D)
+        # the first line of sites absorbed runs along the shorter side:
+        # down column 0 untransposed, along row 0 transposed
+        first = [s.site for s in p.steps[:short]]
+        if p.transpose:
+            assert first == [(0, j) for j in range(short)]
+        else:
+            assert first == [(i, 0) for i in range(short)]
+        assert p.slots == long_ - 1
 
 
 def test_paper_row_and_quadrant_bond_sizes():
