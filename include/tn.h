@@ -155,6 +155,28 @@ tn_status tn_contract_grid(const tn_plan* plan, const double* const* sites,
                            void* workspace, size_t ws_bytes, void* hip_stream,
                            tn_result* out);
 
+/* Allocation-free form of tn_contract_grid, for callers that cannot allocate
+ * memory: code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, arithmetic and kernels as
+ * tn_contract_grid, except the workspace: the call contracts in the
+ * library's own static device array of TN_STATIC_SCRATCH_BYTES bytes, one
+ * copy per GPU (held from the first call on that device until the process
+ * ends), and builds the workspace head in a fixed host buffer of 1 MiB.  It
+ * calls no hipMalloc, hipHostMalloc, hipFree or other allocating routine,
+ * creates no stream or event, and runs every launch on hip_stream (the
+ * quadrant side-stream option and profiling do not apply).  The array keeps
+ * the last call's contents; nothing in it needs to start at zero, since each
+ * call uploads its own counters and slots.  Calls are serialised within the
+ * process (a lock held until the result is written); calls from different
+ * processes use different copies.  Blocks until *out is written.
+ * Errors: as tn_contract_grid, and TN_ENOMEM when the plan's workspace_bytes
+ * [precision] exceed TN_STATIC_SCRATCH_BYTES or its workspace head exceeds
+ * the host buffer (plans with more than about 8000 steps).                */
+#define TN_STATIC_SCRATCH_BYTES (160ull << 20)
+tn_status tn_contract_grid_static(const tn_plan* plan, const double* const* sites,
+                                  int32_t sites_on_device, int32_t precision, void* hip_stream,
+                                  tn_result* out);
+
 /* ------------------------------------------------------------ batching
  * Many independent lattices contracted by one persistent launch (the paper's
  * observable evaluations need one full contraction per local quantity, §5).

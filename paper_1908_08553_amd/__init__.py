@@ -13,6 +13,7 @@ from ._native import (  # noqa: F401
     TN_PREC_F64, TN_PREC_F32, TN_PREC_BF16X3,
     TnError, Plan, Result, lib, library_path,
     tn_plan_grid, tn_plan_stats, tn_plan_text, tn_contract_grid, tn_set_option,
+    tn_contract_grid_static, TN_STATIC_SCRATCH_BYTES,
     TN_OPT_KERNEL_IMPL, TN_OPT_BATCH_THREADS, TN_OPT_FUSE_STEPS, TN_OPT_CHUNK_SCHEDULE,
     TN_OPT_QUADRANT_STREAMS, TN_OPT_CHAIN_STEPS, TN_OPT_ENV_STREAMS, TN_OPT_ENV_ROWS,
     TN_OPT_ENV_SITES,

@@ -86,6 +86,10 @@ lib.tn_contract_batch.argtypes = [C.POINTER(_P), C.POINTER(C.POINTER(C.c_void_p)
 lib.tn_contract_grid.restype = C.c_int32
 lib.tn_contract_grid.argtypes = [_P, C.POINTER(C.c_void_p), C.c_int32, C.c_int32, _P,
                                  C.c_size_t, _P, C.POINTER(tn_result)]
+lib.tn_contract_grid_static.restype = C.c_int32
+lib.tn_contract_grid_static.argtypes = [_P, C.POINTER(C.c_void_p), C.c_int32, C.c_int32, _P,
+                                        C.POINTER(tn_result)]
+TN_STATIC_SCRATCH_BYTES = 160 << 20
 
 
 class tn_double_layer_site(C.Structure):
@@ -201,6 +205,20 @@ def tn_contract_grid(plan: Plan, site_ptrs, sites_on_device: bool,
     status = lib.tn_contract_grid(plan.handle, arr, 1 if sites_on_device else 0, precision,
                                   C.c_void_p(workspace_ptr), ws_bytes, C.c_void_p(stream_ptr),
                                   C.byref(out))
+    if status == TN_ENONFINITE:
+        return Result.from_c(out)
+    _check(status)
+    return Result.from_c(out)
+
+
+def tn_contract_grid_static(plan: Plan, site_ptrs, sites_on_device: bool, precision: int,
+                            stream_ptr: int) -> Result:
+    """tn_contract_grid in the library's static device workspace (no
+    allocation by the library or here)."""
+    arr = site_ptrs if isinstance(site_ptrs, C.Array) else (C.c_void_p * len(site_ptrs))(*site_ptrs)
+    out = tn_result()
+    status = lib.tn_contract_grid_static(plan.handle, arr, 1 if sites_on_device else 0,
+                                         precision, C.c_void_p(stream_ptr), C.byref(out))
     if status == TN_ENONFINITE:
         return Result.from_c(out)
     _check(status)

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -132,6 +133,51 @@ tn_status tn_contract_grid(const tn_plan* plan, const double* const* sites,
     std::string err;
     const tn_status s = tn::contract(p, sites, sites_on_device != 0, precision, workspace,
                                      ws_bytes, static_cast<hipStream_t>(hip_stream), out, err);
+    if (s != TN_OK) return fail(s, err);
+    g_err.clear();
+    return TN_OK;
+  } catch (const std::exception& e) {
+    return fail(TN_EDEVICE, e.what());
+  } catch (...) {
+    return fail(TN_EDEVICE, "unknown error");
+  }
+}
+
+namespace {
+// Host image of the workspace head for tn_contract_grid_static: ordinary
+// (pageable) memory of fixed size, so the call allocates nothing; one call at
+// a time in the process uses it.
+constexpr size_t kStaticHeadBytes = static_cast<size_t>(1) << 20;
+std::mutex g_static_mu;
+alignas(256) char g_static_head[kStaticHeadBytes];
+}  // namespace
+
+tn_status tn_contract_grid_static(const tn_plan* plan, const double* const* sites,
+                                  int32_t sites_on_device, int32_t precision, void* hip_stream,
+                                  tn_result* out) {
+  try {
+    if (!plan || !sites || !out) return fail(TN_EINVAL, "null argument");
+    if (precision < TN_PREC_F64 || precision > TN_PREC_BF16X3)
+      return fail(TN_EINVAL, "unknown precision");
+    const tn::Plan& p = plan->p;
+    for (int32_t s = 0; s < p.rows * p.cols; ++s)
+      if (!sites[s]) return fail(TN_EINVAL, "null site pointer");
+    std::memset(out, 0, sizeof(*out));
+    const tn::Layout L = tn::make_layout(p, precision);
+    if (L.total > TN_STATIC_SCRATCH_BYTES)
+      return fail(TN_ENOMEM, "plan needs " + std::to_string(L.total) +
+                                 " bytes of workspace; the static workspace holds " +
+                                 std::to_string(static_cast<size_t>(TN_STATIC_SCRATCH_BYTES)));
+    std::string err;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    tn_status s = tn::static_scratch(&ws, &ws_bytes, err);
+    if (s != TN_OK) return fail(s, err);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    tn::HostKeep keep;
+    keep.adopt(g_static_head, kStaticHeadBytes);
+    s = tn::contract_with(p, sites, sites_on_device != 0, precision, ws, ws_bytes,
+                          static_cast<hipStream_t>(hip_stream), keep, false, out, err);
     if (s != TN_OK) return fail(s, err);
     g_err.clear();
     return TN_OK;

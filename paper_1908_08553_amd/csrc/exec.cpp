@@ -288,12 +288,16 @@ void set_chain_steps(int32_t on) { g_chain_steps = on ? 1 : 0; }
 void set_quadrant_streams(int32_t on) { g_quadrant_streams = on ? 1 : 0; }
 
 HostKeep::~HostKeep() {
-  if (p_) (void)hipHostFree(p_);
+  if (p_ && !fixed_) (void)hipHostFree(p_);
 }
 
 char* HostKeep::block(size_t bytes, hipError_t* e) {
   *e = hipSuccess;
   if (bytes <= cap_) return p_;
+  if (fixed_) {
+    *e = hipErrorOutOfMemory;
+    return nullptr;
+  }
   if (p_) (void)hipHostFree(p_);
   p_ = nullptr;
   cap_ = 0;
@@ -368,7 +372,8 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
   const size_t head = head_bytes(p, L);
   char* img = keep.block(head + sizeof(tn_result), &e);
   if (!img) {
-    err = std::string("hipHostMalloc: ") + hip_msg(e);
+    err = "host image of the workspace head (" + std::to_string(head + sizeof(tn_result)) +
+          " bytes): " + hip_msg(e);
     return TN_ENOMEM;
   }
   std::memset(img, 0, L.descs);
@@ -775,6 +780,11 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
   return TN_OK;
 }
 
+// Copies the result record back once the stream has drained and folds the
+// launch timings in.
+tn_status finish(const Plan& p, int32_t prec, void* ws, hipStream_t stream, HostKeep& keep,
+                 LaunchTimer& timer, LaunchTimer* side_timer, tn_result* out, std::string& err);
+
 tn_status contract(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                    void* ws, size_t ws_bytes, hipStream_t stream, tn_result* out,
                    std::string& err) {
@@ -804,6 +814,20 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
   const tn_status s = enqueue(p, sites, on_device, prec, ws, ws_bytes, stream, keep, timer, err,
                               use_side ? &side : nullptr, use_side ? &side_timer : nullptr);
   if (s != TN_OK) return s;
+  return finish(p, prec, ws, stream, keep, timer, &side_timer, out, err);
+}
+
+tn_status contract_with(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
+                        void* ws, size_t ws_bytes, hipStream_t stream, HostKeep& keep,
+                        bool timed, tn_result* out, std::string& err) {
+  LaunchTimer timer(stream, timed);
+  const tn_status s = enqueue(p, sites, on_device, prec, ws, ws_bytes, stream, keep, timer, err);
+  if (s != TN_OK) return s;
+  return finish(p, prec, ws, stream, keep, timer, nullptr, out, err);
+}
+
+tn_status finish(const Plan& p, int32_t prec, void* ws, hipStream_t stream, HostKeep& keep,
+                 LaunchTimer& timer, LaunchTimer* side_timer, tn_result* out, std::string& err) {
   const Layout L = make_layout(p, prec);
   const DevState* state = reinterpret_cast<const DevState*>(static_cast<char*>(ws) + L.state);
   tn_result* staged = reinterpret_cast<tn_result*>(keep.data() + head_bytes(p, L));
@@ -816,7 +840,7 @@ tn_status contract(const Plan& p, const double* const* sites, bool on_device, in
   }
   *out = *staged;
   timer.flush();
-  side_timer.flush();
+  if (side_timer) side_timer->flush();
   if (out->status != TN_OK) {
     err = "non-finite value in the inputs or an intermediate";
     return out->status;

@@ -80,12 +80,17 @@ class HostKeep {
   HostKeep(const HostKeep&) = delete;
   HostKeep& operator=(const HostKeep&) = delete;
   // At least `bytes` of pinned memory (contents unspecified), or nullptr with
-  // *e set when the allocation fails.
+  // *e set when the allocation fails.  After adopt(), never allocates: the
+  // adopted buffer or nullptr (*e = hipErrorOutOfMemory) when it is too small.
   char* block(size_t bytes, hipError_t* e);
   char* data() const { return p_; }
+  // Use `cap` bytes of caller-owned host memory (pageable; not freed here)
+  // instead of pinned blocks.
+  void adopt(char* p, size_t cap) { p_ = p; cap_ = cap; fixed_ = true; }
  private:
   char* p_ = nullptr;
   size_t cap_ = 0;
+  bool fixed_ = false;
 };
 
 // Bytes of the uploaded head image and offset of the result record in it.
@@ -139,5 +144,18 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
 tn_status contract(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
                    void* ws, size_t ws_bytes, hipStream_t stream, tn_result* out,
                    std::string& err);
+
+// As contract(), with the head image and result record in `keep` and on
+// `stream` alone (no side stream); with timed = false no profiling events
+// are created.  Creates no stream, event, pinned block or device memory when
+// `keep` was adopted and timed is false.
+tn_status contract_with(const Plan& p, const double* const* sites, bool on_device, int32_t prec,
+                        void* ws, size_t ws_bytes, hipStream_t stream, HostKeep& keep,
+                        bool timed, tn_result* out, std::string& err);
+
+// The allocation-free workspace (defined beside its device array): the
+// current device's copy of the library's static scratch array and its size.
+// Looked up once per device; TN_EDEVICE when the lookup fails.
+tn_status static_scratch(void** ptr, size_t* bytes, std::string& err);
 
 }  // namespace tn
