@@ -2,16 +2,20 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-legs]
                     [--no-batch] [--no-serve] [--leg NAME ...] [--calibrate]
+    python bench.py --summarize-stats DIR OUT.txt   (rocprofv3 --stats CSV -> text)
+    python bench.py --summarize-traffic FETCH_DIR WRITE_DIR OUT.json
+                                                    (rocprofv3 --pmc CSVs -> traffic)
 
 One step = one full contraction through the C ABI -- site staging, every
 pairwise absorption with its per-column exact rescale, the quadrant ring
-products with the float64 closing dot, and the result copy -- of a 12x12,
-D=4 network with i.i.d. uniform[0,1) entries (seed 0) already resident in
-HBM, in the order the paper's heuristic picks (smallest bottleneck: the
-quadrant split for even L), FP32 arithmetic.  `value` is the plan's
-algorithmic flops per second.  Prints ONE JSON line; the other orders and
-precisions, the 10x10 FP64 configuration, the 512-lattice batch and the
-served Poisson stream ride along under "legs".
+products with the closing dot, and the result copy -- of a 12x12, D=4
+network with i.i.d. uniform[0,1) entries (seed 0) already resident in HBM,
+in the order the paper's heuristic picks (smallest bottleneck: the quadrant
+split for even L), in FP64 as the paper computes (DGEMM, §6).  `value` is
+the plan's algorithmic flops per second.  Prints ONE JSON line; FP32 and
+split BF16x3 on the same network (each with its |d log Z| against the FP64
+oracle), the column sweep, the 10x10 configuration, the 512-lattice batch
+and the served Poisson stream ride along under "legs".
 """
 from __future__ import annotations
 
@@ -277,12 +281,14 @@ def peps_env_leg(tn, torch, rows=10, cols=10, chi=2, seed=3, reps=5):
             "all_finite": all(r.status == 0 for r in out["results"])}
 
 
-def served_leg(tn, torch, n=240, seed=5):
+def served_leg(tn, torch, n=2000, seed=5):
     """Poisson stream: L ~ U{4..13} square Ising lattices, D ~ U{2,4} (D=4 is
     the two-replica network), tag ~ U{FP64, BF16x3}, beta*J ~ U[0.1, 0.8],
     heuristic order.  First the plain FP64 GPU path runs every request back
-    to back (saturation rate mu); then the server takes the stream at arrival
-    rates 0.5 mu and 0.9 mu.  Accuracy: |d log Z| against the FP64 path."""
+    to back (rate mu).  Then the server takes every request at once
+    (saturation), first all tagged FP64 (results bitwise those of the serial
+    path), then as tagged; then the Poisson stream at arrival rates 0.5 mu
+    and 0.9 mu.  Accuracy: |d log Z| against the FP64 serial path."""
     import numpy as np
     import lattice_inputs as li
     rng = np.random.default_rng(seed)
@@ -308,6 +314,33 @@ def served_leg(tn, torch, n=240, seed=5):
            "mean_flops": sum(p.info()["flops"] for p in plans) / n}
     # one slot per hardware queue left beside the caller's stream
     srv = tn.Server(24 << 30, max_slots=3, queue_depth=n + 8)
+
+    def closed_loop(tags):
+        """Every request submitted at t = 0 (saturation): contractions/s,
+        latency, and |d log Z| per precision against the FP64 serial path."""
+        tickets = []
+        start = time.perf_counter()
+        for (L, D, _, sites), tag in zip(reqs, tags):
+            tickets.append(srv.submit(L, L, sites, D=D, precision=tag))
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - start
+        lat = [(tm[2] - tm[0]) * 1e-6 for _, tm in res]
+        err = {}
+        same = True
+        for k, ((r, _), tag) in enumerate(zip(res, tags)):
+            err[tag] = max(err.get(tag, 0.0), abs(r.log_abs - ref[k].log_abs))
+            if tag == "f64":
+                same = same and (r.mantissa, r.exp2_sum) == (ref[k].mantissa, ref[k].exp2_sum)
+        return {"contractions_per_s": n / wall, "wall_s": wall, "p50_ms": pct(lat, 0.5),
+                "p99_ms": pct(lat, 0.99), "max_abs_dlogz_vs_fp64_serial": err,
+                "fp64_results_bitwise_equal_to_serial": same,
+                "speedup_vs_fp64_serial": (n / wall) / mu,
+                "peak_active": srv.stats()["peak_active"]}
+
+    # the same requests, all FP64: equal (bitwise) accuracy to the serial path
+    out["saturation_all_f64"] = closed_loop(["f64"] * n)
+    # the mix as tagged (half FP64, half split BF16x3)
+    out["saturation_mixed"] = closed_loop([r[2] for r in reqs])
     for frac in (0.5, 0.9):
         lam = frac * mu
         arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n))
@@ -331,11 +364,11 @@ def served_leg(tn, torch, n=240, seed=5):
         err = {"f64": 0.0, "bf16x3": 0.0}
         for k in range(n):
             d = abs(done[k][0].log_abs - ref[k].log_abs)
-            err[reqs[k][2]] = max(err[reqs[k][2]], d / max(1.0, abs(ref[k].log_abs)))
+            err[reqs[k][2]] = max(err[reqs[k][2]], d)
         out[f"rate_{frac}"] = {"arrival_per_s": lam, "p50_ms": pct(lat, 0.5),
                                "p99_ms": pct(lat, 0.99), "max_ms": max(lat),
                                "contractions_per_s": n / span,
-                               "max_rel_dlogz_vs_fp64": err,
+                               "max_abs_dlogz_vs_fp64_serial": err,
                                "peak_active": srv.stats()["peak_active"]}
     srv.close()
     return out
@@ -343,9 +376,13 @@ def served_leg(tn, torch, n=240, seed=5):
 
 def cpu_baseline():
     """The FP64 oracle, unchanged, contracting the whole headline network
-    (12x12, D=4, uniform seed 0, the heuristic's quadrant plan)."""
+    (12x12, D=4, uniform seed 0, the heuristic's quadrant plan); its log|Z|
+    is also the accuracy reference of every leg on that network.  The
+    two-replica Ising leg's reference is the oracle's row transfer matrix
+    (untimed, milliseconds)."""
     import lattice_inputs as li
     from oracle import contract as OC
+    from oracle import network as ON
     from oracle import plan as OP
     try:
         from threadpoolctl import threadpool_info
@@ -360,7 +397,22 @@ def cpu_baseline():
     return {"value": plan.flops / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"one complete 12x12 D=4 contraction (quadrant plan, {plan.flops:.3e} "
                       f"flops), FP64 numpy/OpenBLAS, {dt:.1f} s",
-            "log_abs": r.log_abs}
+            "log_abs": r.log_abs, "sign": r.sign,
+            "ising12_d4_log_abs_transfer_matrix": 2 * ON.transfer_log_z(12, 12, 0.44)}
+
+
+LEGS = [("quad12_f32", 12, 12, 4, "uniform", 1, "f32"),
+        ("quad12_bf16x3", 12, 12, 4, "uniform", 1, "bf16x3"),
+        ("sweep12_f64", 12, 12, 4, "uniform", 0, "f64"),
+        ("sweep12_f32", 12, 12, 4, "uniform", 0, "f32"),
+        ("sweep12_bf16x3", 12, 12, 4, "uniform", 0, "bf16x3"),
+        ("ising12_d4_quad_f64", 12, 12, 4, "ising", 1, "f64"),
+        ("ising12_d4_quad_f32", 12, 12, 4, "ising", 1, "f32"),
+        ("ising12_d4_quad_bf16x3", 12, 12, 4, "ising", 1, "bf16x3"),
+        ("sweep10_f64_normal", 10, 10, 4, "normal", 0, "f64"),
+        ("quad10_f64_normal", 10, 10, 4, "normal", 1, "f64"),
+        ("quad10_f32", 10, 10, 4, "uniform", 1, "f32"),
+        ("quad10_bf16x3", 10, 10, 4, "uniform", 1, "bf16x3")]
 
 
 def main():
@@ -376,7 +428,23 @@ def main():
                     help="run only the named leg(s) besides the headline (repeatable)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also time a plain 256 MiB device copy")
+    ap.add_argument("--summarize-stats", nargs=2, metavar=("DIR", "OUT"), default=None,
+                    help="reduce a rocprofv3 --stats CSV directory to a text summary")
+    ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
+                    default=None, help="reduce two rocprofv3 --pmc runs (FETCH_SIZE, "
+                    "WRITE_SIZE) with --calibrate to per-launch HBM bytes")
+    ap.add_argument("--command", default="", help="command line recorded in a summary")
+    ap.add_argument("--workload", default="quadrant",
+                    help="workload key of a traffic record (quadrant / sweep)")
     args = ap.parse_args()
+    if args.summarize_stats or args.summarize_traffic:
+        from paper_1908_08553_amd import profsum
+        if args.summarize_stats:
+            profsum.write_stats(args.summarize_stats[0], args.summarize_stats[1], args.command)
+        if args.summarize_traffic:
+            profsum.write_traffic(*args.summarize_traffic, command=args.command, root=ROOT,
+                                  workload=args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU quadrant partition is a design, not part of this build)",
@@ -387,23 +455,16 @@ def main():
     torch.cuda.set_device(0)
 
     calib = copy_calibration(torch) if args.calibrate else None
-    head = run_leg(tn, torch, 12, 12, 4, "uniform", 0, tn.TN_ORDER_HEURISTIC, "f32",
+    head = run_leg(tn, torch, 12, 12, 4, "uniform", 0, tn.TN_ORDER_HEURISTIC, "f64",
                    args.steps, args.warmup, profile=True)
     log(f"headline: {head['ms']:.3f} ms/contraction, {head['gflops']:.1f} GFLOP/s")
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline()
+        log(f"cpu baseline: {json.dumps(cpu)}")
     legs = {}
     if not args.no_legs:
-        spec = [("sweep12_f32", 12, 12, 4, "uniform", 0, "f32"),
-                ("sweep12_bf16x3", 12, 12, 4, "uniform", 0, "bf16x3"),
-                ("sweep12_f64", 12, 12, 4, "uniform", 0, "f64"),
-                ("quad12_bf16x3", 12, 12, 4, "uniform", 1, "bf16x3"),
-                ("quad12_f64", 12, 12, 4, "uniform", 1, "f64"),
-                ("ising12_d4_quad_f32", 12, 12, 4, "ising", 1, "f32"),
-                ("sweep10_f64_normal", 10, 10, 4, "normal", 0, "f64"),
-                ("quad10_f64_normal", 10, 10, 4, "normal", 1, "f64"),
-                ("quad10_f32", 10, 10, 4, "uniform", 1, "f32"),
-                ("quad10_bf16x3", 10, 10, 4, "uniform", 1, "bf16x3")]
-        if args.leg:
-            spec = [x for x in spec if x[0] in args.leg]
+        spec = [x for x in LEGS if not args.leg or x[0] in args.leg]
         for name, r, c, D, kind, order, prec in spec:
             leg = run_leg(tn, torch, r, c, D, kind, 0, order, prec, max(3, args.steps // 4),
                           1, profile=True)
@@ -413,14 +474,20 @@ def main():
             legs[name] = leg
             log(f"{name}: {leg['ms']:.3f} ms, {leg['gflops']:.1f} GFLOP/s, "
                 f"log|Z|={leg['log_abs']:.10f}")
-        ref = legs["quad12_f64"]["log_abs"] if "quad12_f64" in legs else None
-        for name, leg in list(legs.items()) + [("headline", head)]:
-            if ref is not None and leg["rows"] == 12 and leg["inputs"] == "uniform":
-                leg["dlogz_vs_gpu_f64"] = abs(leg["log_abs"] - ref)
+    # accuracy: |d log Z| (the relative error in Z) of every 12x12 leg against
+    # the FP64 oracle (or, without the CPU leg, against the GPU FP64 headline)
+    ref_u = cpu["log_abs"] if cpu else head["log_abs"]
+    ref_i = (cpu["ising12_d4_log_abs_transfer_matrix"] if cpu
+             else legs.get("ising12_d4_quad_f64", {}).get("log_abs"))
+    ref_name = "oracle_f64" if cpu else "gpu_f64"
+    for name, leg in list(legs.items()) + [("headline", head)]:
+        ref = {"uniform": ref_u, "ising": ref_i}.get(leg["inputs"]) if leg["rows"] == 12 else None
+        if ref is not None:
+            leg[f"abs_dlogz_vs_{ref_name}"] = abs(leg["log_abs"] - ref)
+    if not args.no_legs:
         if not args.no_batch:
             legs["batch512_f32"] = batch_leg(tn, torch)
             log(f"batch: {legs['batch512_f32']['contractions_per_s']:.0f} contractions/s")
-        if not args.no_batch:
             legs["peps6_observables_f64"] = peps_leg(tn, torch)
             log(f"peps observables: {json.dumps(legs['peps6_observables_f64'])}")
             legs["peps10_observables_env_f64"] = peps_env_leg(tn, torch)
@@ -441,24 +508,27 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic: 12x12 lattice, D=4, i.i.d. uniform[0,1) site tensors, seed 0",
         "config": {"workload": "12x12 square-lattice network, bond dimension 4, minimal-bottleneck "
-                               "(quadrant) order, FP32 products with exact FP64-exponent rescaling "
-                               "and an FP64 closing dot",
+                               "(quadrant) order, FP64 throughout with exact power-of-two "
+                               "rescaling",
                    "rows": 12, "cols": 12, "D": 4, "order": "HEURISTIC -> QUADRANT 6,6",
-                   "precision": "f32", "parallelism": "single GPU"},
+                   "precision": "f64", "parallelism": "single GPU"},
         "contractions_per_s": head["contractions_per_s"],
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "log_abs": head["log_abs"],
-        "roofline": roofline(head_kernels, "f32", "quadrant"),
+        "roofline": roofline(head_kernels, "f64", "quadrant"),
         "kernels": head_kernels,
         "legs": legs,
     }
+    for k, v in head.items():
+        if k.startswith("abs_dlogz_vs_"):
+            line[k] = v
     if calib:
         line["copy_calibration"] = calib
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline()
+    if cpu:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

@@ -75,6 +75,58 @@ def test_alone_equals_in_the_mix_bitwise(tn):
     srv.close()
 
 
+def test_nonfinite_request_is_isolated_in_the_mix(tn):
+    # A request whose sites hold a NaN (or an Inf) runs beside others: it
+    # returns TN_ENONFINITE, and every other request's result is bitwise its
+    # result alone.  The 13x13 FP64 request keeps the device busy while the
+    # bad ones are admitted beside it.
+    def bad_sites(L, D, K, value, where):
+        sites, _ = ising_request(L, D, K)
+        sites = [np.array(t, copy=True) for t in sites]
+        sites[where].flat[0] = value
+        return sites
+
+    good = [(13, 4, 0.44, "f64"), (6, 4, 0.5, "f64"), (9, 2, 0.3, "bf16x3"), (8, 4, 0.6, "f64"),
+            (5, 2, 0.7, "bf16x3"), (11, 4, 0.25, "bf16x3")]
+    bad = [(7, 4, 0.4, "f64", np.nan, 24), (10, 4, 0.4, "bf16x3", np.inf, 55),
+           (6, 2, 0.2, "f64", np.nan, 35)]
+    srv = tn.Server(16 * GiB, max_slots=3)
+    alone = []
+    for L, D, K, prec in good:
+        sites, want = ising_request(L, D, K)
+        res, _ = srv.wait(srv.submit(L, L, sites, D=D, precision=prec))
+        assert res.status == 0
+        alone.append((res.sign, res.mantissa, res.exp2_sum))
+    print("[gpu] server: good requests alone done; mixing in non-finite ones", flush=True)
+    order = [("g", 0), ("b", 0), ("g", 1), ("g", 2), ("b", 1), ("g", 3), ("g", 4), ("b", 2),
+             ("g", 5)]
+    tickets = []
+    for kind, i in order:
+        if kind == "g":
+            L, D, K, prec = good[i]
+            sites, _ = ising_request(L, D, K)
+        else:
+            L, D, K, prec, value, where = bad[i]
+            sites = bad_sites(L, D, K, value, where)
+        tickets.append((kind, i, srv.submit(L, L, sites, D=D, precision=prec)))
+    mixed = {}
+    for kind, i, t in tickets:
+        while True:
+            st, res, _ = srv.poll(t)
+            if st != tn.TN_PENDING:
+                break
+            time.sleep(1e-4)
+        if kind == "b":
+            assert st == tn.TN_ENONFINITE and res.status == tn.TN_ENONFINITE, (bad[i], st)
+        else:
+            assert st == tn.TN_OK and res.status == 0
+            mixed[i] = (res.sign, res.mantissa, res.exp2_sum)
+    assert [mixed[i] for i in range(len(good))] == alone
+    st = srv.stats()
+    assert st["peak_active"] >= 2 and st["active"] == 0 and st["queued"] == 0
+    srv.close()
+
+
 def test_small_requests_overtake_a_running_large_one(tn):
     # three slots: with 4 hardware queues per process (GPU_MAX_HW_QUEUES) and
     # the caller's own stream, more slot streams would share a queue with the
