@@ -60,6 +60,15 @@ typedef int32_t tn_status;
 #define TN_ORDER_QUADRANT   1
 #define TN_ORDER_HEURISTIC  2
 #define TN_ORDER_SWEEP_AUTO 3
+/*   ROWS     : the paper's row scheme (§4, Fig. 2a): every row is contracted
+ *              left to right into one tensor with all its vertical legs open
+ *              (chi^(2L) entries in the bulk), and the resulting chain of row
+ *              tensors is contracted from the top row down by matrix-vector
+ *              products, in float64 (the chain is the final reduction).
+ *   ROWS_T   : the same over columns (planned order ROWS, transpose = 1).
+ *   HEURISTIC also enumerates ROWS and ROWS_T, after the quadrant splits.   */
+#define TN_ORDER_ROWS       4
+#define TN_ORDER_ROWS_T     5
 
 /* Arithmetic of the contraction.
  *   F64    : every step in float64.
@@ -99,7 +108,7 @@ typedef struct {
   int32_t n_steps;         /* INIT + ABSORB steps over all units                 */
   int32_t n_units;         /* 1 (sweep) or 4 (quadrant)                          */
   int32_t n_slots;         /* rescale points                                     */
-  int32_t reserved;
+  int32_t n_links;         /* ROWS: links of the row chain (0 otherwise)         */
   int64_t peak_entries;    /* bottleneck: largest intermediate, in entries       */
   int64_t flops;           /* algorithmic: sum of 2 * d(out) * d(shared)         */
   int64_t moved_entries;   /* algorithmic boundary traffic: sum of d(in)+d(out)  */
@@ -108,6 +117,9 @@ typedef struct {
   int32_t ring_slices[3];     /* per precision: split-K slices the workspace holds for the
                                  stored ring product (1 = unsplit, 0 = no ring)          */
   int32_t reserved2;
+  int64_t buffer_entries;  /* intermediate storage kept at once: two buffers of   */
+                           /* each unit's largest intermediate, plus the stored   */
+                           /* ring product or two row-chain vectors (entries)     */
 } tn_plan_info;
 
 typedef struct tn_plan tn_plan;
@@ -125,6 +137,15 @@ const char* tn_last_error(void);
  * fewer than 2 rows or columns, split out of range), TN_EOVERFLOW.         */
 tn_status tn_plan_grid(const tn_grid* grid, int32_t order, int32_t quad_h,
                        int32_t quad_w, tn_plan** out);
+
+/* As tn_plan_grid, with a memory-feasibility check (§4: the order decides
+ * the intermediate sizes and with them whether the contraction fits; §6:
+ * the row scheme runs out of memory first).  max_buffer_entries bounds the
+ * plan's buffer_entries (<= 0: no bound).  An explicit order whose plan
+ * exceeds it returns TN_ENOMEM; HEURISTIC and SWEEP_AUTO drop the candidates
+ * that exceed it and return TN_ENOMEM only when none is left.             */
+tn_status tn_plan_grid_budget(const tn_grid* grid, int32_t order, int32_t quad_h,
+                              int32_t quad_w, int64_t max_buffer_entries, tn_plan** out);
 
 /* Sizes and costs of a plan (§4: element counts of every pairwise step and
  * the bottleneck).                                                          */

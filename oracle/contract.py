@@ -94,6 +94,23 @@ def contract(sites: Sequence[np.ndarray], plan: P.Plan) -> Result:
     if plan.order == P.COLSWEEP:
         B, E = run_unit(sites, plan, 0)
         return _result(float(B.reshape(-1)[0]), E)
+    if plan.order == P.ROWS:
+        # §4, row scheme: each row to one tensor, then the chain of row
+        # tensors contracted from the first row on, one matrix-vector product
+        # per row, rescaled exactly after each link but the last
+        T = [run_unit(sites, plan, u) for u in range(len(plan.units))]
+        v, E = T[0]
+        for lk in plan.chain:
+            R, e = T[lk.unit]
+            E += e
+            if lk.side == 0:
+                v = v.reshape(lk.K) @ R.reshape(lk.K, lk.N)
+            else:
+                v = R.reshape(lk.N, lk.K) @ v.reshape(lk.K)
+            if lk.rescale >= 0:
+                v, e = _rescale(v)
+                E += e
+        return _result(float(np.asarray(v).reshape(-1)[0]), E)
     g = plan.ring
     T = [run_unit(sites, plan, u) for u in range(4)]
     E = sum(t[1] for t in T)

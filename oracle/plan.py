@@ -44,9 +44,9 @@ import numpy as np
 LEFT, UP, RIGHT, DOWN = 0, 1, 2, 3
 INT64_MAX = (1 << 63) - 1
 
-COLSWEEP, QUADRANT, HEURISTIC, SWEEP_AUTO = 0, 1, 2, 3
+COLSWEEP, QUADRANT, HEURISTIC, SWEEP_AUTO, ROWS, ROWS_T = 0, 1, 2, 3, 4, 5
 ORDER_NAMES = {COLSWEEP: "COLSWEEP", QUADRANT: "QUADRANT", HEURISTIC: "HEURISTIC",
-               SWEEP_AUTO: "SWEEP_AUTO"}
+               SWEEP_AUTO: "SWEEP_AUTO", ROWS: "ROWS", ROWS_T: "ROWS_T"}
 
 # frame name -> (local L, U, R, Dn as canonical legs)
 FRAME_LEGS = {
@@ -151,6 +151,22 @@ class Ring:
 
 
 @dataclass
+class Link:
+    """One link of the row chain: v <- v . R (side 0, R = unit's tensor as
+    [K][N]) or v <- R . v (side 1, R as [N][K]); K = the row's up legs."""
+    unit: int
+    side: int
+    K: int
+    N: int
+    flops: int
+    rescale: int = -1
+
+
+class PlanTooLarge(Exception):
+    """No candidate order fits the intermediate-storage budget."""
+
+
+@dataclass
 class Plan:
     rows: int
     cols: int
@@ -167,6 +183,8 @@ class Plan:
     peak: int
     flops: int
     moved: int
+    chain: List[Link] = field(default_factory=list)
+    buffers: int = 0          # intermediate storage, entries (see _buffers)
 
 
 def _bond_dim(b, hdim, vdim) -> int:
@@ -236,8 +254,25 @@ def _sweep(rows, cols, hdim, vdim, unit_id, frame, nh, nw,
     return steps, boundary, slot
 
 
+def _buffers(units, steps, ring, chain) -> int:
+    """Entries of intermediate storage a plan keeps at once when every unit
+    holds two buffers (input and output of its current step) of its largest
+    intermediate until the end, plus the stored ring product, or two chain
+    vectors of the largest link output.  (§4: the bottleneck tensor sets the
+    memory; this counts everything live alongside it.)"""
+    total = 0
+    for u in range(len(units)):
+        big = max((s.out for s in steps if s.unit == u), default=1)
+        total = _add(total, _mul(big, 2))
+    if ring is not None:
+        total = _add(total, _mul(ring.m, ring.n))
+    if chain:
+        total = _add(total, _mul(max(lk.N for lk in chain), 2))
+    return total
+
+
 def _finish(p_rows, p_cols, hdim, vdim, requested, order, transpose, quad,
-            units, steps, ring, slots) -> Plan:
+            units, steps, ring, slots, chain=None) -> Plan:
     peak = 0
     flops = 0
     moved = 0
@@ -252,8 +287,13 @@ def _finish(p_rows, p_cols, hdim, vdim, requested, order, transpose, quad,
         for u in units:
             moved = _add(moved, u.result)
         moved = _add(moved, _mul(_mul(ring.m, ring.n), 2))
+    for lk in chain or []:
+        peak = max(peak, lk.N)
+        flops = _add(flops, lk.flops)
+        moved = _add(moved, _add(_mul(lk.K, lk.N), _add(lk.K, lk.N)))
     return Plan(p_rows, p_cols, hdim, vdim, requested, order, transpose, quad,
-                units, steps, ring, slots, peak, flops, moved)
+                units, steps, ring, slots, peak, flops, moved, list(chain or []),
+                _buffers(units, steps, ring, chain))
 
 
 def plan_colsweep(rows, cols, hdim, vdim, transpose=0, requested=COLSWEEP) -> Plan:
@@ -318,9 +358,114 @@ def plan_quadrant(rows, cols, hdim, vdim, h=0, w=0, requested=QUADRANT) -> Plan:
                    units, steps, ring, slot)
 
 
+def _row_unit(rows, cols, hdim, vdim, frame, i, nw, uid, up_first, slot, rescale_last):
+    """Contract local row i of ``frame`` into one tensor, left to right (§4,
+    the row scheme).  Each site is joined by its local left leg; its other
+    legs are new and go in place of the joined one, in the order up, right,
+    down (``up_first``) or down, right, up.  The row tensor then holds its up
+    legs left to right followed by its down legs right to left, or its down
+    legs left to right followed by its up legs right to left.  Rescale after
+    every step (except, with ``rescale_last`` false, the last)."""
+    fl = FRAME_LEGS[frame]
+    order = (1, 2, 3) if up_first else (3, 2, 1)
+    steps: List[Step] = []
+    boundary: List[Tuple[str, int, int]] = []
+    for j in range(nw):
+        r, c = frame_site(frame, rows, cols, i, j)
+        canon = canonical_legs(rows, cols, r, c)
+        axis_of = {leg: a for a, leg in enumerate(canon)}
+        present = {loc: fl[loc] for loc in range(4) if fl[loc] in axis_of}
+        new_locs = [loc for loc in order if loc in present]
+        new = [leg_bond(r, c, present[loc]) for loc in new_locs]
+        N = 1
+        for b in new:
+            N = _mul(N, _bond_dim(b, hdim, vdim))
+        if j == 0:
+            perm = tuple(axis_of[present[loc]] for loc in new_locs)
+            boundary = list(new)
+            steps.append(Step(uid, (r, c), "INIT", 1, 1, N, 1, perm, N, 0))
+        else:
+            joined = leg_bond(r, c, present[0])
+            k = boundary.index(joined)
+            pre = 1
+            for b in boundary[:k]:
+                pre = _mul(pre, _bond_dim(b, hdim, vdim))
+            post = 1
+            for b in boundary[k + 1:]:
+                post = _mul(post, _bond_dim(b, hdim, vdim))
+            K = _bond_dim(joined, hdim, vdim)
+            perm = tuple([axis_of[present[0]]] + [axis_of[present[loc]] for loc in new_locs])
+            out = _mul(_mul(pre, N), post)
+            steps.append(Step(uid, (r, c), "ABSORB", pre, K, N, post, perm, out,
+                              _mul(_mul(out, K), 2)))
+            boundary = boundary[:k] + new + boundary[k + 1:]
+        if j < nw - 1 or rescale_last:
+            steps[-1].rescale = slot
+            slot += 1
+    return steps, boundary, slot
+
+
+def plan_rows(rows, cols, hdim, vdim, transpose=0, requested=ROWS) -> Plan:
+    """The paper's row scheme (§4, Fig. 2a): every lattice row (every column
+    when transposed) is contracted into one tensor with all its vertical legs
+    open, leaving a chain of row tensors, which is then contracted as an MPS
+    from the first row down by matrix-vector products.  Even rows keep their
+    up legs first, odd rows their down legs first, so the legs a link sums
+    over sit in the same order on the chain vector and on the row tensor."""
+    frame = "T" if transpose else "ID"
+    nh, nw = (cols, rows) if transpose else (rows, cols)
+    fl = FRAME_LEGS[frame]
+    units: List[Unit] = []
+    steps: List[Step] = []
+    slot = 0
+    for i in range(nh):
+        st, legs, slot = _row_unit(rows, cols, hdim, vdim, frame, i, nw, i, i % 2 == 0,
+                                   slot, nh > 1)
+        res = 1
+        for b in legs:
+            res = _mul(res, _bond_dim(b, hdim, vdim))
+        units.append(Unit(frame, 1, nw, res, legs))
+        steps += st
+    chain: List[Link] = []
+    v = list(units[0].legs) if nh > 1 else []
+    for i in range(1, nh):
+        ups, downs = [], []
+        for j in range(nw):
+            r, c = frame_site(frame, rows, cols, i, j)
+            ups.append(leg_bond(r, c, fl[1]))
+            if i < nh - 1:
+                downs.append(leg_bond(r, c, fl[3]))
+        legs = units[i].legs
+        if i % 2 == 0:       # [up left->right][down right->left]
+            side, up_part, down_part = 0, legs[:nw], legs[nw:]
+            assert up_part == ups and down_part == downs[::-1]
+        else:                # [down left->right][up right->left]
+            side, up_part, down_part = 1, legs[len(downs):], legs[:len(downs)]
+            assert up_part == ups[::-1] and down_part == downs
+        assert up_part == v, "chain legs out of order"
+        K = 1
+        for b in up_part:
+            K = _mul(K, _bond_dim(b, hdim, vdim))
+        N = 1
+        for b in down_part:
+            N = _mul(N, _bond_dim(b, hdim, vdim))
+        lk = Link(i, side, K, N, _mul(_mul(K, N), 2))
+        if i < nh - 1:
+            lk.rescale = slot
+            slot += 1
+        chain.append(lk)
+        v = list(down_part)
+    return _finish(rows, cols, hdim, vdim, requested, ROWS, transpose, (0, 0),
+                   units, steps, None, slot, chain)
+
+
 def plan_grid(rows: int, cols: int, D: int = 2, hdim=None, vdim=None,
-              order: int = COLSWEEP, quad_h: int = 0, quad_w: int = 0) -> Plan:
-    """Build a plan; raises PlanOverflow if any integer exceeds int64."""
+              order: int = COLSWEEP, quad_h: int = 0, quad_w: int = 0,
+              budget: int = 0) -> Plan:
+    """Build a plan; raises PlanOverflow if any integer exceeds int64 and
+    PlanTooLarge if the plan (or, for HEURISTIC and SWEEP_AUTO, every
+    candidate) keeps more than ``budget`` entries of intermediate storage
+    (``budget`` <= 0: no limit).  ROWS_T is the row scheme over columns."""
     if rows < 1 or cols < 1:
         raise ValueError("rows and cols must be >= 1")
     if hdim is None:
@@ -329,43 +474,49 @@ def plan_grid(rows: int, cols: int, D: int = 2, hdim=None, vdim=None,
         vdim = np.full((max(rows - 1, 0), cols), D, dtype=np.int64)
     hdim = np.asarray(hdim, dtype=np.int64).reshape(rows, max(cols - 1, 0))
     vdim = np.asarray(vdim, dtype=np.int64).reshape(max(rows - 1, 0), cols)
+
+    def fits(p):
+        return budget <= 0 or p.buffers <= budget
+
+    def checked(p):
+        if not fits(p):
+            raise PlanTooLarge()
+        return p
+
     if order == COLSWEEP:
-        return plan_colsweep(rows, cols, hdim, vdim, 0)
+        return checked(plan_colsweep(rows, cols, hdim, vdim, 0))
     if order == QUADRANT:
-        return plan_quadrant(rows, cols, hdim, vdim, quad_h, quad_w)
-    if order == SWEEP_AUTO:
-        # the sweep orientation with the smaller bottleneck (then fewer flops,
-        # then untransposed): the boundary runs along the shorter side
-        cands = []
-        for t in (0, 1):
-            try:
-                cands.append(plan_colsweep(rows, cols, hdim, vdim, t, SWEEP_AUTO))
-            except PlanOverflow:
-                pass
-        if not cands:
-            raise PlanOverflow()
-        best = min(range(len(cands)), key=lambda k: (cands[k].peak, cands[k].flops, k))
-        return cands[best]
+        return checked(plan_quadrant(rows, cols, hdim, vdim, quad_h, quad_w))
+    if order in (ROWS, ROWS_T):
+        return checked(plan_rows(rows, cols, hdim, vdim, 1 if order == ROWS_T else 0, order))
+    if order not in (SWEEP_AUTO, HEURISTIC):
+        raise ValueError("unknown order")
+    # candidates in enumeration order: sweep, transposed sweep, then (HEURISTIC
+    # only) every quadrant split (h, w) lexicographically, the row scheme and
+    # the transposed row scheme
+    makers = [lambda t=t: plan_colsweep(rows, cols, hdim, vdim, t, order) for t in (0, 1)]
     if order == HEURISTIC:
-        cands = []
-        for t in (0, 1):
-            try:
-                cands.append(plan_colsweep(rows, cols, hdim, vdim, t, HEURISTIC))
-            except PlanOverflow:
-                pass
         if rows >= 2 and cols >= 2:
-            for h in range(1, rows):
-                for w in range(1, cols):
-                    try:
-                        cands.append(plan_quadrant(rows, cols, hdim, vdim, h, w,
-                                                   HEURISTIC))
-                    except PlanOverflow:
-                        pass
-        if not cands:
-            raise PlanOverflow()
-        best = min(range(len(cands)), key=lambda k: (cands[k].peak, cands[k].flops, k))
-        return cands[best]
-    raise ValueError("unknown order")
+            makers += [lambda h=h, w=w: plan_quadrant(rows, cols, hdim, vdim, h, w, HEURISTIC)
+                       for h in range(1, rows) for w in range(1, cols)]
+        makers += [lambda t=t: plan_rows(rows, cols, hdim, vdim, t, HEURISTIC) for t in (0, 1)]
+    cands = []
+    built = False
+    for mk in makers:
+        try:
+            p = mk()
+        except PlanOverflow:
+            continue
+        built = True
+        if fits(p):
+            cands.append(p)
+    if not cands:
+        if built:
+            raise PlanTooLarge()
+        raise PlanOverflow()
+    # smallest bottleneck, then fewest flops, then enumeration order
+    best = min(range(len(cands)), key=lambda k: (cands[k].peak, cands[k].flops, k))
+    return cands[best]
 
 
 def _ints(a) -> str:
@@ -393,6 +544,10 @@ def plan_text(p: Plan) -> str:
         g = p.ring
         lines.append(f"ring xa={g.xa} xb={g.xb} ya={g.ya} yb={g.yb} m={g.m} n={g.n}"
                      f" kx={g.kx} ky={g.ky} flops={g.flops}")
+    for k, lk in enumerate(p.chain):
+        resc = str(lk.rescale) if lk.rescale >= 0 else "-"
+        lines.append(f"link {k} unit={lk.unit} side={lk.side} K={lk.K} N={lk.N}"
+                     f" flops={lk.flops} rescale={resc}")
     lines.append(f"totals steps={len(p.steps)} slots={p.slots} peak={p.peak}"
                  f" flops={p.flops} moved={p.moved}")
     return "\n".join(lines) + "\n"

@@ -10,6 +10,7 @@ from ._native import (  # noqa: F401
     TN_OK, TN_PENDING, TN_EINVAL, TN_ENOMEM, TN_EBUSY, TN_EDEVICE, TN_ENOTFOUND,
     TN_ENONFINITE, TN_EOVERFLOW,
     TN_ORDER_COLSWEEP, TN_ORDER_QUADRANT, TN_ORDER_HEURISTIC, TN_ORDER_SWEEP_AUTO,
+    TN_ORDER_ROWS, TN_ORDER_ROWS_T,
     TN_PREC_F64, TN_PREC_F32, TN_PREC_BF16X3,
     TnError, Plan, Result, lib, library_path,
     tn_plan_grid, tn_plan_stats, tn_plan_text, tn_contract_grid, tn_set_option,

@@ -26,9 +26,11 @@ TN_OK, TN_PENDING = 0, 1
 TN_EINVAL, TN_ENOMEM, TN_EBUSY, TN_EDEVICE = -1, -2, -3, -4
 TN_ENOTFOUND, TN_ENONFINITE, TN_EOVERFLOW = -5, -6, -7
 TN_ORDER_COLSWEEP, TN_ORDER_QUADRANT, TN_ORDER_HEURISTIC, TN_ORDER_SWEEP_AUTO = 0, 1, 2, 3
+TN_ORDER_ROWS, TN_ORDER_ROWS_T = 4, 5
 TN_PREC_F64, TN_PREC_F32, TN_PREC_BF16X3 = 0, 1, 2
 
-_ORDERS = {"colsweep": 0, "quadrant": 1, "heuristic": 2, "sweep_auto": 3}
+_ORDERS = {"colsweep": 0, "quadrant": 1, "heuristic": 2, "sweep_auto": 3, "rows": 4,
+           "rows_t": 5}
 _PRECS = {"f64": 0, "f32": 1, "bf16x3": 2}
 
 
@@ -45,11 +47,11 @@ class tn_result(C.Structure):
 class tn_plan_info(C.Structure):
     _fields_ = [("order", C.c_int32), ("transpose", C.c_int32), ("quad_h", C.c_int32),
                 ("quad_w", C.c_int32), ("n_steps", C.c_int32), ("n_units", C.c_int32),
-                ("n_slots", C.c_int32), ("reserved", C.c_int32),
+                ("n_slots", C.c_int32), ("n_links", C.c_int32),
                 ("peak_entries", C.c_int64), ("flops", C.c_int64),
                 ("moved_entries", C.c_int64), ("workspace_bytes", C.c_int64 * 3),
                 ("hbm_bytes", C.c_int64 * 3), ("ring_slices", C.c_int32 * 3),
-                ("reserved2", C.c_int32)]
+                ("reserved2", C.c_int32), ("buffer_entries", C.c_int64)]
 
 
 _P = C.c_void_p
@@ -57,6 +59,9 @@ lib.tn_last_error.restype = C.c_char_p
 lib.tn_last_error.argtypes = []
 lib.tn_plan_grid.restype = C.c_int32
 lib.tn_plan_grid.argtypes = [C.POINTER(tn_grid), C.c_int32, C.c_int32, C.c_int32, C.POINTER(_P)]
+lib.tn_plan_grid_budget.restype = C.c_int32
+lib.tn_plan_grid_budget.argtypes = [C.POINTER(tn_grid), C.c_int32, C.c_int32, C.c_int32,
+                                    C.c_int64, C.POINTER(_P)]
 lib.tn_plan_stats.restype = C.c_int32
 lib.tn_plan_stats.argtypes = [_P, C.POINTER(tn_plan_info)]
 lib.tn_plan_text.restype = C.c_int32
@@ -163,7 +168,10 @@ class Plan:
 
 
 def tn_plan_grid(rows: int, cols: int, D: int = 2, hdim=None, vdim=None,
-                 order=TN_ORDER_COLSWEEP, quad_h: int = 0, quad_w: int = 0) -> Plan:
+                 order=TN_ORDER_COLSWEEP, quad_h: int = 0, quad_w: int = 0,
+                 budget: int = 0) -> Plan:
+    """tn_plan_grid, or tn_plan_grid_budget when ``budget`` (the most entries
+    of intermediate storage) is positive."""
     if isinstance(order, str):
         order = _ORDERS[order]
     h = _int_array(hdim)
@@ -172,7 +180,11 @@ def tn_plan_grid(rows: int, cols: int, D: int = 2, hdim=None, vdim=None,
                 C.cast(h, C.POINTER(C.c_int32)) if h is not None else None,
                 C.cast(v, C.POINTER(C.c_int32)) if v is not None else None)
     out = C.c_void_p()
-    _check(lib.tn_plan_grid(C.byref(g), order, quad_h, quad_w, C.byref(out)))
+    if budget > 0:
+        _check(lib.tn_plan_grid_budget(C.byref(g), order, quad_h, quad_w, int(budget),
+                                       C.byref(out)))
+    else:
+        _check(lib.tn_plan_grid(C.byref(g), order, quad_h, quad_w, C.byref(out)))
     return Plan(out.value)
 
 
@@ -181,7 +193,8 @@ def tn_plan_stats(plan: Plan) -> dict:
     _check(lib.tn_plan_stats(plan.handle, C.byref(info)))
     return {"order": info.order, "transpose": info.transpose,
             "quad": (info.quad_h, info.quad_w), "n_steps": info.n_steps,
-            "n_units": info.n_units, "n_slots": info.n_slots,
+            "n_units": info.n_units, "n_slots": info.n_slots, "n_links": info.n_links,
+            "buffer_entries": info.buffer_entries,
             "peak_entries": info.peak_entries, "flops": info.flops,
             "moved_entries": info.moved_entries,
             "workspace_bytes": list(info.workspace_bytes),

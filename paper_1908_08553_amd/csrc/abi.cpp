@@ -52,13 +52,19 @@ const char* tn_last_error(void) { return g_err.c_str(); }
 
 tn_status tn_plan_grid(const tn_grid* grid, int32_t order, int32_t quad_h, int32_t quad_w,
                        tn_plan** out) {
+  return tn_plan_grid_budget(grid, order, quad_h, quad_w, 0, out);
+}
+
+tn_status tn_plan_grid_budget(const tn_grid* grid, int32_t order, int32_t quad_h,
+                              int32_t quad_w, int64_t max_buffer_entries, tn_plan** out) {
   try {
     if (!grid || !out) return fail(TN_EINVAL, "null argument");
     *out = nullptr;
     auto* h = new (std::nothrow) tn_plan;
     if (!h) return fail(TN_ENOMEM, "out of host memory");
     std::string err;
-    const tn_status s = tn::build_plan(*grid, order, quad_h, quad_w, h->p, err);
+    const tn_status s = tn::build_plan(*grid, order, quad_h, quad_w, h->p, err,
+                                       max_buffer_entries);
     if (s != TN_OK) {
       delete h;
       return fail(s, err);
@@ -85,6 +91,8 @@ tn_status tn_plan_stats(const tn_plan* plan, tn_plan_info* out) {
     out->n_steps = static_cast<int32_t>(p.steps.size());
     out->n_units = static_cast<int32_t>(p.units.size());
     out->n_slots = p.slots;
+    out->n_links = static_cast<int32_t>(p.chain.size());
+    out->buffer_entries = p.buffers;
     out->peak_entries = p.peak;
     out->flops = p.flops;
     out->moved_entries = p.moved;

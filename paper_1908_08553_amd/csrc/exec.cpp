@@ -28,6 +28,8 @@ inline int32_t elem_bytes(int32_t t) { return t == EL_F64 ? 8 : 4; }
 int32_t step_out_type(const Plan& p, const Step& s, int32_t prec) {
   if (prec == TN_PREC_F64) return EL_F64;
   if (p.order == TN_ORDER_COLSWEEP && s.last_col) return EL_F64;
+  // a one-row row scheme is that row's sweep: its last step is the scalar
+  if (p.order == TN_ORDER_ROWS && p.units.size() == 1 && s.last_col) return EL_F64;
   return EL_F32;
 }
 
@@ -170,6 +172,8 @@ Layout make_layout(const Plan& p, int32_t prec) {
   L.s32 = off; off = align_up(off + 4 * ns);
   L.shi = off; off = align_up(off + 2 * ns);
   L.slo = off; off = align_up(off + 2 * ns);
+  L.buf.assign(p.units.size(), {0, 0});
+  L.buf_bytes.assign(p.units.size(), 0);
   for (size_t u = 0; u < p.units.size(); ++u) {
     const Unit& U = p.units[u];
     size_t mx = 0;
@@ -225,6 +229,19 @@ Layout make_layout(const Plan& p, int32_t prec) {
       }
     }
   }
+  if (!p.chain.empty()) {
+    int64_t vmax = 1, parts = 1;
+    for (const Link& lk : p.chain) {
+      vmax = std::max(vmax, lk.N);
+      parts = std::max(parts, link_chunks(lk.side, lk.K, lk.N) * lk.N);
+    }
+    L.vbuf_bytes = align_up(sizeof(double) * static_cast<size_t>(vmax));
+    L.vbuf[0] = off; off += L.vbuf_bytes;
+    L.vbuf[1] = off; off += L.vbuf_bytes;
+    L.n_link_partials = parts;
+    L.link_partials = off;
+    off = align_up(off + sizeof(double) * static_cast<size_t>(parts));
+  }
   L.total = off;
   return L;
 }
@@ -244,6 +261,14 @@ int64_t algorithmic_bytes(const Plan& p, int32_t prec) {
     const int64_t e = prec == TN_PREC_F64 ? 8 : 4;
     for (const Unit& U : p.units) bytes += U.result * e;
     bytes += 2 * p.ring.m * p.ring.n * e;
+  }
+  for (size_t i = 0; i < p.chain.size(); ++i) {
+    const Link& lk = p.chain[i];
+    const Unit& U = p.units[lk.unit];
+    const int64_t er = elem_bytes(L.out_type[U.first_step + U.n_steps - 1]);
+    const Unit& U0 = p.units[0];
+    const int64_t ev = i == 0 ? elem_bytes(L.out_type[U0.first_step + U0.n_steps - 1]) : 8;
+    bytes += lk.K * lk.N * er + lk.K * ev + lk.N * 8;
   }
   return bytes;
 }
@@ -380,9 +405,10 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
   DevState* hs = reinterpret_cast<DevState*>(img + L.state);
   hs->n_slots = p.slots;
   hs->n_steps = static_cast<int32_t>(nsteps);
-  char* init_dst[4];
+  std::vector<char*> init_dst(p.units.size());
   for (size_t u = 0; u < p.units.size(); ++u) init_dst[u] = base + L.buf[u][0];
-  fill_stage_descs(p, L, 0, dsite.data(), init_dst, reinterpret_cast<StageDesc*>(img + L.descs));
+  fill_stage_descs(p, L, 0, dsite.data(), init_dst.data(),
+                   reinterpret_cast<StageDesc*>(img + L.descs));
   TN_HIP(hipMemcpyAsync(base + L.state, img + L.state, head - L.state, hipMemcpyHostToDevice,
                         stream));
 
@@ -632,10 +658,15 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
     for (size_t u = 0; u < nu; ++u) main_units.push_back(u);
   }
   for (size_t t = 0; t < max_acts; ++t) {
-    tn_status st = launch_actions(main_units, t, stream, timer);
-    if (st != TN_OK) return st;
+    // at most four units' actions go out together (the launchers' group size)
+    for (size_t g0 = 0; g0 < main_units.size(); g0 += 4) {
+      const std::vector<size_t> grp(main_units.begin() + g0,
+                                    main_units.begin() + std::min(main_units.size(), g0 + 4));
+      tn_status st = launch_actions(grp, t, stream, timer);
+      if (st != TN_OK) return st;
+    }
     if (split_streams) {
-      st = launch_actions(side_units, t, side->stream, *side_timer);
+      tn_status st = launch_actions(side_units, t, side->stream, *side_timer);
       if (st != TN_OK) return st;
     }
   }
@@ -667,6 +698,43 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
       TN_HIP(launch_env_tap(state, slot_last, io->tap_rec, stream));
       timer.after("env_tap", 0.0, 0.0);
     }
+  } else if (!p.chain.empty()) {
+    // the row chain: v = first row's tensor, then one matrix-vector product
+    // per row in float64, each rescaled exactly but the last (the scalar)
+    auto unit_out = [&](int32_t u, int32_t* type) {
+      const Unit& U = p.units[u];
+      *type = L.out_type[U.first_step + U.n_steps - 1];
+      return static_cast<const void*>(base + L.buf[u][final_buf[u]]);
+    };
+    const double* vout = nullptr;
+    for (size_t i = 0; i < p.chain.size(); ++i) {
+      const Link& lk = p.chain[i];
+      LinkArgs a;
+      int32_t vt = EL_F64, rt = EL_F64;
+      a.v = i == 0 ? unit_out(0, &vt) : static_cast<const void*>(vout);
+      a.v_f64 = vt == EL_F64;
+      a.R = unit_out(lk.unit, &rt);
+      a.R_f64 = rt == EL_F64;
+      a.K = lk.K; a.N = lk.N; a.side = lk.side;
+      a.slot_v = lk.scale_v >= 0 ? slot_exp + lk.scale_v : nullptr;
+      const int32_t rs = p.units[lk.unit].final_slot;
+      a.slot_R = rs >= 0 ? slot_exp + rs : nullptr;
+      a.out = reinterpret_cast<double*>(base + L.vbuf[i & 1]);
+      a.max_slot = lk.rescale >= 0 ? slot_exp + lk.rescale : nullptr;
+      a.flags = &state->flags;
+      a.partials = reinterpret_cast<double*>(base + L.link_partials);
+      timer.before();
+      TN_HIP(launch_row_link(a, stream));
+      timer.after(a.v_f64 && a.R_f64 ? "row_link_f64" : "row_link_f32_to_f64",
+                  static_cast<double>(lk.K * lk.N) * (a.R_f64 ? 8.0 : 4.0) +
+                      static_cast<double>(lk.K) * (a.v_f64 ? 8.0 : 4.0) +
+                      8.0 * static_cast<double>(lk.N),
+                  static_cast<double>(lk.flops));
+      vout = a.out;
+    }
+    timer.before();
+    TN_HIP(launch_finalize(state, vout, copy, nullptr, 0, stream));
+    timer.after("finalize", 0.0, 0.0);
   } else if (!p.has_ring) {
     const double* scalar = reinterpret_cast<const double*>(base + L.buf[0][final_buf[0]]);
     timer.before();

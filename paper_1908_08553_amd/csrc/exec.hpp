@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <array>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -21,8 +22,12 @@ struct Layout {
   size_t descs = 0;
   size_t raw = 0;                    // host sites are copied here
   size_t s64 = 0, s32 = 0, shi = 0, slo = 0;
-  size_t buf[4][2] = {};             // unit boundary ping-pong buffers
-  size_t buf_bytes[4] = {};
+  std::vector<std::array<size_t, 2>> buf;   // unit boundary ping-pong buffers
+  std::vector<size_t> buf_bytes;
+  size_t vbuf[2] = {};               // row chain: float64 chain vectors
+  size_t vbuf_bytes = 0;
+  size_t link_partials = 0;          // row chain: per-link partial sums
+  int64_t n_link_partials = 0;
   size_t yt = 0, yt_bytes = 0;       // ring: the stored product X (split-K slices)
   int32_t yt_slices = 1;
   size_t partials = 0;

@@ -211,6 +211,26 @@ struct DoubleLayerSite {
 bool double_layer_ok(const DoubleLayerSite& s);
 hipError_t launch_double_layer(const DoubleLayerSite* sites, int32_t n, hipStream_t stream);
 
+// One link of the row scheme's chain (row_chain.hip): out = v R (side 0, R as
+// [K][N]) or R v (side 1, R as [N][K]), float64, v and R scaled by 2^-e of
+// their slots on load; the exponent of max |out| goes to max_slot (null on
+// the last link).  `partials` holds link_chunks(side, K, N) * N doubles.
+struct LinkArgs {
+  const void* v = nullptr;
+  const void* R = nullptr;
+  int32_t v_f64 = 1, R_f64 = 1;
+  int64_t K = 1, N = 1;
+  int32_t side = 0;
+  const int32_t* slot_v = nullptr;
+  const int32_t* slot_R = nullptr;
+  double* out = nullptr;
+  int32_t* max_slot = nullptr;
+  int32_t* flags = nullptr;
+  double* partials = nullptr;
+};
+int64_t link_chunks(int32_t side, int64_t K, int64_t N);
+hipError_t launch_row_link(const LinkArgs& a, hipStream_t stream);
+
 // Writes state->result from the final scalar (or the sum of `n_partials`
 // partials), the site exponents, the rescale slots and state->e_bias, plus
 // the exponent of `cap` (the boundary a cap dot closed against; nullable);

@@ -49,7 +49,8 @@ const int32_t kFrameLegs[5][4] = {
     {LEG_LEFT, LEG_DOWN, LEG_RIGHT, LEG_UP},   // MV  (mirror top-bottom)
 };
 const char* kFrameName[5] = {"ID", "T", "MH", "MHV", "MV"};
-const char* kOrderName[4] = {"COLSWEEP", "QUADRANT", "HEURISTIC", "SWEEP_AUTO"};
+const char* kOrderName[6] = {"COLSWEEP", "QUADRANT", "HEURISTIC", "SWEEP_AUTO", "ROWS",
+                             "ROWS_T"};
 
 struct Lattice {
   int32_t R, C;
@@ -196,6 +197,27 @@ void finish(Plan& p) {
     for (const Unit& U : p.units) p.moved = add(p.moved, U.result);
     p.moved = add(p.moved, mul(mn, 2));
   }
+  int32_t vslot = p.units.empty() ? -1 : p.units[0].final_slot;
+  int64_t big_link = 0;
+  for (Link& lk : p.chain) {
+    p.peak = std::max(p.peak, lk.N);
+    p.flops = add(p.flops, lk.flops);
+    p.moved = add(p.moved, add(mul(lk.K, lk.N), add(lk.K, lk.N)));
+    lk.scale_v = vslot;
+    vslot = lk.rescale;
+    big_link = std::max(big_link, lk.N);
+  }
+  // intermediate storage: two buffers of every unit's largest intermediate,
+  // the stored ring product, two chain vectors
+  p.buffers = 0;
+  for (const Unit& U : p.units) {
+    int64_t big = 1;
+    for (int32_t k = U.first_step; k < U.first_step + U.n_steps; ++k)
+      big = std::max(big, p.steps[k].out);
+    p.buffers = add(p.buffers, mul(big, 2));
+  }
+  if (p.has_ring) p.buffers = add(p.buffers, mul(p.ring.m, p.ring.n));
+  if (!p.chain.empty()) p.buffers = add(p.buffers, mul(big_link, 2));
 }
 
 void plan_colsweep(const Lattice& L, int32_t transpose, int32_t requested, Plan& p) {
@@ -254,10 +276,137 @@ void plan_quadrant(const Lattice& L, int32_t h, int32_t w, int32_t requested, Pl
   finish(p);
 }
 
+// Row i of `frame` contracted left to right into one tensor (paper §4, the
+// row scheme).  Each site joins by its local left leg; its other legs go in
+// place of the joined one, ordered up, right, down (up_first) or down,
+// right, up, so the row tensor ends as [up legs left->right][down legs
+// right->left] or [down legs left->right][up legs right->left].  Rescale
+// after every step (the last one only with rescale_last).
+std::vector<int32_t> row_unit(const Lattice& L, int32_t unit, int32_t frame, int32_t i,
+                              int32_t nw, bool up_first, bool rescale_last, int32_t& slot,
+                              std::vector<Step>& steps) {
+  const int32_t* fl = kFrameLegs[frame];
+  const int32_t order_a[3] = {1, 2, 3}, order_b[3] = {3, 2, 1};
+  const int32_t* order = up_first ? order_a : order_b;
+  std::vector<int32_t> bnd;
+  for (int32_t j = 0; j < nw; ++j) {
+    int32_t r, c;
+    L.site_of(frame, i, j, r, c);
+    Step s;
+    s.unit = unit; s.r = r; s.c = c; s.col = j; s.last_col = (j == nw - 1);
+    s.site_entries = 1;
+    for (int32_t leg = 0; leg < 4; ++leg)
+      if (L.has(r, c, leg)) s.site_entries = mul(s.site_entries, L.dim(L.bond(r, c, leg)));
+    std::vector<int32_t> new_legs;
+    for (int32_t k = 0; k < 3; ++k)
+      if (L.has(r, c, fl[order[k]])) new_legs.push_back(fl[order[k]]);
+    int64_t N = 1;
+    for (int32_t leg : new_legs) N = mul(N, L.dim(L.bond(r, c, leg)));
+    if (j == 0) {
+      s.kind = STEP_INIT;
+      for (int32_t leg : new_legs) {
+        s.perm[s.nperm++] = L.axis(r, c, leg);
+        bnd.push_back(L.bond(r, c, leg));
+      }
+      s.pre = s.K = s.post = 1;
+      s.N = s.out = N;
+      s.flops = 0;
+    } else {
+      const int32_t jl = fl[0];
+      const int32_t joined = L.bond(r, c, jl);
+      const size_t k = static_cast<size_t>(std::find(bnd.begin(), bnd.end(), joined) - bnd.begin());
+      if (k == bnd.size()) throw std::runtime_error("row leg missing");
+      int64_t pre = 1, post = 1;
+      for (size_t a = 0; a < k; ++a) pre = mul(pre, L.dim(bnd[a]));
+      for (size_t a = k + 1; a < bnd.size(); ++a) post = mul(post, L.dim(bnd[a]));
+      s.perm[s.nperm++] = L.axis(r, c, jl);
+      std::vector<int32_t> nb(bnd.begin(), bnd.begin() + k);
+      for (int32_t leg : new_legs) {
+        s.perm[s.nperm++] = L.axis(r, c, leg);
+        nb.push_back(L.bond(r, c, leg));
+      }
+      nb.insert(nb.end(), bnd.begin() + k + 1, bnd.end());
+      bnd.swap(nb);
+      s.kind = STEP_ABSORB;
+      s.pre = pre; s.K = L.dim(joined); s.N = N; s.post = post;
+      s.out = mul(mul(pre, N), post);
+      s.flops = mul(mul(s.out, s.K), 2);
+    }
+    steps.push_back(s);
+    if (j < nw - 1 || rescale_last) steps.back().rescale = slot++;
+  }
+  return bnd;
+}
+
+// The row scheme (paper §4, Fig. 2a): one unit per row (per column when
+// transposed), then the chain of row tensors closed from the first row on.
+// Even rows keep their up legs first and odd rows their down legs first, so
+// a link's summed legs have the same order on the chain vector and the row.
+void plan_rows(const Lattice& L, int32_t transpose, int32_t requested, Plan& p) {
+  p.requested = requested;
+  p.order = TN_ORDER_ROWS;
+  p.transpose = transpose;
+  p.qh = p.qw = 0;
+  p.has_ring = false;
+  p.units.clear();
+  p.steps.clear();
+  p.chain.clear();
+  const int32_t frame = transpose ? FRAME_T : FRAME_ID;
+  const int32_t nh = transpose ? L.C : L.R, nw = transpose ? L.R : L.C;
+  const int32_t* fl = kFrameLegs[frame];
+  int32_t slot = 0;
+  std::vector<std::vector<int32_t>> legs(nh);
+  for (int32_t i = 0; i < nh; ++i) {
+    Unit U;
+    U.frame = frame; U.rows = 1; U.cols = nw;
+    U.first_step = static_cast<int32_t>(p.steps.size());
+    legs[i] = row_unit(L, i, frame, i, nw, i % 2 == 0, nh > 1, slot, p.steps);
+    U.n_steps = static_cast<int32_t>(p.steps.size()) - U.first_step;
+    U.result = 1;
+    for (int32_t b : legs[i]) U.result = mul(U.result, L.dim(b));
+    p.units.push_back(U);
+  }
+  std::vector<int32_t> v = nh > 1 ? legs[0] : std::vector<int32_t>{};
+  for (int32_t i = 1; i < nh; ++i) {
+    std::vector<int32_t> ups, downs;
+    for (int32_t j = 0; j < nw; ++j) {
+      int32_t r, c;
+      L.site_of(frame, i, j, r, c);
+      ups.push_back(L.bond(r, c, fl[1]));
+      if (i < nh - 1) downs.push_back(L.bond(r, c, fl[3]));
+    }
+    const std::vector<int32_t>& lg = legs[i];
+    std::vector<int32_t> up_part, down_part;
+    Link lk;
+    lk.unit = i;
+    if (i % 2 == 0) {
+      lk.side = 0;
+      up_part.assign(lg.begin(), lg.begin() + nw);
+      down_part.assign(lg.begin() + nw, lg.end());
+      std::reverse(downs.begin(), downs.end());
+    } else {
+      lk.side = 1;
+      down_part.assign(lg.begin(), lg.begin() + downs.size());
+      up_part.assign(lg.begin() + downs.size(), lg.end());
+      std::reverse(ups.begin(), ups.end());
+    }
+    if (up_part != ups || down_part != downs || up_part != v)
+      throw std::runtime_error("row chain legs out of order");
+    for (int32_t b : up_part) lk.K = mul(lk.K, L.dim(b));
+    for (int32_t b : down_part) lk.N = mul(lk.N, L.dim(b));
+    lk.flops = mul(mul(lk.K, lk.N), 2);
+    if (i < nh - 1) lk.rescale = slot++;
+    p.chain.push_back(lk);
+    v = down_part;
+  }
+  p.slots = slot;
+  finish(p);
+}
+
 }  // namespace
 
 tn_status build_plan(const tn_grid& grid, int32_t order, int32_t quad_h, int32_t quad_w,
-                     Plan& out, std::string& err) {
+                     Plan& out, std::string& err, int64_t budget) {
   const int32_t R = grid.rows, C = grid.cols;
   if (R < 1 || C < 1) { err = "rows and cols must be >= 1"; return TN_EINVAL; }
   if (static_cast<int64_t>(R) * C > (1 << 20)) { err = "lattice too large"; return TN_EINVAL; }
@@ -273,52 +422,57 @@ tn_status build_plan(const tn_grid& grid, int32_t order, int32_t quad_h, int32_t
   for (int32_t d : p.hdim) if (d < 1) { err = "bond dimension < 1"; return TN_EINVAL; }
   for (int32_t d : p.vdim) if (d < 1) { err = "bond dimension < 1"; return TN_EINVAL; }
   Lattice L{R, C, &p.hdim, &p.vdim};
+  auto fits = [&](const Plan& q) { return budget <= 0 || q.buffers <= budget; };
+  bool too_large = false;
   try {
     if (order == TN_ORDER_COLSWEEP) {
       plan_colsweep(L, 0, TN_ORDER_COLSWEEP, p);
+      too_large = !fits(p);
     } else if (order == TN_ORDER_QUADRANT) {
       if (R < 2 || C < 2) { err = "QUADRANT needs >= 2 rows and >= 2 columns"; return TN_EINVAL; }
       const int32_t h = quad_h ? quad_h : (R + 1) / 2;
       const int32_t w = quad_w ? quad_w : (C + 1) / 2;
       if (h < 1 || h > R - 1 || w < 1 || w > C - 1) { err = "quadrant split out of range"; return TN_EINVAL; }
       plan_quadrant(L, h, w, TN_ORDER_QUADRANT, p);
-    } else if (order == TN_ORDER_SWEEP_AUTO) {
-      bool have = false;
-      Plan best;
-      for (int32_t t = 0; t < 2; ++t) {
-        Plan cand = p;
-        try {
-          plan_colsweep(L, t, TN_ORDER_SWEEP_AUTO, cand);
-          if (!have || cand.peak < best.peak || (cand.peak == best.peak && cand.flops < best.flops)) {
-            best = cand;
-            have = true;
-          }
-        } catch (Overflow&) {}
-      }
-      if (!have) throw Overflow{};
-      p = best;
-    } else if (order == TN_ORDER_HEURISTIC) {
-      bool have = false;
+      too_large = !fits(p);
+    } else if (order == TN_ORDER_ROWS || order == TN_ORDER_ROWS_T) {
+      plan_rows(L, order == TN_ORDER_ROWS_T ? 1 : 0, order, p);
+      too_large = !fits(p);
+    } else if (order == TN_ORDER_SWEEP_AUTO || order == TN_ORDER_HEURISTIC) {
+      // candidates in enumeration order: sweep, transposed sweep, then (for
+      // HEURISTIC) every quadrant split (h, w) lexicographically, the row
+      // scheme and the transposed row scheme; the smallest bottleneck, then
+      // the fewest flops, then the earliest candidate among those that fit
+      bool have = false, built = false;
       Plan best;
       auto consider = [&](Plan& cand) {
+        built = true;
+        if (!fits(cand)) return;
         if (!have || cand.peak < best.peak || (cand.peak == best.peak && cand.flops < best.flops)) {
-          best = cand;   // earlier candidates win exact ties
+          best = cand;
           have = true;
         }
       };
       for (int32_t t = 0; t < 2; ++t) {
         Plan cand = p;
-        try { plan_colsweep(L, t, TN_ORDER_HEURISTIC, cand); consider(cand); } catch (Overflow&) {}
+        try { plan_colsweep(L, t, order, cand); consider(cand); } catch (Overflow&) {}
       }
-      if (R >= 2 && C >= 2) {
-        for (int32_t h = 1; h < R; ++h)
-          for (int32_t w = 1; w < C; ++w) {
-            Plan cand = p;
-            try { plan_quadrant(L, h, w, TN_ORDER_HEURISTIC, cand); consider(cand); } catch (Overflow&) {}
-          }
+      if (order == TN_ORDER_HEURISTIC) {
+        if (R >= 2 && C >= 2) {
+          for (int32_t h = 1; h < R; ++h)
+            for (int32_t w = 1; w < C; ++w) {
+              Plan cand = p;
+              try { plan_quadrant(L, h, w, TN_ORDER_HEURISTIC, cand); consider(cand); } catch (Overflow&) {}
+            }
+        }
+        for (int32_t t = 0; t < 2; ++t) {
+          Plan cand = p;
+          try { plan_rows(L, t, TN_ORDER_HEURISTIC, cand); consider(cand); } catch (Overflow&) {}
+        }
       }
-      if (!have) throw Overflow{};
-      p = best;
+      if (!built) throw Overflow{};
+      if (have) p = best;
+      too_large = !have;
     } else {
       err = "unknown order";
       return TN_EINVAL;
@@ -326,6 +480,10 @@ tn_status build_plan(const tn_grid& grid, int32_t order, int32_t quad_h, int32_t
   } catch (Overflow&) {
     err = "plan integers overflow int64";
     return TN_EOVERFLOW;
+  }
+  if (too_large) {
+    err = "no plan keeps at most " + std::to_string(budget) + " entries of intermediate storage";
+    return TN_ENOMEM;
   }
   out = std::move(p);
   return TN_OK;
@@ -558,6 +716,13 @@ std::string plan_text(const Plan& p) {
     os << "ring xa=" << g.xa << " xb=" << g.xb << " ya=" << g.ya << " yb=" << g.yb
        << " m=" << g.m << " n=" << g.n << " kx=" << g.kx << " ky=" << g.ky
        << " flops=" << g.flops << "\n";
+  }
+  for (size_t k = 0; k < p.chain.size(); ++k) {
+    const Link& lk = p.chain[k];
+    os << "link " << k << " unit=" << lk.unit << " side=" << lk.side << " K=" << lk.K
+       << " N=" << lk.N << " flops=" << lk.flops << " rescale=";
+    if (lk.rescale >= 0) os << lk.rescale; else os << "-";
+    os << "\n";
   }
   os << "totals steps=" << p.steps.size() << " slots=" << p.slots << " peak=" << p.peak
      << " flops=" << p.flops << " moved=" << p.moved << "\n";

@@ -54,6 +54,18 @@ struct Ring {
   int64_t m = 1, n = 1, kx = 1, ky = 1, flops = 0;
 };
 
+// One link of the row scheme's chain (paper §4, Fig. 2a): the chain vector v
+// (the first row's tensor, then each link's output) meets the next row's
+// tensor R over the row's up legs: v <- v R with R as [K][N] (side 0) or
+// v <- R v with R as [N][K] (side 1).  K = up legs, N = down legs (1 for the
+// last row, whose link yields the scalar).
+struct Link {
+  int32_t unit = 0, side = 0;
+  int64_t K = 1, N = 1, flops = 0;
+  int32_t rescale = -1;     // exponent slot measured after the link (-1: last)
+  int32_t scale_v = -1;     // slot whose exponent scales v on load
+};
+
 struct Plan {
   int32_t rows = 0, cols = 0;
   std::vector<int32_t> hdim, vdim;
@@ -63,8 +75,13 @@ struct Plan {
   std::vector<Step> steps;
   bool has_ring = false;
   Ring ring;
+  std::vector<Link> chain;         // ROWS: links in order (empty otherwise)
   int32_t slots = 0;
   int64_t peak = 0, flops = 0, moved = 0;
+  // intermediate storage the order keeps at once, in entries: two buffers of
+  // each unit's largest intermediate, plus the stored ring product or two
+  // chain vectors of the largest link output
+  int64_t buffers = 0;
   int64_t total_site_entries = 0;
   // Cut plans: local columns [cut_c0, cut_c1) of a full-lattice column sweep,
   // left to right (cut_mirror 0) or right to left (1).  They start with a SEED
@@ -77,9 +94,11 @@ struct Plan {
   std::vector<int32_t> cut_legs;   // bond ids of the ending boundary, slowest first
 };
 
-// Builds a plan.  Returns TN_OK, TN_EINVAL or TN_EOVERFLOW (message in err).
+// Builds a plan.  Returns TN_OK, TN_EINVAL, TN_EOVERFLOW or, when the plan
+// (for HEURISTIC / SWEEP_AUTO: every candidate) keeps more than `budget`
+// entries of intermediate storage, TN_ENOMEM (budget <= 0: no limit).
 tn_status build_plan(const tn_grid& grid, int32_t order, int32_t quad_h,
-                     int32_t quad_w, Plan& out, std::string& err);
+                     int32_t quad_w, Plan& out, std::string& err, int64_t budget = 0);
 
 // Cut plans of the column sweep (see Plan::is_cut): same steps, site folds and
 // rescale points as the full sweep over sweep steps [k0, k1) (step k absorbs

@@ -31,7 +31,10 @@ void run(int r, int c, int D, const int32_t* h, const int32_t* v, int order, int
   if (s != TN_OK) {
     // QUADRANT needs two rows and two columns; splits must be inside the lattice
     const bool quad_ok = r >= 2 && c >= 2 && qh >= 0 && qh < r && qw >= 0 && qw < c;
-    check(order == TN_ORDER_QUADRANT && !quad_ok, "unexpected planning error", r, c, D, order);
+    // the row scheme's D^(2L) row tensors may not fit int64
+    const bool rows_big = (order == TN_ORDER_ROWS || order == TN_ORDER_ROWS_T) && s == TN_EOVERFLOW;
+    check((order == TN_ORDER_QUADRANT && !quad_ok) || rows_big, "unexpected planning error", r, c,
+          D, order);
     return;
   }
   ++plans;
@@ -43,7 +46,37 @@ void run(int r, int c, int D, const int32_t* h, const int32_t* v, int order, int
     check(st.out <= p.peak, "peak", r, c, D, order);
     f += st.flops;
   }
-  check(f + (p.has_ring ? p.ring.flops : 0) == p.flops, "flop total", r, c, D, order);
+  int64_t fl = 0;
+  for (const tn::Link& lk : p.chain) fl += lk.flops;
+  check(f + (p.has_ring ? p.ring.flops : 0) + fl == p.flops, "flop total", r, c, D, order);
+  // the row chain: each link sums the previous output (the first row's
+  // tensor first) against a row tensor of K x N entries; the last one ends
+  // in the scalar; every slot scales exactly the tensor measured into it
+  if (!p.chain.empty()) {
+    int64_t k = p.units[0].result;
+    int32_t vslot = p.units[0].final_slot;
+    for (size_t i = 0; i < p.chain.size(); ++i) {
+      const tn::Link& lk = p.chain[i];
+      const bool last = i + 1 == p.chain.size();
+      check(lk.K == k && p.units[lk.unit].result == lk.K * lk.N && lk.scale_v == vslot &&
+                (last ? (lk.N == 1 && lk.rescale < 0) : lk.rescale >= 0) &&
+                lk.unit == static_cast<int32_t>(i + 1),
+            "row chain", r, c, D, order);
+      k = lk.N;
+      vslot = lk.rescale;
+    }
+  }
+  // under a budget just below this plan's storage an explicit order is
+  // refused, and the heuristic returns a plan within the budget or nothing
+  if (p.buffers > 1 && order != TN_ORDER_SWEEP_AUTO) {
+    tn::Plan q;
+    const tn_status sb = tn::build_plan(g, order, qh, qw, q, err, p.buffers - 1);
+    if (order == TN_ORDER_HEURISTIC)
+      check(sb == TN_ENOMEM || (sb == TN_OK && q.buffers <= p.buffers - 1 && q.peak >= p.peak),
+            "budgeted heuristic", r, c, D, order);
+    else
+      check(sb == TN_ENOMEM, "budget refused", r, c, D, order);
+  }
   const std::string t = tn::plan_text(p);
   check(t.rfind("tnplan v1", 0) == 0, "plan text", r, c, D, order);
 }
@@ -189,13 +222,13 @@ int main() {
       for (size_t i = 0; i < h.size(); ++i) h[i] = 1 + static_cast<int32_t>((i * 7 + 3) % 4);
       for (size_t i = 0; i < v.size(); ++i) v[i] = 1 + static_cast<int32_t>((i * 5 + 1) % 4);
       for (int D = 1; D <= 5; ++D)
-        for (int order = 0; order < 4; ++order) {
+        for (int order = 0; order < 6; ++order) {
           run(r, c, D, nullptr, nullptr, order, 0, 0, plans);
           if (order == TN_ORDER_QUADRANT)
             for (int qh = 1; qh < r; ++qh)
               for (int qw = 1; qw < c; ++qw) run(r, c, D, nullptr, nullptr, order, qh, qw, plans);
         }
-      for (int order = 0; order < 4; ++order)
+      for (int order = 0; order < 6; ++order)
         run(r, c, 1, h.empty() ? nullptr : h.data(), v.empty() ? nullptr : v.data(), order, 0, 0,
             plans);
       for (int D = 1; D <= 3; ++D) run_cuts(r, c, D, nullptr, nullptr, plans);

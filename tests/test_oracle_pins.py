@@ -13,7 +13,7 @@ from oracle import invariants as inv
 from oracle import network as nw
 from oracle import plan as P
 
-ORDERS = [P.COLSWEEP, P.QUADRANT, P.HEURISTIC]
+ORDERS = [P.COLSWEEP, P.QUADRANT, P.HEURISTIC, P.ROWS, P.ROWS_T]
 
 
 def rel(a, b):
@@ -236,6 +236,54 @@ def test_sweep_auto_closed_forms(R, C_):
         assert p.slots == long_ - 1
 
 
+def _rows_flops(R, C_, D):
+    # edge rows: joining site j (1 <= j <= C-2) makes D^(j+1) down legs times
+    # the right leg from D^j down legs, the right leg and the site's two new
+    # legs; the last site closes the right leg.  Bulk rows carry up and down
+    # legs alike.  Links: D^C x D^C products, the last one D^C x 1.
+    edge = sum(2 * D ** (j + 3) for j in range(1, C_ - 1)) + 2 * D ** (C_ + 1)
+    bulk = sum(2 * D ** (2 * j + 4) for j in range(1, C_ - 1)) + 2 * D ** (2 * C_ + 1)
+    return 2 * edge + (R - 2) * bulk + (R - 2) * 2 * D ** (2 * C_) + 2 * D ** C_
+
+
+@pytest.mark.parametrize("R,C_", [(r, c) for r in range(3, 9) for c in range(3, 8)])
+def test_rows_closed_forms(R, C_):
+    # §4, row scheme: contracting along the rows leaves a chain of row tensors
+    # whose bulk members carry chi^L legs up and chi^L down
+    for D in (2, 3):
+        p = P.plan_grid(R, C_, D, order=P.ROWS)
+        assert p.order == P.ROWS and p.transpose == 0
+        assert len(p.units) == R and len(p.chain) == R - 1
+        assert [u.result for u in p.units] == [D ** C_] + [D ** (2 * C_)] * (R - 2) + [D ** C_]
+        assert p.peak == D ** (2 * C_)
+        assert p.flops == _rows_flops(R, C_, D)
+        assert p.buffers == 6 * D ** C_ + (R - 2) * 2 * D ** (2 * C_)
+        assert [lk.N for lk in p.chain] == [D ** C_] * (R - 2) + [1]
+        t = P.plan_grid(C_, R, D, order=P.ROWS_T)       # the same over columns
+        assert (t.peak, t.flops, t.transpose) == (p.peak, p.flops, 1)
+
+
+def test_heuristic_with_a_storage_budget():
+    # §4 / §6: the order decides what fits.  Under a budget between the
+    # sweep's and the quadrant's storage the heuristic falls back to the
+    # sweep; below every candidate nothing fits.
+    for L, D in [(6, 2), (8, 2), (10, 4), (12, 4)]:
+        q = P.plan_grid(L, L, D, order=P.QUADRANT)
+        sw = P.plan_grid(L, L, D, order=P.COLSWEEP)
+        assert sw.buffers == 2 * D ** (L + 1) and sw.buffers < q.buffers
+        assert P.plan_grid(L, L, D, order=P.HEURISTIC).order == P.QUADRANT
+        got = P.plan_grid(L, L, D, order=P.HEURISTIC, budget=q.buffers - 1)
+        assert got.order == P.COLSWEEP and got.buffers <= q.buffers - 1
+        with pytest.raises(P.PlanTooLarge):
+            P.plan_grid(L, L, D, order=P.HEURISTIC, budget=sw.buffers - 1)
+        with pytest.raises(P.PlanTooLarge):
+            P.plan_grid(L, L, D, order=P.QUADRANT, budget=q.buffers - 1)
+    # the row scheme is the first to run out (§6): at 10 x 10, D = 4 its bulk
+    # row tensors hold 4^20 entries each
+    with pytest.raises(P.PlanTooLarge):
+        P.plan_grid(10, 10, 4, order=P.ROWS, budget=1 << 31)
+
+
 def test_paper_row_and_quadrant_bond_sizes():
     # §4: sweeping whole rows/columns leaves boundary legs of total size
     # chi^L (the chain); quadrants meet in a ring whose bonds carry chi^(L/2)
@@ -312,3 +360,11 @@ def test_pins_catch_a_perturbed_site():
     bad2 = [t.copy() for t in s]
     bad2[4].flat[3] *= 1.01
     assert rel(nw.brute_bonds(bad2, 3, 3), ref) > 1e-6
+
+
+def test_pins_catch_a_wrong_chain_side(monkeypatch):
+    sites = li.uniform(4, 3, 2, seed=5)
+    ref = nw.brute_bonds(sites, 4, 3)
+    p = P.plan_grid(4, 3, 2, order=P.ROWS)
+    p.chain[0].side = 1 - p.chain[0].side     # read the row tensor transposed
+    assert rel(C.contract(sites, p).value, ref) > 1e-6

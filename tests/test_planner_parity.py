@@ -6,7 +6,7 @@ import pytest
 import paper_1908_08553_amd as tn
 from oracle import plan as P
 
-ORDERS = [P.COLSWEEP, P.QUADRANT, P.HEURISTIC, P.SWEEP_AUTO]
+ORDERS = [P.COLSWEEP, P.QUADRANT, P.HEURISTIC, P.SWEEP_AUTO, P.ROWS, P.ROWS_T]
 
 
 def both(rows, cols, D=2, hdim=None, vdim=None, order=P.COLSWEEP, qh=0, qw=0):
@@ -24,6 +24,14 @@ def test_uniform_plans_bit_exact(rows, cols):
                 continue
             if order == P.HEURISTIC and rows * cols > 100 and D > 2:
                 continue
+            if order in (P.ROWS, P.ROWS_T):
+                try:
+                    P.plan_grid(rows, cols, D, order=order)
+                except P.PlanOverflow:
+                    with pytest.raises(tn.TnError) as e:
+                        tn.tn_plan_grid(rows, cols, D, order=order)
+                    assert e.value.status == tn.TN_EOVERFLOW
+                    continue
             got, ref = both(rows, cols, D, order=order)
             assert got == ref
 
@@ -108,3 +116,40 @@ def test_ring_split_slices_host_only():
     # no ring: sweeps; no MFMA ring: D = 3 gives m = 243
     assert tn.tn_plan_grid(10, 10, 4).info()["ring_slices"] == [0, 0, 0]
     assert tn.tn_plan_grid(10, 10, 3, order=tn.TN_ORDER_QUADRANT).info()["ring_slices"] == [1, 1, 1]
+
+
+def test_row_scheme_and_budget_bit_exact():
+    # every explicit order and the heuristic under budgets around each
+    # candidate's storage: the same plan, or "too large" on both sides
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        rows, cols = (int(x) for x in rng.integers(1, 8, size=2))
+        D = int(rng.integers(1, 4))
+        sizes = sorted({P.plan_grid(rows, cols, D, order=o).buffers
+                        for o in (P.COLSWEEP, P.ROWS, P.ROWS_T)})
+        if rows >= 2 and cols >= 2:
+            sizes.append(P.plan_grid(rows, cols, D, order=P.QUADRANT).buffers)
+        for b in sorted({s + d for s in sizes for d in (-1, 0)} | {0}):
+            for order in (P.HEURISTIC, P.SWEEP_AUTO, P.COLSWEEP, P.ROWS, P.ROWS_T):
+                try:
+                    ref = P.plan_text(P.plan_grid(rows, cols, D, order=order, budget=b))
+                except P.PlanTooLarge:
+                    ref = None
+                try:
+                    got = tn.tn_plan_text(tn.tn_plan_grid(rows, cols, D, order=order, budget=b))
+                except tn.TnError as e:
+                    assert e.status == tn.TN_ENOMEM, (rows, cols, D, order, b)
+                    got = None
+                if b <= 0:
+                    assert got is not None
+                assert got == ref, (rows, cols, D, order, b)
+
+
+def test_buffer_entries_match_oracle():
+    for (r, c, D) in [(6, 6, 2), (8, 8, 2), (6, 6, 4), (12, 12, 4), (5, 7, 3), (1, 9, 2)]:
+        for order in (P.COLSWEEP, P.HEURISTIC, P.ROWS, P.ROWS_T):
+            ref = P.plan_grid(r, c, D, order=order)
+            info = tn.tn_plan_grid(r, c, D, order=order).info()
+            assert info["buffer_entries"] == ref.buffers
+            assert info["n_links"] == len(ref.chain)
+            assert info["peak_entries"] == ref.peak and info["flops"] == ref.flops
