@@ -281,6 +281,53 @@ def peps_env_leg(tn, torch, rows=10, cols=10, chi=2, seed=3, reps=5):
             "all_finite": all(r.status == 0 for r in out["results"])}
 
 
+def orders_leg(tn, torch, reps=5):
+    """The paper's order comparison (§6, Fig. 6: row scheme against quadrant
+    scheme, 5 <= L <= 10): FP64 contractions of L x L networks (uniform
+    entries, seed 0) in the row scheme, the quadrant order and the column
+    sweep, at D = 2 for L = 5..10 and D = 4 for L = 5..8.  A plan is run only
+    when its intermediate storage fits the free device memory
+    (tn_plan_grid_budget); the row scheme stops fitting first."""
+    import lattice_inputs as li
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free) // 8          # float64 entries
+    out = {}
+    for D, Ls in ((2, range(5, 11)), (4, range(5, 9))):
+        for L in Ls:
+            row = {}
+            sites = None
+            for name, order in (("rows", tn.TN_ORDER_ROWS), ("quadrant", tn.TN_ORDER_QUADRANT),
+                                ("sweep", tn.TN_ORDER_COLSWEEP)):
+                try:
+                    plan = tn.tn_plan_grid(L, L, D, order=order, budget=budget)
+                except tn.TnError as e:
+                    if e.status not in (tn.TN_ENOMEM, tn.TN_EOVERFLOW):
+                        raise
+                    row[name] = {"fits": False, "peak_entries": None}
+                    continue
+                if sites is None:
+                    sites = tn.prepare_sites(tn.device_sites(li.uniform(L, L, D, 0)))
+                info = plan.info()
+                ws = tn.workspace_for(plan, tn.TN_PREC_F64)
+                r = tn.contract_grid(plan, sites, "f64", ws)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    r = tn.contract_grid(plan, sites, "f64", ws)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / reps
+                del ws
+                row[name] = {"fits": True, "ms": 1e3 * dt, "gflops": info["flops"] / dt / 1e9,
+                             "peak_entries": info["peak_entries"],
+                             "buffer_entries": info["buffer_entries"], "log_abs": r.log_abs}
+            q = row["quadrant"]
+            if row["rows"]["fits"]:
+                row["rows_over_quadrant_time"] = row["rows"]["ms"] / q["ms"]
+                row["abs_dlogz_rows_vs_quadrant"] = abs(row["rows"]["log_abs"] - q["log_abs"])
+            out[f"L{L}_D{D}"] = row
+    return out
+
+
 def served_leg(tn, torch, n=2000, seed=5):
     """Poisson stream: L ~ U{4..13} square Ising lattices, D ~ U{2,4} (D=4 is
     the two-replica network), tag ~ U{FP64, BF16x3}, beta*J ~ U[0.1, 0.8],
@@ -493,6 +540,9 @@ def main():
             legs["peps10_observables_env_f64"] = peps_env_leg(tn, torch)
             log(f"peps observables, cached environments: "
                 f"{json.dumps(legs['peps10_observables_env_f64'])}")
+        if not args.leg or "orders" in args.leg:
+            legs["orders"] = orders_leg(tn, torch)
+            log(f"orders: {json.dumps(legs['orders'])}")
         if not args.no_serve:
             legs["served"] = served_leg(tn, torch)
             log(f"served: {json.dumps(legs['served'])}")

@@ -26,6 +26,11 @@ Modules (each function cites the passage of the paper it follows):
 * ``peps``         -- norm and expectation-value networks of a real PEPS
                        (paper §3 and §5): double-layer sites, the observable
                        set m^x, m^z, c_ij, and brute-force amplitudes.
+* ``ite``          -- imaginary-time evolution of a PEPS (§5: Trotter-Suzuki
+                       step, one-body gates, two-body gates split by SVD with
+                       truncation, normalisation, energy) and exact
+                       diagonalisation of the transverse-field Ising model
+                       (§3), pinned in ``tests/test_ite_oracle.py``.
 
 Parity status of every function is stated in its docstring.  Each is pinned
 in ``tests/test_oracle_pins.py`` (and ``tests/test_peps_oracle.py`` for
