@@ -338,6 +338,72 @@ tn_status tn_envset_run(tn_envset* set, const double* const* base, const double*
 
 tn_status tn_envset_destroy(tn_envset* set);
 
+/* ------------------------------------------------------------ imaginary time
+ * Ground state of the transverse-field Ising model (§3)
+ *   H = -J sum_<ij> S^z_i S^z_j - gamma sum_i S^x_i,  S = Pauli matrices
+ * (S^z takes the values +1 and -1; the critical point lies near gamma = 3J)
+ * by imaginary-time evolution of a PEPS (§5): from the uniform superposition
+ * of product states (bond dimension 1), each step applies the second-order
+ * Trotter-Suzuki product U^gamma(dtau/2) U^J(dtau) U^gamma(dtau/2):
+ *   - the one-body gate exp(gamma t sigma^x) contracted into every site's
+ *     spin index;
+ *   - the two-body gate exp(J dtau s_i s_j) on every nearest-neighbour pair:
+ *     the two sites contracted over their shared bond and the gate over their
+ *     spins, the result folded into a matrix (each site's open indices) and
+ *     split by a singular value decomposition (one-sided Jacobi on the GPU)
+ *     into U sqrt(lambda) and sqrt(lambda) V^T, keeping the singular values
+ *     at or above eps times the largest, at most chi_max of them (the rest of
+ *     every bond, up to chi_max, holds zeros).  Pairs go in four classes of
+ *     disjoint bonds: horizontal bonds with the left site in an even column,
+ *     in an odd column, vertical bonds with the upper site in an even row, in
+ *     an odd row;
+ *   - the state normalised to <Psi|Psi> = 1 after each of the three operator
+ *     sets (the norm network contracted in float64 by this library, every
+ *     site scaled by the same factor).
+ * The energy <H> and the local m^x, m^z, c_ij come from the expectation-value
+ * networks of §5, contracted in one batched launch.  Each pair's singular
+ * pair is signed so that the first entry of the left vector above 1e-6 of
+ * its largest magnitude is positive.  All device memory is the caller's
+ * workspace; every call runs on the stream given at create and blocks until
+ * its work is done.                                                         */
+typedef struct tn_ite tn_ite;
+
+typedef struct {
+  int32_t rows, cols;      /* lattice (>= 1 each, at most 4096 sites)           */
+  int32_t chi_max;         /* largest bond dimension kept, 1..3                */
+  int32_t reserved;        /* must be 0                                        */
+  double  J, gamma;        /* couplings of H                                   */
+  double  eps;             /* relative singular-value cutoff (>= 0; the paper's */
+                           /* timing runs use 0.01)                            */
+} tn_ite_config;
+
+/* Workspace bytes (device memory) an evolution of this configuration needs.
+ * Errors: TN_EINVAL (bad configuration), TN_EOVERFLOW.                      */
+tn_status tn_ite_workspace(const tn_ite_config* cfg, size_t* bytes);
+
+/* Set up the evolution in `workspace` (>= tn_ite_workspace bytes, 256-byte
+ * aligned, owned by the caller, reserved until destroy) on hip_stream, with
+ * the state set to the uniform product state.  Uses the current device.     */
+tn_status tn_ite_create(const tn_ite_config* cfg, void* workspace, size_t ws_bytes,
+                        void* hip_stream, tn_ite** out);
+
+/* n_steps Trotter steps of imaginary time dtau each (dtau > 0).  Errors:
+ * TN_EINVAL, TN_EDEVICE, TN_ENONFINITE (the norm became zero or non-finite). */
+tn_status tn_ite_step(tn_ite* ite, double dtau, int32_t n_steps);
+
+/* <H> / <Psi|Psi> of the current state, with m^x and m^z per site (row-major,
+ * rows*cols each) and c_ij per nearest-neighbour bond (horizontal bonds row
+ * by row, then vertical), the same layout as tn_observables.  Host arrays. */
+tn_status tn_ite_energy(tn_ite* ite, double* energy, double* mx, double* mz, double* czz);
+
+/* Device pointers to the current site tensors, rows*cols of them, row-major:
+ * site k is A[2][chi_max]...[chi_max] (spin index first, then its bond legs
+ * in canonical order), float64, C-order.  They stay valid until destroy; a
+ * caller may write a state into them between calls.                       */
+tn_status tn_ite_sites(tn_ite* ite, double** sites);
+
+tn_status tn_ite_destroy(tn_ite* ite);
+
 /* ------------------------------------------------------------ serving
  * A request loop that admits contractions of different sizes and precisions
  * as they arrive.  A scheduler thread admits queued requests first-come-

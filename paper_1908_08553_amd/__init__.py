@@ -19,7 +19,7 @@ from ._native import (  # noqa: F401
     TN_OPT_QUADRANT_STREAMS, TN_OPT_CHAIN_STEPS, TN_OPT_ENV_STREAMS, TN_OPT_ENV_ROWS,
     TN_OPT_ENV_SITES,
     tn_profile_enable, tn_profile_read,
-    Batch, tn_batch_workspace, tn_contract_batch, Server, EnvSet,
+    Batch, tn_batch_workspace, tn_contract_batch, Server, EnvSet, Ite,
     plan_grid, contract_grid, device_sites, workspace_for,
     tn_double_layer, tn_double_layer_prepare, tn_observables, Sites, prepare_sites,
 )

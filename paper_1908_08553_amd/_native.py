@@ -659,3 +659,100 @@ class Server:
 
     def __del__(self):
         self.close()
+
+
+# ------------------------------------------------------------ imaginary time
+class tn_ite_config(C.Structure):
+    _fields_ = [("rows", C.c_int32), ("cols", C.c_int32), ("chi_max", C.c_int32),
+                ("reserved", C.c_int32), ("J", C.c_double), ("gamma", C.c_double),
+                ("eps", C.c_double)]
+
+
+lib.tn_ite_workspace.restype = C.c_int32
+lib.tn_ite_workspace.argtypes = [C.POINTER(tn_ite_config), C.POINTER(C.c_size_t)]
+lib.tn_ite_create.restype = C.c_int32
+lib.tn_ite_create.argtypes = [C.POINTER(tn_ite_config), _P, C.c_size_t, _P, C.POINTER(_P)]
+lib.tn_ite_step.restype = C.c_int32
+lib.tn_ite_step.argtypes = [_P, C.c_double, C.c_int32]
+lib.tn_ite_energy.restype = C.c_int32
+lib.tn_ite_energy.argtypes = [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                              C.POINTER(C.c_double), C.POINTER(C.c_double)]
+lib.tn_ite_sites.restype = C.c_int32
+lib.tn_ite_sites.argtypes = [_P, C.POINTER(C.c_void_p)]
+lib.tn_ite_destroy.restype = C.c_int32
+lib.tn_ite_destroy.argtypes = [_P]
+
+
+class Ite:
+    """tn_ite over a torch-allocated workspace: imaginary-time evolution of a
+    rows x cols PEPS for H = -J sum S^z S^z - gamma sum S^x (S = Pauli)."""
+
+    def __init__(self, rows: int, cols: int, chi_max: int, J: float, gamma: float,
+                 eps: float = 0.01, device="cuda"):
+        import torch
+        self.rows, self.cols, self.chi = rows, cols, chi_max
+        self.cfg = tn_ite_config(rows, cols, chi_max, 0, J, gamma, eps)
+        n = C.c_size_t(0)
+        _check(lib.tn_ite_workspace(C.byref(self.cfg), C.byref(n)))
+        self.ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib.tn_ite_create(C.byref(self.cfg), C.c_void_p(self.ws.data_ptr()),
+                                 self.ws.numel(), C.c_void_p(self.stream.cuda_stream),
+                                 C.byref(h)))
+        self._h = h
+
+    def step(self, dtau: float, n: int = 1):
+        _check(lib.tn_ite_step(self._h, dtau, n))
+
+    def energy(self):
+        """(E, mx, mz, czz) of the current state."""
+        n = self.rows * self.cols
+        nb = self.rows * (self.cols - 1) + (self.rows - 1) * self.cols
+        e = C.c_double()
+        mx, mz, cz = (C.c_double * n)(), (C.c_double * n)(), (C.c_double * max(nb, 1))()
+        _check(lib.tn_ite_energy(self._h, C.byref(e), mx, mz, cz))
+        return e.value, list(mx), list(mz), list(cz)[:nb]
+
+    def site_views(self):
+        """The current site tensors as float64 torch views of the workspace
+        (canonical shapes [2][chi]..[chi]); writing them sets the state."""
+        import torch
+        n = self.rows * self.cols
+        ptrs = (C.c_void_p * n)()
+        _check(lib.tn_ite_sites(self._h, ptrs))
+        base = self.ws.data_ptr()
+        out = []
+        for k in range(n):
+            r, c = divmod(k, self.cols)
+            rank = (c > 0) + (r > 0) + (c < self.cols - 1) + (r < self.rows - 1)
+            shape = (2,) + (self.chi,) * rank
+            cnt = 2 * self.chi ** rank
+            off = ptrs[k] - base
+            out.append(self.ws[off:off + 8 * cnt].view(torch.float64).reshape(shape))
+        return out
+
+    def evolve(self, tau: float, steps: int, energy_every: int = 2):
+        """`steps` Trotter steps of dtau = tau / steps; [(step, energy)] every
+        `energy_every` steps (the paper's monitoring, §5)."""
+        dtau = tau / steps
+        out = []
+        done = 0
+        while done < steps:
+            k = min(energy_every, steps - done) if energy_every else steps - done
+            self.step(dtau, k)
+            done += k
+            if energy_every and done % energy_every == 0:
+                out.append((done, self.energy()[0]))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.tn_ite_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover
+            pass

@@ -12,6 +12,7 @@
 
 #include "batch.hpp"
 #include "envset.hpp"
+#include "ite.hpp"
 #include "exec.hpp"
 #include "server.hpp"
 #include "kernels.hpp"
@@ -32,6 +33,10 @@ struct tn_server {
 
 struct tn_envset {
   tn::EnvSetImpl* impl;
+};
+
+struct tn_ite {
+  tn::IteImpl* impl;
 };
 
 namespace {
@@ -496,6 +501,75 @@ tn_status tn_double_layer(const tn_double_layer_site* sites, int32_t n, void* hi
   } catch (...) {
     return fail(TN_EINVAL, "tn_double_layer failed");
   }
+}
+
+tn_status tn_ite_workspace(const tn_ite_config* cfg, size_t* bytes) {
+  try {
+    if (!cfg || !bytes) return fail(TN_EINVAL, "null argument");
+    std::string err;
+    const tn_status s = tn::ite_workspace(*cfg, bytes, err);
+    return s == TN_OK ? s : fail(s, err);
+  } catch (...) {
+    return fail(TN_EINVAL, "tn_ite_workspace failed");
+  }
+}
+
+tn_status tn_ite_create(const tn_ite_config* cfg, void* workspace, size_t ws_bytes,
+                        void* hip_stream, tn_ite** out) {
+  try {
+    if (!cfg || !workspace || !out) return fail(TN_EINVAL, "null argument");
+    *out = nullptr;
+    std::string err;
+    tn::IteImpl* impl = nullptr;
+    const tn_status s = tn::ite_create(*cfg, workspace, ws_bytes,
+                                       static_cast<hipStream_t>(hip_stream), &impl, err);
+    if (s != TN_OK) return fail(s, err);
+    *out = new tn_ite{impl};
+    return TN_OK;
+  } catch (const std::exception& e) {
+    return fail(TN_EDEVICE, e.what());
+  } catch (...) {
+    return fail(TN_EDEVICE, "tn_ite_create failed");
+  }
+}
+
+tn_status tn_ite_step(tn_ite* ite, double dtau, int32_t n_steps) {
+  try {
+    if (!ite) return fail(TN_EINVAL, "null argument");
+    std::string err;
+    const tn_status s = tn::ite_step(ite->impl, dtau, n_steps, err);
+    return s == TN_OK ? s : fail(s, err);
+  } catch (const std::exception& e) {
+    return fail(TN_EDEVICE, e.what());
+  } catch (...) {
+    return fail(TN_EDEVICE, "tn_ite_step failed");
+  }
+}
+
+tn_status tn_ite_energy(tn_ite* ite, double* energy, double* mx, double* mz, double* czz) {
+  try {
+    if (!ite || !energy || !mx || !mz || !czz) return fail(TN_EINVAL, "null argument");
+    std::string err;
+    const tn_status s = tn::ite_energy(ite->impl, energy, mx, mz, czz, err);
+    return s == TN_OK ? s : fail(s, err);
+  } catch (const std::exception& e) {
+    return fail(TN_EDEVICE, e.what());
+  } catch (...) {
+    return fail(TN_EDEVICE, "tn_ite_energy failed");
+  }
+}
+
+tn_status tn_ite_sites(tn_ite* ite, double** sites) {
+  if (!ite || !sites) return fail(TN_EINVAL, "null argument");
+  tn::ite_sites(ite->impl, sites);
+  return TN_OK;
+}
+
+tn_status tn_ite_destroy(tn_ite* ite) {
+  if (!ite) return TN_OK;
+  tn::ite_destroy(ite->impl);
+  delete ite;
+  return TN_OK;
 }
 
 tn_status tn_observables(const tn_result* results, int32_t rows, int32_t cols, double* mx,

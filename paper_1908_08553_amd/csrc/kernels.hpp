@@ -231,6 +231,29 @@ struct LinkArgs {
 int64_t link_chunks(int32_t side, int64_t K, int64_t N);
 hipError_t launch_row_link(const LinkArgs& a, hipStream_t stream);
 
+// Imaginary-time evolution kernels (ite.hip).  Site k of the state is
+// A[2][chi^rank] at `off` entries into the state buffer (half = chi^rank).
+constexpr int32_t kIteMaxChi = 3;
+constexpr int32_t kIteMaxDim = 64;
+struct IteSiteDesc {
+  int64_t off, half;
+};
+// A pair gate's sites: offsets, bond-leg counts and the index of the shared
+// bond among each site's bond legs (canonical order).
+struct ItePairDesc {
+  int64_t off_i, off_j;
+  int32_t ri, rj, ai, aj;
+};
+struct IteGate2 {
+  double g[16];    // G[(s_i s_j)][(a c)], row-major
+};
+hipError_t launch_ite_gate1(double* state, const IteSiteDesc* sites, int32_t n_sites,
+                            int64_t max_half, const double g[4], hipStream_t stream);
+hipError_t launch_ite_scale(double* state, int64_t n, double f, hipStream_t stream);
+hipError_t launch_ite_pairs(double* state, const ItePairDesc* pairs, int32_t n_pairs,
+                            const IteGate2& gate, int32_t chi, double eps, int32_t* kept,
+                            hipStream_t stream);
+
 // Writes state->result from the final scalar (or the sum of `n_partials`
 // partials), the site exponents, the rescale slots and state->e_bias, plus
 // the exponent of `cap` (the boundary a cap dot closed against; nullable);
