@@ -328,6 +328,47 @@ def orders_leg(tn, torch, reps=5):
     return out
 
 
+def ite_leg(tn, torch, steps=10):
+    """Imaginary-time evolution (§5) on the paper's Fig. 5 workload: L x L
+    lattices, 5 <= L <= 8, chi = 2, Gamma = J = 1, eps = 0.01: milliseconds
+    per Trotter step (one-body gates, pair gates with their SVDs, three
+    normalisations) and per energy evaluation (1 + 2L^2 + 2L(L-1) networks of
+    bond dimension 4), after `steps` warm steps.  Also the 2 x 2 and 3 x 3
+    energies of Fig. 4 (chi = 2, tau = 3, 200 steps) next to exact
+    diagonalisation, which the CPU leg supplies."""
+    out = {}
+    for L in range(5, 9):
+        ite = tn.Ite(L, L, 2, 1.0, 1.0, 0.01)
+        ite.step(0.03, steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ite.step(0.03, steps)
+        torch.cuda.synchronize()
+        t_step = (time.perf_counter() - t0) / steps
+        ite.energy()
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            e = ite.energy()[0]
+        t_e = (time.perf_counter() - t0) / reps
+        ite.close()
+        out[f"L{L}"] = {"ms_per_step": 1e3 * t_step, "ms_per_energy": 1e3 * t_e,
+                        "networks_per_energy": 1 + 2 * L * L + 2 * L * (L - 1),
+                        "energy_per_site": e / (L * L)}
+    fig4 = {}
+    for L in (2, 3):
+        for G in (0.5, 1.0, 2.0):
+            ite = tn.Ite(L, L, 2, 1.0, G, 1e-10)
+            t0 = time.perf_counter()
+            es = ite.evolve(3.0, 200, energy_every=2)
+            torch.cuda.synchronize()
+            fig4[f"{L}x{L}_G{G}"] = {"energy_per_site": es[-1][1] / (L * L),
+                                     "s_for_200_steps_with_energies": time.perf_counter() - t0}
+            ite.close()
+    out["fig4"] = fig4
+    return out
+
+
 def served_leg(tn, torch, n=2000, seed=5):
     """Poisson stream: L ~ U{4..13} square Ising lattices, D ~ U{2,4} (D=4 is
     the two-replica network), tag ~ U{FP64, BF16x3}, beta*J ~ U[0.1, 0.8],
@@ -441,11 +482,15 @@ def cpu_baseline():
     t = time.perf_counter()
     r = OC.contract(sites, plan)
     dt = time.perf_counter() - t
+    from oracle import ite as OI
+    ed = {f"{L}x{L}_G{G}": OI.ground_energy(L, L, 1.0, G) / (L * L)
+          for L in (2, 3) for G in (0.5, 1.0, 2.0)}
     return {"value": plan.flops / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"one complete 12x12 D=4 contraction (quadrant plan, {plan.flops:.3e} "
                       f"flops), FP64 numpy/OpenBLAS, {dt:.1f} s",
             "log_abs": r.log_abs, "sign": r.sign,
-            "ising12_d4_log_abs_transfer_matrix": 2 * ON.transfer_log_z(12, 12, 0.44)}
+            "ising12_d4_log_abs_transfer_matrix": 2 * ON.transfer_log_z(12, 12, 0.44),
+            "ed_energy_per_site": ed}
 
 
 LEGS = [("quad12_f32", 12, 12, 4, "uniform", 1, "f32"),
@@ -543,6 +588,14 @@ def main():
         if not args.leg or "orders" in args.leg:
             legs["orders"] = orders_leg(tn, torch)
             log(f"orders: {json.dumps(legs['orders'])}")
+        if not args.leg or "ite" in args.leg:
+            legs["ite"] = ite_leg(tn, torch)
+            if cpu:
+                for k, v in legs["ite"]["fig4"].items():
+                    v["ed_energy_per_site"] = cpu["ed_energy_per_site"][k]
+                    v["rel_error_vs_ed"] = abs(v["energy_per_site"] - v["ed_energy_per_site"]) / \
+                        abs(v["ed_energy_per_site"])
+            log(f"ite: {json.dumps(legs['ite'])}")
         if not args.no_serve:
             legs["served"] = served_leg(tn, torch)
             log(f"served: {json.dumps(legs['served'])}")
