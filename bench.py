@@ -576,19 +576,25 @@ def main():
         ref = {"uniform": ref_u, "ising": ref_i}.get(leg["inputs"]) if leg["rows"] == 12 else None
         if ref is not None:
             leg[f"abs_dlogz_vs_{ref_name}"] = abs(leg["log_abs"] - ref)
+    def want(name):
+        return not args.leg or name in args.leg
+
     if not args.no_legs:
         if not args.no_batch:
-            legs["batch512_f32"] = batch_leg(tn, torch)
-            log(f"batch: {legs['batch512_f32']['contractions_per_s']:.0f} contractions/s")
-            legs["peps6_observables_f64"] = peps_leg(tn, torch)
-            log(f"peps observables: {json.dumps(legs['peps6_observables_f64'])}")
-            legs["peps10_observables_env_f64"] = peps_env_leg(tn, torch)
-            log(f"peps observables, cached environments: "
-                f"{json.dumps(legs['peps10_observables_env_f64'])}")
-        if not args.leg or "orders" in args.leg:
+            if want("batch512_f32"):
+                legs["batch512_f32"] = batch_leg(tn, torch)
+                log(f"batch: {legs['batch512_f32']['contractions_per_s']:.0f} contractions/s")
+            if want("peps6_observables_f64"):
+                legs["peps6_observables_f64"] = peps_leg(tn, torch)
+                log(f"peps observables: {json.dumps(legs['peps6_observables_f64'])}")
+            if want("peps10_observables_env_f64"):
+                legs["peps10_observables_env_f64"] = peps_env_leg(tn, torch)
+                log(f"peps observables, cached environments: "
+                    f"{json.dumps(legs['peps10_observables_env_f64'])}")
+        if want("orders"):
             legs["orders"] = orders_leg(tn, torch)
             log(f"orders: {json.dumps(legs['orders'])}")
-        if not args.leg or "ite" in args.leg:
+        if want("ite"):
             legs["ite"] = ite_leg(tn, torch)
             if cpu:
                 for k, v in legs["ite"]["fig4"].items():
@@ -596,7 +602,7 @@ def main():
                     v["rel_error_vs_ed"] = abs(v["energy_per_site"] - v["ed_energy_per_site"]) / \
                         abs(v["ed_energy_per_site"])
             log(f"ite: {json.dumps(legs['ite'])}")
-        if not args.no_serve:
+        if not args.no_serve and want("served"):
             legs["served"] = served_leg(tn, torch)
             log(f"served: {json.dumps(legs['served'])}")
     head_kernels = head.pop("kernels")

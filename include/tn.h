@@ -266,10 +266,14 @@ tn_status tn_contract_batch(const tn_plan* const* plans, const double* const* co
 typedef struct {
   const double* A;   /* [d][dims[0]]..[dims[rank-1]], C-order                  */
   const double* op;  /* [d][d] operator O[s'][s], or NULL for the identity     */
-  double* E;         /* [dims[0]^2]..[dims[rank-1]^2], C-order (output)        */
+  double* E;         /* [dims[perm[0]]^2]..[dims[perm[rank-1]]^2], C-order      */
   int32_t d;         /* spin dimension                                         */
   int32_t rank;      /* bond legs in canonical order (left, up, right, down)   */
-  int32_t dims[4];   /* bond dimensions, the first `rank` are used             */
+  int32_t dims[4];   /* bond dimensions of A, the first `rank` are used        */
+  int32_t perm[4];   /* E's bond leg k is A's bond leg perm[k] (the first     */
+                     /* `rank` entries, a permutation); all zero: E's legs in */
+                     /* A's order.  Used to lay a site out for the transposed */
+                     /* lattice (left <-> up, right <-> down).                */
 } tn_double_layer_site;
 
 tn_status tn_double_layer(const tn_double_layer_site* sites, int32_t n, void* hip_stream);

@@ -99,7 +99,7 @@ TN_STATIC_SCRATCH_BYTES = 160 << 20
 
 class tn_double_layer_site(C.Structure):
     _fields_ = [("A", C.c_void_p), ("op", C.c_void_p), ("E", C.c_void_p), ("d", C.c_int32),
-                ("rank", C.c_int32), ("dims", C.c_int32 * 4)]
+                ("rank", C.c_int32), ("dims", C.c_int32 * 4), ("perm", C.c_int32 * 4)]
 
 
 lib.tn_double_layer.restype = C.c_int32
@@ -527,20 +527,25 @@ class EnvSet:
 
 # ------------------------------------------------------------------ PEPS
 def tn_double_layer_prepare(pairs):
-    """Checked descriptor array of (A, op, E) triples for repeated calls over
-    the same tensors (it keeps them alive)."""
+    """Checked descriptor array of (A, op, E) or (A, op, E, perm) entries for
+    repeated calls over the same tensors (it keeps them alive); perm lists
+    which of A's bond legs each of E's bond legs is (default: the same)."""
     import torch
     arr = (tn_double_layer_site * max(len(pairs), 1))()
-    for i, (A, op, E) in enumerate(pairs):
+    for i, item in enumerate(pairs):
+        A, op, E = item[:3]
         for t in (A, E) + ((op,) if op is not None else ()):
             if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
                 raise ValueError("double-layer tensors must be contiguous float64 device tensors")
         dims = list(A.shape[1:])
-        if len(dims) > 4 or tuple(E.shape) != tuple(n * n for n in dims):
-            raise ValueError("E must have shape dims^2 of A's bond legs (at most 4)")
+        perm = list(item[3]) if len(item) > 3 else list(range(len(dims)))
+        if len(dims) > 4 or sorted(perm) != list(range(len(dims))) or \
+                tuple(E.shape) != tuple(dims[a] * dims[a] for a in perm):
+            raise ValueError("E must have shape dims^2 of A's bond legs in perm order (at most 4)")
         arr[i] = tn_double_layer_site(A.data_ptr(), op.data_ptr() if op is not None else None,
                                       E.data_ptr(), A.shape[0], len(dims),
-                                      (C.c_int32 * 4)(*(dims + [1] * (4 - len(dims)))))
+                                      (C.c_int32 * 4)(*(dims + [1] * (4 - len(dims)))),
+                                      (C.c_int32 * 4)(*(perm + list(range(len(perm), 4)))))
     return arr, len(pairs), list(pairs)
 
 

@@ -490,6 +490,9 @@ tn_status tn_double_layer(const tn_double_layer_site* sites, int32_t n, void* hi
       }
       y.n_in = m;
       y.n_out = m * m;
+      bool given = false;
+      for (int k = 0; k < 4; ++k) given = given || x.perm[k] != 0;
+      for (int k = 0; k < 4; ++k) y.perm[k] = given ? x.perm[k] : k;
       if (x.rank < 0 || x.rank > 4 || !tn::double_layer_ok(y))
         return fail(TN_EINVAL, "bad double-layer site " + std::to_string(i));
     }

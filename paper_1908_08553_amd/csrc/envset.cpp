@@ -245,21 +245,45 @@ tn_status layout(EnvSetImpl& es, const tn_grid& grid, int32_t n, const int32_t* 
     if (s != TN_OK) return s;
   }
 
-  // a network's seed and cap are the environments at its cuts: same bonds in
-  // the same order (a planner invariant, checked once here)
+  // a network's seed and cap, and a site environment's two boundaries, are
+  // the environments at its cuts: the same bonds in the same order as the
+  // full sweep's boundary there (a planner invariant, checked once here, bond
+  // by bond)
+  std::vector<std::vector<int32_t>> legs;
+  s = sweep_legs(grid, legs, err);
+  if (s != TN_OK) return s;
+  auto seed_env = [&](int64_t k) -> const Plan& {   // boundary before step k
+    return (k % R == 0) ? es.left[k / R - 1] : es.fwd[k - 1];
+  };
+  auto cap_env = [&](int64_t k) -> const Plan& {    // all sites after step k
+    return (k % R == R - 1) ? es.right[C - 2 - k / R] : es.rev[k + 1];
+  };
   for (const Plan& p : es.cuts) {
     if (p.cut_k0 > 0) {
       const int64_t k = p.cut_k0;
-      const Plan& l = (k % R == 0) ? es.left[k / R - 1] : es.fwd[k - 1];
-      if (l.cut_legs.empty() || l.steps.back().out != p.steps[0].out) {
+      const Plan& l = seed_env(k);
+      if (l.cut_legs != legs[k - 1] || l.steps.back().out != p.steps[0].out) {
         err = "seed does not match its environment";
         return TN_EINVAL;
       }
     }
     if (p.cut_open_end) {
       const int64_t k = p.cut_k1 - 1;
-      const Plan& r = (k % R == R - 1) ? es.right[C - 2 - k / R] : es.rev[k + 1];
-      if (p.cut_legs != r.cut_legs) { err = "cap does not match its environment"; return TN_EINVAL; }
+      const Plan& r = cap_env(k);
+      if (p.cut_legs != r.cut_legs || p.cut_legs != legs[k]) {
+        err = "cap does not match its environment";
+        return TN_EINVAL;
+      }
+    }
+  }
+  for (const auto& w : es.sites_work) {
+    if (w.k > 0 && seed_env(w.k).cut_legs != legs[w.k - 1]) {
+      err = "site environment: boundary before the step out of leg order";
+      return TN_EINVAL;
+    }
+    if (w.k < total_steps - 1 && cap_env(w.k).cut_legs != legs[w.k]) {
+      err = "site environment: boundary after the step out of leg order";
+      return TN_EINVAL;
     }
   }
   es.S = g_env_streams;

@@ -184,7 +184,10 @@ tn_status build_layers(IteImpl& t, int32_t kinds, std::string& err) {
       d.n_out = S.half[i] * S.half[i];
       d.d = 2;
       d.rank = S.rank[i];
-      for (int32_t a = 0; a < 4; ++a) d.dims[a] = a < S.rank[i] ? S.chi : 1;
+      for (int32_t a = 0; a < 4; ++a) {
+        d.dims[a] = a < S.rank[i] ? S.chi : 1;
+        d.perm[a] = a;
+      }
       v.push_back(d);
     }
   ITE_HIP(launch_double_layer(v.data(), static_cast<int32_t>(v.size()), t.stream));

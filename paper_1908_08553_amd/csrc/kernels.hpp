@@ -207,6 +207,7 @@ struct DoubleLayerSite {
   int64_t n_in, n_out;
   int32_t d, rank;
   int32_t dims[4];
+  int32_t perm[4];   // E's bond leg k is A's bond leg perm[k] (a permutation)
 };
 bool double_layer_ok(const DoubleLayerSite& s);
 hipError_t launch_double_layer(const DoubleLayerSite* sites, int32_t n, hipStream_t stream);

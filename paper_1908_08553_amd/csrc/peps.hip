@@ -31,15 +31,23 @@ __global__ __launch_bounds__(kDlThreads) void double_layer_kernel(DlArgs args) {
   const DoubleLayerSite& x = args.s[blockIdx.y];
   const int64_t e = static_cast<int64_t>(blockIdx.x) * kDlThreads + threadIdx.x;
   if (e >= x.n_out) return;
-  // paired index of leg k: p_k = a_k * dim_k + a_k'; legs C-order, last fastest
-  int64_t rest = e, ket = 0, bra = 0, stride = 1;
+  // C-order strides of A's bond legs
+  int64_t astr[4];
+  int64_t st = 1;
   for (int k = x.rank - 1; k >= 0; --k) {
-    const int64_t dk = x.dims[k];
+    astr[k] = st;
+    st *= x.dims[k];
+  }
+  // E's leg k is A's leg perm[k]; its paired index p_k = a * dim + a' (E's
+  // legs C-order, last fastest)
+  int64_t rest = e, ket = 0, bra = 0;
+  for (int k = x.rank - 1; k >= 0; --k) {
+    const int a = x.perm[k];
+    const int64_t dk = x.dims[a];
     const int64_t p = rest % (dk * dk);
     rest /= dk * dk;
-    ket += (p / dk) * stride;
-    bra += (p % dk) * stride;
-    stride *= dk;
+    ket += (p / dk) * astr[a];
+    bra += (p % dk) * astr[a];
   }
   double acc = 0.0;
   for (int sp = 0; sp < x.d; ++sp) {
@@ -58,6 +66,11 @@ __global__ __launch_bounds__(kDlThreads) void double_layer_kernel(DlArgs args) {
 
 bool double_layer_ok(const DoubleLayerSite& s) {
   if (!s.A || !s.E || s.d < 1 || s.d > 64 || s.rank < 0 || s.rank > 4) return false;
+  int32_t seen = 0;
+  for (int k = 0; k < s.rank; ++k) {
+    if (s.perm[k] < 0 || s.perm[k] >= s.rank || (seen >> s.perm[k]) & 1) return false;
+    seen |= 1 << s.perm[k];
+  }
   int64_t n = 1;
   for (int k = 0; k < s.rank; ++k) {
     if (s.dims[k] < 1 || s.dims[k] > 46340) return false;

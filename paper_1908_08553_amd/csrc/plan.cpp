@@ -557,6 +557,24 @@ tn_status build_sweep_cut(const tn_grid& grid, int32_t mirror, int64_t k0, int64
   return TN_OK;
 }
 
+tn_status sweep_legs(const tn_grid& grid, std::vector<std::vector<int32_t>>& legs,
+                     std::string& err) {
+  Plan p;
+  const tn_status st = build_plan(grid, TN_ORDER_COLSWEEP, 0, 0, p, err);
+  if (st != TN_OK) return st;
+  Lattice L{p.rows, p.cols, &p.hdim, &p.vdim};
+  std::vector<Step> all;
+  int32_t slot = 0;
+  legs.clear();
+  try {
+    sweep(L, 0, FRAME_ID, p.rows, p.cols, false, slot, all, &legs);
+  } catch (Overflow&) {
+    err = "plan integers overflow int64";
+    return TN_EOVERFLOW;
+  }
+  return TN_OK;
+}
+
 tn_status build_cut_plan(const tn_grid& grid, int32_t mirror, int32_t c0, int32_t c1, Plan& out,
                          std::string& err) {
   if (grid.rows < 1 || c0 < 0 || c1 < c0) { err = "cut columns out of range"; return TN_EINVAL; }

@@ -119,6 +119,12 @@ tn_status build_cut_plan(const tn_grid& grid, int32_t mirror, int32_t c0, int32_
 // at the bottom-right site, which starts the boundary (INIT).  1 <= r < rows.
 tn_status build_rev_step(const tn_grid& grid, int32_t r, int32_t c, Plan& out, std::string& err);
 
+// Bond ids of the boundary after every step of the full left-to-right column
+// sweep (legs[k] after step k, slowest first): the leg order every cut plan,
+// environment and reverse step of the sweep must share.
+tn_status sweep_legs(const tn_grid& grid, std::vector<std::vector<int32_t>>& legs,
+                     std::string& err);
+
 // Canonical text: identical bytes for identical plans.
 std::string plan_text(const Plan& p);
 

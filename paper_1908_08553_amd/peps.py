@@ -46,11 +46,17 @@ class ObservableSet:
         if mode not in ("auto", "batch", "env"):
             raise ValueError("mode must be 'auto', 'batch' or 'env'")
         if mode == "auto":
-            # one workgroup per network while a column-sweep boundary
-            # (chi^2)^(rows+1) stays within a few MB; cached environments,
-            # whose column absorptions spread over the whole GPU, beyond
-            mode = "env" if (chi * chi) ** (rows + 1) > AUTO_ENV_ENTRIES else "batch"
+            # one workgroup per network while a column-sweep boundary along
+            # the shorter side, (chi^2)^(min(rows, cols)+1), stays within a few
+            # MB; cached environments, whose column absorptions spread over the
+            # whole GPU, beyond
+            short = min(rows, cols)
+            mode = "env" if (chi * chi) ** (short + 1) > AUTO_ENV_ENTRIES else "batch"
         self.rows, self.cols, self.chi, self.d, self.mode = rows, cols, chi, d, mode
+        # cached environments sweep left to right; a lattice taller than wide
+        # is evaluated as its transpose (site (r, c) at (c, r), legs left <->
+        # up and right <-> down), so the boundary runs along the shorter side
+        self.transposed = mode == "env" and rows > cols
         self.n = rows * cols
         self.pairs = pairs(rows, cols)
         self.count = 1 + 2 * self.n + len(self.pairs)
@@ -69,12 +75,34 @@ class ObservableSet:
                                device=device)
             self.table = self.batch.prepare(self.networks())   # the buffers never move
         else:
-            subst = [[k] for k in range(self.n)] * 2 + [[i, j] for i, j in self.pairs]
-            self.env = EnvSet(rows, cols, chi * chi, networks=subst, precision=precision,
+            t = self.site_index
+            subst = ([[t(k)] for k in range(self.n)] * 2 +
+                     [[t(i), t(j)] for i, j in self.pairs])
+            er, ec = (cols, rows) if self.transposed else (rows, cols)
+            self.env = EnvSet(er, ec, chi * chi, networks=subst, precision=precision,
                               device=device)
-            _, sx, sz = self.E
-            repl = sx + sz + [sz[t] for ij in self.pairs for t in ij]
-            self.table = self.env.prepare(self.E[0], repl)
+            norm, sx, sz = self.E
+            base = [None] * self.n
+            for k in range(self.n):
+                base[t(k)] = norm[k]
+            repl = sx + sz + [sz[x] for ij in self.pairs for x in ij]
+            self.table = self.env.prepare(base, repl)
+
+    def site_index(self, k: int) -> int:
+        """Index of site k (row-major) in the lattice the networks run on."""
+        if not self.transposed:
+            return k
+        r, c = divmod(k, self.cols)
+        return c * self.rows + r
+
+    def leg_perm(self, k: int):
+        """For each bond leg of site k's double-layer tensor, the leg of the
+        state tensor it comes from (identity unless transposed)."""
+        r, c = divmod(k, self.cols)
+        present = [c > 0, r > 0, c < self.cols - 1, r < self.rows - 1]
+        axis = {leg: sum(present[:leg]) for leg in range(4) if present[leg]}
+        order = (1, 0, 3, 2) if self.transposed else (0, 1, 2, 3)   # left, up, right, down
+        return [axis[leg] for leg in order if present[leg]]
 
     def networks(self):
         """Site lists of every network, in the documented order."""
@@ -97,7 +125,8 @@ class ObservableSet:
             norm, ex, ez = self.E
             work = []
             for k, A in enumerate(peps):
-                work += [(A, None, norm[k]), (A, sx, ex[k]), (A, sz, ez[k])]
+                p = self.leg_perm(k)
+                work += [(A, None, norm[k], p), (A, sx, ex[k], p), (A, sz, ez[k], p)]
             self._dl, self._dl_key = tn_double_layer_prepare(work), key
         tn_double_layer(None, stream, prepared=self._dl)
         if self.env is not None:
@@ -128,47 +157,3 @@ class ObservableSet:
             if h is not None:
                 h.close()
 
-
-def main(argv=None):
-    """Time repeated observable evaluations of a random real PEPS (N(0,1)
-    tensors from a seed): python -m paper_1908_08553_amd.peps --rows 10
-    --cols 10 --chi 2 --mode env --reps 5."""
-    import argparse
-    import time
-
-    import numpy as np
-    import torch
-    p = argparse.ArgumentParser(description=main.__doc__)
-    p.add_argument("--rows", type=int, default=10)
-    p.add_argument("--cols", type=int, default=10)
-    p.add_argument("--chi", type=int, default=2)
-    p.add_argument("--mode", default="auto", choices=["auto", "batch", "env"])
-    p.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16x3"])
-    p.add_argument("--reps", type=int, default=5)
-    p.add_argument("--seed", type=int, default=1)
-    a = p.parse_args(argv)
-    rng = np.random.default_rng(a.seed)
-    peps = []
-    for r in range(a.rows):
-        for c in range(a.cols):
-            legs = (c > 0) + (r > 0) + (c < a.cols - 1) + (r < a.rows - 1)
-            peps.append(torch.as_tensor(rng.standard_normal((2,) + (a.chi,) * legs),
-                                        dtype=torch.float64).cuda())
-    sx = torch.tensor([[0.0, 0.5], [0.5, 0.0]], dtype=torch.float64).cuda()
-    sz = torch.tensor([[0.5, 0.0], [0.0, -0.5]], dtype=torch.float64).cuda()
-    obs = ObservableSet(a.rows, a.cols, a.chi, precision=a.precision, mode=a.mode)
-    out = obs.run(peps, sx, sz)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.reps):
-        out = obs.run(peps, sx, sz)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / a.reps
-    print(f"{a.rows}x{a.cols} chi={a.chi} mode={obs.mode} {a.precision}: {obs.count} networks, "
-          f"{1e3 * dt:.3f} ms per evaluation, log norm {out['results'][0].log_abs:.12f}, "
-          f"mean m^z {sum(out['mz']) / len(out['mz']):.6f}", flush=True)
-    obs.close()
-
-
-if __name__ == "__main__":
-    main()

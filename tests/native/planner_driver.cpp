@@ -198,6 +198,30 @@ void run_cuts(int r, int c, int D, const int32_t* h, const int32_t* v, long& pla
       prev = q.cut_legs;
     }
   }
+  // the full sweep's boundary legs after every step: every forward cut ends
+  // in them, every right environment and reverse step (the boundary of all
+  // sites after a step, as site environments and caps read it) too
+  {
+    std::vector<std::vector<int32_t>> legs;
+    if (tn::sweep_legs(g, legs, err) != TN_OK || legs.size() != static_cast<size_t>(total)) {
+      check(false, "sweep legs", r, c, D, 105);
+    } else {
+      for (int64_t k = 0; k + 1 < total; ++k) {
+        tn::Plan f;
+        if (tn::build_sweep_cut(g, 0, 0, k + 1, f, err) != TN_OK || f.cut_legs != legs[k])
+          check(false, "forward cut legs", r, c, D, 105);
+        const int rr = static_cast<int>((k + 1) % r), cc = static_cast<int>((k + 1) / r);
+        tn::Plan q;
+        if (rr == 0) {   // after a whole column: the right environment at that cut
+          if (cc < c && (tn::build_cut_plan(g, 1, 0, c - cc, q, err) != TN_OK || q.cut_legs != legs[k]))
+            check(false, "right environment legs", r, c, D, 105);
+        } else if (tn::build_rev_step(g, rr, cc, q, err) != TN_OK || q.cut_legs != legs[k]) {
+          // the reverse step at (rr, cc) ends in the boundary after (rr - 1, cc)
+          check(false, "reverse step legs vs sweep", r, c, D, 105);
+        }
+      }
+    }
+  }
   // a left cut ending at column cut q meets the right cut ending there
   for (int q = 1; q < c; ++q) {
     tn::Plan a, b;

@@ -145,6 +145,14 @@ def test_auto_mode_choice_and_agreement_8x8(tn):
     small = ObservableSet(6, 6, 2)
     assert small.mode == "batch"
     small.close()
+    # the shorter side decides: a 12 x 3 lattice sweeps 4^4-entry boundaries
+    # in the batch; a 9 x 8 one takes environments, transposed
+    tall = ObservableSet(12, 3, 2)
+    assert tall.mode == "batch"
+    tall.close()
+    big = ObservableSet(9, 8, 2)
+    assert big.mode == "env" and big.transposed
+    big.close()
     peps = [dev(A) for A in li.peps(8, 8, 2, 17)]
     auto = ObservableSet(8, 8, 2)
     assert auto.mode == "env"
@@ -159,3 +167,22 @@ def test_auto_mode_choice_and_agreement_8x8(tn):
     assert na.sign == nb.sign and abs(na.log_abs - nb.log_abs) <= 1e-12
     for key in ("mx", "mz", "czz"):
         np.testing.assert_allclose(a[key], b[key], rtol=0, atol=1e-12, err_msg=key)
+
+
+@pytest.mark.parametrize("rows,cols", [(7, 3), (6, 4)])
+def test_tall_lattice_environments_transposed(tn, rows, cols):
+    # environments sweep the transposed lattice (legs laid out by the
+    # double-layer kernel's leg permutation); observables against the oracle
+    from paper_1908_08553_amd.peps import ObservableSet
+    peps = li.peps(rows, cols, 2, rows * cols)
+    want = Q.expectation_values(peps, rows, cols, SX, SZ, P.COLSWEEP)
+    obs = ObservableSet(rows, cols, 2, precision="f64", mode="env")
+    assert obs.transposed
+    print(f"[gpu] env observables {rows}x{cols}, transposed", flush=True)
+    got = obs.run([dev(A) for A in peps], dev(SX), dev(SZ))
+    obs.close()
+    norm = got["results"][0]
+    assert norm.status == 0 and norm.sign == want["norm"].sign
+    assert abs(norm.log_abs - want["norm"].log_abs) <= 1e-12
+    for key in ("mx", "mz", "czz"):
+        np.testing.assert_allclose(got[key], want[key], rtol=0, atol=1e-11, err_msg=key)
