@@ -204,6 +204,7 @@ def batch_leg(tn, torch, n=512, seed=2024, reps=20):
     return {"lattices": n, "precision": "f32", "ms": 1e3 * dt,
             "contractions_per_s": n / dt, "gflops": flops / dt / 1e9,
             "flops_per_batch": flops, "tuned_threads": tuned["best"],
+            "tuned_split": tuned["split"],
             "tuning_ms": {str(k): v for k, v in tuned["ms"].items()},
             "sequential_ms": 1e3 * dt_seq, "sequential_contractions_per_s": n / dt_seq,
             "speedup_vs_sequential": dt_seq / dt, "bitwise_equal_to_single_step_launches": same,

@@ -199,20 +199,26 @@ tn_status tn_contract_grid_static(const tn_plan* plan, const double* const* site
                                   tn_result* out);
 
 /* ------------------------------------------------------------ batching
- * Many independent lattices contracted by one persistent launch (the paper's
- * observable evaluations need one full contraction per local quantity, §5).
- * Every plan must be a column-sweep plan (TN_ORDER_COLSWEEP, transposed or
- * not).  The batch copies the plans; the caller may free them after create.
+ * Many independent lattices contracted by one replayed launch graph (the
+ * paper's observable evaluations need one full contraction per local
+ * quantity, §5).  Every plan must be a column-sweep plan (TN_ORDER_COLSWEEP,
+ * transposed or not).  The batch copies the plans; the caller may free them
+ * after create.
  *
- * One launch contracts the whole batch: workgroup b sweeps the b-th costliest
- * lattice with all of its waves, so the dispatcher starts the largest first.
- * Staging and the batch kernel are captured once into a hipGraph at create
- * time and replayed by every tn_batch_run.                                 */
+ * The graph stages every site, then runs two paths side by side: the `split`
+ * costliest lattices advance in lock-step, one launch per sweep step, each
+ * step spread over as many workgroups as its size calls for; every other
+ * lattice is swept by one workgroup with all its waves, costliest first (one
+ * launch).  Both paths compute every output block with the same per-wave
+ * arithmetic, so results are bitwise independent of `threads` and `split`.
+ * Staging and both paths are captured once into a hipGraph at create time and
+ * replayed by every tn_batch_run.                                          */
 typedef struct tn_batch tn_batch;
 
 typedef struct {
-  int32_t threads;         /* workgroup size: 256, 512 or 1024 (0 = default)    */
-  int32_t reserved;        /* must be 0                                        */
+  int32_t threads;         /* workgroup size of the one-workgroup path: 256,   */
+                           /* 512 or 1024 (0 = default)                        */
+  int32_t split;           /* costliest lattices run in lock-step, 0..n        */
 } tn_batch_config;
 
 /* Workspace bytes a batch of these plans needs in `precision`.              */

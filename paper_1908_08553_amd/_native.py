@@ -73,7 +73,7 @@ lib.tn_set_option.argtypes = [C.c_int32, C.c_int64]
 lib.tn_profile_enable.restype = C.c_int32
 lib.tn_profile_enable.argtypes = [C.c_int32]
 class tn_batch_config(C.Structure):
-    _fields_ = [("threads", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("threads", C.c_int32), ("split", C.c_int32)]
 
 
 lib.tn_batch_workspace.restype = C.c_int32
@@ -371,9 +371,10 @@ def tn_batch_workspace(plans, precision) -> int:
 class Batch:
     """A tn_batch: device tables + captured launch graph for a fixed list of
     column-sweep plans.  `threads` of 0 uses the library default (see
-    tn_set_option)."""
+    tn_set_option); the `split` costliest lattices run in lock-step across
+    the GPU."""
 
-    def __init__(self, plans, precision="f32", threads=0, device="cuda"):
+    def __init__(self, plans, precision="f32", threads=0, device="cuda", split=0):
         import torch
         if isinstance(precision, str):
             precision = _PRECS[precision]
@@ -381,7 +382,7 @@ class Batch:
         self.precision = precision
         nbytes = tn_batch_workspace(self.plans, precision)
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
-        cfg = tn_batch_config(threads, 0)
+        cfg = tn_batch_config(threads, split)
         h = C.c_void_p()
         _check(lib.tn_batch_create(_plan_array(self.plans), len(self.plans), precision,
                                    C.byref(cfg), C.c_void_p(self.workspace.data_ptr()),

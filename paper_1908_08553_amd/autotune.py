@@ -1,12 +1,16 @@
-"""Autotuner for the batched persistent launch.
+"""Autotuner for the batched launch graph.
 
-The batched kernel's launch-shape knob is the workgroup size: how many waves
-sweep one lattice together (more waves finish a large lattice sooner; fewer
-leave room for more lattices per compute unit).  ``tune_batch`` times every candidate on the caller's own batch
-(replaying the captured graph), checks that every candidate returns
-bit-identical results, and caches the fastest under a signature of the
-workload (device name, precision, sorted lattice shapes and plan costs) in a
-JSON file: $TN_TUNE_CACHE, else ``tune_cache.json`` beside this module.
+Two launch-shape knobs: the workgroup size of the one-workgroup-per-lattice
+path (how many waves sweep one lattice together: more finish a large lattice
+sooner, fewer leave room for more lattices per compute unit), and the split,
+how many of the costliest lattices instead advance in lock-step with every
+step spread over the GPU (each lock-step launch costs a graph node; the
+costliest lattices otherwise set the batch's time on one compute unit).
+``tune_batch`` times every pair on the caller's own batch (replaying the
+captured graph), checks that every candidate returns bit-identical results,
+and caches the fastest under a signature of the workload (device name,
+precision, sorted lattice shapes and plan costs) in a JSON file:
+$TN_TUNE_CACHE, else ``tune_cache.json`` beside this module.
 ``tuned_batch`` builds a Batch with the cached choice (library defaults when
 the workload has not been tuned).
 """
@@ -20,6 +24,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 from . import _native as N
 
 CANDIDATES: List[int] = [256, 512, 1024]
+SPLITS: List[int] = [0, 16, 32, 64, 128, 256, 512]
 
 
 def cache_path() -> str:
@@ -55,27 +60,28 @@ def _save(d: Dict) -> None:
     os.replace(tmp, path)
 
 
-def tuned_config(plans, precision) -> Optional[int]:
+def tuned_config(plans, precision) -> Optional[Tuple[int, int]]:
     e = _load().get(signature(plans, precision))
-    return e["threads"] if e else None
+    return (e["threads"], e.get("split", 0)) if e else None
 
 
-def tune_batch(plans, site_lists, precision="f32", candidates=CANDIDATES, reps=5,
-               warmup=1, save=True) -> Dict:
-    """Time each workgroup-size candidate; returns
-    {"best": threads, "ms": {threads: median ms}, "signature": ...}."""
+def tune_batch(plans, site_lists, precision="f32", candidates=CANDIDATES, splits=SPLITS,
+               reps=5, warmup=1, save=True) -> Dict:
+    """Time each (workgroup size, split) pair; returns {"best": threads,
+    "split": split, "ms": {"threads/split": median ms}, "signature": ...}."""
     import torch
     timings = {}
     ref = None
-    for threads in candidates:
-        b = N.Batch(plans, precision, threads)
+    pairs = [(t, s) for s in splits if s <= len(plans) for t in candidates]
+    for threads, split in pairs:
+        b = N.Batch(plans, precision, threads, split=split)
         prep = b.prepare(site_lists)
         for _ in range(warmup):
             res = b.run(None, prepared=prep)
         if ref is None:
             ref = [(r.mantissa, r.exp2_sum) for r in res]
         elif [(r.mantissa, r.exp2_sum) for r in res] != ref:
-            raise RuntimeError(f"workgroup size {threads} changed the results")
+            raise RuntimeError(f"workgroup size {threads}, split {split} changed the results")
         ms = []
         for _ in range(reps):
             a = torch.cuda.Event(enable_timing=True)
@@ -86,17 +92,19 @@ def tune_batch(plans, site_lists, precision="f32", candidates=CANDIDATES, reps=5
             torch.cuda.synchronize()
             ms.append(a.elapsed_time(z))
         ms.sort()
-        timings[threads] = ms[len(ms) // 2]
+        timings[(threads, split)] = ms[len(ms) // 2]
         b.close()
     best = min(timings, key=timings.get)
     sig = signature(plans, precision)
     if save:
         d = _load()
-        d[sig] = {"threads": best, "ms": timings[best]}
+        d[sig] = {"threads": best[0], "split": best[1], "ms": timings[best]}
         _save(d)
-    return {"best": best, "ms": timings, "signature": sig}
+    return {"best": best[0], "split": best[1],
+            "ms": {f"{t}/{s}": v for (t, s), v in timings.items()}, "signature": sig}
 
 
 def tuned_batch(plans, precision="f32") -> N.Batch:
-    threads = tuned_config(plans, precision)
-    return N.Batch(plans, precision, threads or 0)
+    cfg = tuned_config(plans, precision)
+    threads, split = cfg if cfg else (0, 0)
+    return N.Batch(plans, precision, threads, split=split)

@@ -237,12 +237,14 @@ tn_status tn_batch_create(const tn_plan* const* plans, int32_t n, int32_t precis
     if (precision < TN_PREC_F64 || precision > TN_PREC_BF16X3) return fail(TN_EINVAL, "unknown precision");
     std::vector<const tn::Plan*> v;
     if (collect(plans, n, v) != TN_OK) return TN_EINVAL;
-    if (cfg && cfg->reserved != 0) return fail(TN_EINVAL, "tn_batch_config.reserved must be 0");
+    if (cfg && (cfg->split < 0 || cfg->split > n))
+      return fail(TN_EINVAL, "tn_batch_config.split must be 0..n");
     const int32_t threads = (cfg && cfg->threads) ? cfg->threads : g_batch_threads;
+    const int32_t split = cfg ? cfg->split : 0;
     std::string err;
     tn::BatchImpl* impl = nullptr;
     const tn_status s = tn::batch_create(v.data(), n, precision, threads, workspace, ws_bytes,
-                                         &impl, err);
+                                         &impl, err, split);
     if (s != TN_OK) return fail(s, err);
     *out = new tn_batch{impl};
     return TN_OK;

@@ -148,7 +148,7 @@ class ObservableSet:
                                      reps=reps)
         self.batch.close()
         self.batch = Batch([self.plan] * self.count, precision=self.precision,
-                           threads=report["best"], device=self.device)
+                           threads=report["best"], device=self.device, split=report["split"])
         self.table = self.batch.prepare(self.networks())
         return report
 

@@ -141,11 +141,50 @@ def test_autotuner_picks_a_config_and_caches_it(tn, tmp_path, monkeypatch):
     monkeypatch.setenv("TN_TUNE_CACHE", str(tmp_path / "cache.json"))
     mix = li.batch_mix(32, 11)
     plans, sites = build(tn, mix)
-    out = autotune.tune_batch(plans, sites, "f32", candidates=[256, 512], reps=2)
-    assert out["best"] in (256, 512)
-    assert autotune.tuned_config(plans, "f32") == out["best"]
+    out = autotune.tune_batch(plans, sites, "f32", candidates=[256, 512], splits=[0, 4, 32],
+                              reps=2)
+    assert out["best"] in (256, 512) and out["split"] in (0, 4, 32)
+    assert autotune.tuned_config(plans, "f32") == (out["best"], out["split"])
     b = autotune.tuned_batch(plans, "f32")
     assert len(b.run(sites)) == 32
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_lockstep_split_is_bitwise_the_same(tn, mix48, prec):
+    # the costliest lattices in lock-step over the GPU, the rest one
+    # workgroup each: every split (none, some, all) and workgroup size gives
+    # the same bits, and the split lattices match the oracle
+    mix, ref = mix48
+    plans, sites = build(tn, mix)
+    base = None
+    for threads, split in [(512, 0), (256, 5), (1024, 17), (512, 48)]:
+        print(f"[gpu] batch prec={prec} threads={threads} split={split}", flush=True)
+        b = tn.Batch(plans, prec, threads, split=split)
+        res = b.run(sites)
+        again = b.run(sites)
+        b.close()
+        bits = [(r.sign, r.mantissa, r.exp2_sum) for r in res]
+        assert bits == [(r.sign, r.mantissa, r.exp2_sum) for r in again]
+        if base is None:
+            base = bits
+        assert bits == base, (threads, split)
+    for got, want in zip(res, ref):
+        tol = 1e-12 if prec == "f64" else 1e-5 * max(1.0, abs(want.log_abs))
+        assert abs(got.log_abs - want.log_abs) <= tol
+
+
+def test_lockstep_nonfinite_lattice_is_flagged(tn):
+    mix = li.batch_mix(12, 3)
+    plans, sites = build(tn, mix)
+    costs = [p.info()["flops"] for p in plans]
+    worst = int(np.argmax(costs))
+    import torch
+    sites[worst][len(sites[worst]) // 2].view(-1)[0] = float("nan")
+    b = tn.Batch(plans, "f32", 512, split=3)
+    res = b.run(sites)
+    b.close()
+    assert res[worst].status == tn.TN_ENONFINITE
+    assert all(r.status == 0 for i, r in enumerate(res) if i != worst)
 
 
 def test_quadrant_plan_rejected(tn):
