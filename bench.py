@@ -526,6 +526,8 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
                     default=None, help="reduce two rocprofv3 --pmc runs (FETCH_SIZE, "
                     "WRITE_SIZE) with --calibrate to per-launch HBM bytes")
+    ap.add_argument("--chunk-schedule", type=int, default=None,
+                    help="TN_OPT_CHUNK_SCHEDULE for every contraction of the run")
     ap.add_argument("--command", default="", help="command line recorded in a summary")
     ap.add_argument("--workload", default="quadrant",
                     help="workload key of a traffic record (quadrant / sweep)")
@@ -546,6 +548,8 @@ def main():
     import torch
     import paper_1908_08553_amd as tn
     torch.cuda.set_device(0)
+    if args.chunk_schedule is not None:
+        tn.tn_set_option(tn.TN_OPT_CHUNK_SCHEDULE, args.chunk_schedule)
 
     calib = copy_calibration(torch) if args.calibrate else None
     head = run_leg(tn, torch, 12, 12, 4, "uniform", 0, tn.TN_ORDER_HEURISTIC, "f64",

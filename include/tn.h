@@ -479,13 +479,14 @@ tn_status tn_server_destroy(tn_server* server);
  *                        1 = pairs of bulk rows (same products in the same
  *                        order as single steps: bitwise-identical results);
  *                        0 = one launch per step.
- *   TN_OPT_CHUNK_SCHEDULE : workgroups of a column-chunk launch: 0 (default)
- *                        = one per tile of 16 boundary fibres, two or more
- *                        resident per CU; 1 = one persistent workgroup per CU
- *                        over a contiguous run of 128-byte tiles (32 FP32
- *                        fibres), the next tile's slice loaded during the
- *                        current one.  Both give results within the stated
- *                        tolerances (FP32 sums may differ in the last bits).  */
+ *   TN_OPT_CHUNK_SCHEDULE : kernel of the column chunks: 0 (default) = the
+ *                        chunk's intermediate results held in each
+ *                        wavefront's registers (suffix 1 or a multiple of
+ *                        16; other suffixes as with 1); 1 = the slice held in
+ *                        LDS by a workgroup and every step passing through
+ *                        LDS; 2 = as 0 with chunks of at most 3 rows in every
+ *                        precision.  All give results within the stated
+ *                        tolerances (sums may differ in the last bits).     */
 #define TN_OPT_KERNEL_IMPL 0
 #define TN_OPT_BATCH_THREADS 1
 #define TN_OPT_FUSE_STEPS 2

@@ -24,6 +24,11 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang"
                 "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wno-unused-result",
           "-I", INCLUDE, "-I", CSRC]
+# Per-source device flags.  The register-resident chunk kernel keeps its
+# whole slice in VGPRs: with MFMA results in the VGPR form the input and
+# output tiles of a step share one register file (the AGPR form puts them in
+# different files and doubles the footprint).
+EXTRA = {"absorb_chunk_reg.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def sources():
@@ -38,7 +43,8 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmds.append([HIPCC, *COMMON, "-x", "hip", *DEVICE_FLAGS, "-c", src, "-o", obj])
+        extra = EXTRA.get(os.path.basename(src), [])
+        cmds.append([HIPCC, *COMMON, "-x", "hip", *DEVICE_FLAGS, *extra, "-c", src, "-o", obj])
         objs.append(obj)
     jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1)), 16))
 

@@ -440,8 +440,8 @@ tn_status tn_set_option(int32_t option, int64_t value) {
     return TN_OK;
   }
   if (option == TN_OPT_CHUNK_SCHEDULE) {
-    if (value < 0 || value > 1) return fail(TN_EINVAL, "TN_OPT_CHUNK_SCHEDULE must be 0 or 1");
-    tn::set_chunk_persistent(static_cast<int32_t>(value));
+    if (value < 0 || value > 2) return fail(TN_EINVAL, "TN_OPT_CHUNK_SCHEDULE must be 0, 1 or 2");
+    tn::set_chunk_schedule(static_cast<int32_t>(value));
     return TN_OK;
   }
   if (option == TN_OPT_FUSE_STEPS) {

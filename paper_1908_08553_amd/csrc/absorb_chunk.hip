@@ -31,6 +31,7 @@
 #include <cstring>
 
 #include "absorb_device.hpp"
+#include "chunk_group.hpp"
 #include "kernels.hpp"
 
 namespace tn {
@@ -38,64 +39,24 @@ namespace {
 
 using namespace dev;
 
-constexpr int kChunkGroup = 4;
+constexpr int kChunkGroup = chunk::kGroup;
+typedef chunk::Group ChunkGroup;
+using chunk::GroupRef;
+using chunk::UnitRef;
 
-struct ChunkUnit {
-  const void* in;
-  void* out;
-  const void* S[kChunkMax];
-  const uint16_t* hi[kChunkMax];
-  const uint16_t* lo[kChunkMax];
-  int64_t pre, post;     // prefix of the first step, suffix of the last
-  int32_t k, k1, nl;     // steps; K of the first step (4 or 16); N of the last (4 or 16)
-  int32_t pad;
-  const int32_t* scale_slot;
-  int32_t* max_slot;
-};
-
-struct ChunkGroup {
-  ChunkUnit u[kChunkGroup];
-  uint32_t first[kChunkGroup + 1];   // unused entries hold the total tile count
-  int32_t n;
-  int32_t* flags;
-};
-
-// The launch's ChunkGroup is read in place from the kernel-argument segment
-// (constant address space, uniform: scalar loads), so dynamic unit and step
-// indices need no private copy of it.
-#define KARG __attribute__((address_space(4)))
-typedef const KARG ChunkGroup* GroupRef;
-typedef const KARG ChunkUnit& UnitRef;
-
-// Launch shapes: SP spectators per tile, at most KM rows per chunk, NW waves
-// per workgroup, PS = persistent workgroups.
-//  schedule 0: one workgroup per tile, two or more resident per CU (float:
-//    64 KiB slices of 64-byte row runs; tiles spread over the XCDs in
-//    contiguous runs so both halves of a 128-byte line go through one L2);
-//  schedule 1: one persistent workgroup per CU over a contiguous tile range
-//    (float: 128 KiB slices of 128-byte row runs), the next slice loaded into
-//    registers while the current one is contracted.
-template <typename T, int SCHED>
+// Launch shape: SP spectators per tile, at most KM rows per chunk, NW waves
+// per workgroup; one workgroup per tile, two or more resident per CU (float:
+// 64 KiB slices of 64-byte row runs; tiles spread over the XCDs in contiguous
+// runs so both halves of a 128-byte line go through one L2).
+template <typename T>
 struct Cfg;
 template <>
-struct Cfg<float, 0> {
+struct Cfg<float> {
   static constexpr int SP = 16, KM = 4, NW = 8;
-  static constexpr bool PS = false;
 };
 template <>
-struct Cfg<float, 1> {
-  static constexpr int SP = 32, KM = 4, NW = 16;
-  static constexpr bool PS = true;
-};
-template <>
-struct Cfg<double, 0> {
+struct Cfg<double> {
   static constexpr int SP = 16, KM = 3, NW = 8;
-  static constexpr bool PS = false;
-};
-template <>
-struct Cfg<double, 1> {
-  static constexpr int SP = 16, KM = 3, NW = 8;
-  static constexpr bool PS = true;
 };
 
 // XOR of the base-4 digits of x (x < 2^16), two bits.
@@ -324,16 +285,10 @@ struct Tile {
   int pad;
 };
 
-// Unit of group tile t.
-__device__ inline int unit_index(GroupRef g, uint32_t t) {
-  return static_cast<int>(t >= g->first[1]) + static_cast<int>(t >= g->first[2]) +
-         static_cast<int>(t >= g->first[3]);
-}
-
 template <int SP>
 __device__ inline Tile tile_at(GroupRef g, uint32_t t) {
   Tile x;
-  const int ui = unit_index(g, t);
+  const int ui = chunk::unit_index(g, t);
   UnitRef d = g->u[ui];
   const int64_t tile = t - g->first[ui];
   x.ui = ui;
@@ -554,11 +509,11 @@ __device__ inline void slice_store(UnitRef d, const Tile& x, const T* lds, T& mx
   }
 }
 
-template <typename T, int MODE, int SCHED>
-__global__ __launch_bounds__((64 * Cfg<T, SCHED>::NW)) __attribute__((amdgpu_waves_per_eu(4))) void
+template <typename T, int MODE>
+__global__ __launch_bounds__((64 * Cfg<T>::NW)) __attribute__((amdgpu_waves_per_eu(4))) void
 absorb_chunk(ChunkGroup arg) {
   (void)arg;   // read in place below
-  using C = Cfg<T, SCHED>;
+  using C = Cfg<T>;
   using V4 = typename std::conditional<MODE == M_F64, f64x4, f32x4>::type;
   constexpr int SP = C::SP, NW = C::NW, NTH = 64 * NW, KM = C::KM;
   constexpr int RMAX = 16 << (2 * (KM - 1));
@@ -568,146 +523,67 @@ absorb_chunk(ChunkGroup arg) {
   __shared__ __attribute__((aligned(16))) uint16_t sH[MODE == M_BF16X3 ? KM * 256 : 1];
   __shared__ __attribute__((aligned(16))) uint16_t sL[MODE == M_BF16X3 ? KM * 256 : 1];
   const GroupRef g = (GroupRef)__builtin_amdgcn_kernarg_segment_ptr();
-  const uint32_t total = g->first[kChunkGroup];
   V4 v[Regs<IT>::N];
 
-  if constexpr (!C::PS) {
-    // one tile; consecutive tiles on one XCD (workgroup b runs on XCD b % 8)
-    const uint32_t nb = gridDim.x;
-    const uint32_t t = (nb % 8 == 0) ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
-    const Tile x = tile_at<SP>(g, t);
-    UnitRef d = g->u[x.ui];
-    slice_load<T, V4, SP, NTH, IT>(d, x, v);   // in flight while the sites are staged
-    stage_sites<T, MODE, NTH>(d, sS, sH, sL);
-    slice_to_lds<T, V4, SP, NTH, IT>(d, x, v, lds);
-    __syncthreads();
-    slice_steps<T, MODE, SP, NW, KM, C::PS ? 2 : 8>(d, lds, sS, sH, sL);
-    T mx = 0;
-    int bad = 0;
-    slice_store<T, V4, SP, NTH, IT>(d, x, lds, mx, bad);
-    if (d.max_slot) reduce_and_publish<T, NW>(mx, bad, d.max_slot, g->flags);
-  } else {
-    const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
-    const uint32_t t0 = blockIdx.x * per;
-    const uint32_t t1 = min(total, t0 + per);
-    if (t0 >= t1) return;
-    Tile cur = tile_at<SP>(g, t0);
-    int staged = -1;
-    T mx = 0;
-    int bad = 0;
-    for (uint32_t t = t0; t < t1; ++t) {
-      UnitRef d = g->u[cur.ui];
-      if (staged != cur.ui) {
-        stage_sites<T, MODE, NTH>(d, sS, sH, sL);
-        staged = cur.ui;
-      }
-      if (t == t0) slice_load<T, V4, SP, NTH, IT>(d, cur, v);
-      slice_to_lds<T, V4, SP, NTH, IT>(d, cur, v, lds);
-      __syncthreads();
-      const bool more = t + 1 < t1;
-      Tile nxt = cur;
-      if (more) {
-        nxt = tile_at<SP>(g, t + 1);
-        slice_load<T, V4, SP, NTH, IT>(g->u[nxt.ui], nxt, v);
-      }
-      slice_steps<T, MODE, SP, NW, KM, C::PS ? 2 : 8>(d, lds, sS, sH, sL);
-      slice_store<T, V4, SP, NTH, IT>(d, cur, lds, mx, bad);
-      if (!more || nxt.ui != cur.ui) {
-        if (d.max_slot) reduce_and_publish<T, NW>(mx, bad, d.max_slot, g->flags);
-        mx = 0;
-        bad = 0;
-      }
-      __syncthreads();
-      cur = nxt;
-    }
-  }
+  // one tile; consecutive tiles on one XCD (workgroup b runs on XCD b % 8)
+  const uint32_t nb = gridDim.x;
+  const uint32_t t = (nb % 8 == 0) ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
+  const Tile x = tile_at<SP>(g, t);
+  UnitRef d = g->u[x.ui];
+  slice_load<T, V4, SP, NTH, IT>(d, x, v);   // in flight while the sites are staged
+  stage_sites<T, MODE, NTH>(d, sS, sH, sL);
+  slice_to_lds<T, V4, SP, NTH, IT>(d, x, v, lds);
+  __syncthreads();
+  slice_steps<T, MODE, SP, NW, KM, 8>(d, lds, sS, sH, sL);
+  T mx = 0;
+  int bad = 0;
+  slice_store<T, V4, SP, NTH, IT>(d, x, lds, mx, bad);
+  if (d.max_slot) reduce_and_publish<T, NW>(mx, bad, d.max_slot, g->flags);
 }
 
-// Launch schedule of the column-chunk kernels (see Cfg).
-int32_t g_chunk_sched = 0;
-
-// Resident workgroups per CU of one instantiation, times the CU count.
-template <typename T, int MODE, int SCHED>
-int32_t chunk_grid_cap() {
-  static int32_t cap = 0;
-  if (cap == 0) {
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, absorb_chunk<T, MODE, SCHED>,
-                                                     64 * Cfg<T, SCHED>::NW, 0) != hipSuccess)
-      return 256;
-    cap = std::max(1, cus * std::max(1, per_cu));
-  }
-  return cap;
-}
-
-template <typename T, int MODE, int SCHED>
+template <typename T, int MODE>
 hipError_t go_chunk(const ChunkArgs* a, int32_t n, const StagedArrays& st, DevState* state,
                     hipStream_t stream) {
-  using C = Cfg<T, SCHED>;
+  for (int32_t u = 0; u < n; ++u)
+    if (a[u].k < 2 || a[u].k > Cfg<T>::KM) return hipErrorInvalidValue;
   ChunkGroup g;
-  std::memset(&g, 0, sizeof(g));
-  g.n = n;
-  g.flags = &state->flags;
-  uint64_t total = 0;
-  for (int32_t u = 0; u < n; ++u) {
-    const ChunkArgs& x = a[u];
-    if (x.k < 2 || x.k > C::KM) return hipErrorInvalidValue;
-    ChunkUnit& c = g.u[u];
-    c.in = x.in;
-    c.out = x.out;
-    for (int j = 0; j < x.k; ++j) {
-      c.S[j] = (MODE == M_F64) ? static_cast<const void*>(st.s64 + x.s_off[j])
-                               : static_cast<const void*>(st.s32 + x.s_off[j]);
-      c.hi[j] = st.shi + x.s_off[j];
-      c.lo[j] = st.slo + x.s_off[j];
-    }
-    c.pre = x.pre;
-    c.post = x.post;
-    c.k = x.k;
-    c.k1 = x.k1;
-    c.nl = x.nl;
-    c.scale_slot = x.scale_slot;
-    c.max_slot = x.max_slot;
-    g.first[u] = static_cast<uint32_t>(total);
-    total += static_cast<uint64_t>(x.pre * x.post / C::SP);
-    if (total > static_cast<uint64_t>(INT_MAX)) return hipErrorInvalidValue;
-  }
-  for (int32_t u = n; u <= kChunkGroup; ++u) g.first[u] = static_cast<uint32_t>(total);
-  const uint32_t grid = static_cast<uint32_t>(
-      C::PS ? std::min<uint64_t>(total, chunk_grid_cap<T, MODE, SCHED>()) : total);
-  hipLaunchKernelGGL((absorb_chunk<T, MODE, SCHED>), dim3(grid), dim3(64 * C::NW), 0, stream, g);
+  if (!chunk::fill_group(g, a, n, st, &state->flags, MODE == M_F64)) return hipErrorInvalidValue;
+  const uint32_t grid = g.first[kChunkGroup];
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((absorb_chunk<T, MODE>), dim3(grid), dim3(64 * Cfg<T>::NW), 0, stream, g);
   return hipGetLastError();
 }
 
-template <int SCHED>
-hipError_t go_chunk_mode(const ChunkArgs* a, int32_t n, const StagedArrays& st, DevState* state,
-                         hipStream_t stream, const char** kname) {
+hipError_t go_chunk_lds(const ChunkArgs* a, int32_t n, const StagedArrays& st, DevState* state,
+                        hipStream_t stream, const char** kname) {
   if (a[0].type == EL_F64) {
     *kname = "absorb_chunk_f64";
-    return go_chunk<double, M_F64, SCHED>(a, n, st, state, stream);
+    return go_chunk<double, M_F64>(a, n, st, state, stream);
   }
   if (a[0].arith == AR_BF16X3) {
     *kname = "absorb_chunk_bf16x3";
-    return go_chunk<float, M_BF16X3, SCHED>(a, n, st, state, stream);
+    return go_chunk<float, M_BF16X3>(a, n, st, state, stream);
   }
   *kname = "absorb_chunk_f32";
-  return go_chunk<float, M_F32, SCHED>(a, n, st, state, stream);
+  return go_chunk<float, M_F32>(a, n, st, state, stream);
 }
+
+// Kernel of the column chunks: 0 = registers where the shape allows (rows of
+// up to 4 in FP32/BF16x3, 3 in FP64), 1 = LDS slices only, 2 = registers with
+// at most 3 rows in every precision.
+int32_t g_chunk_sched = 0;
 
 }  // namespace
 
 int32_t chunk_max_steps(int32_t type) {
-  if (type == EL_F64) return g_chunk_sched ? Cfg<double, 1>::KM : Cfg<double, 0>::KM;
-  return g_chunk_sched ? Cfg<float, 1>::KM : Cfg<float, 0>::KM;
+  if (g_chunk_sched == 2) return 3;
+  return type == EL_F64 ? Cfg<double>::KM : Cfg<float>::KM;
 }
 
-void set_chunk_persistent(int32_t on) { g_chunk_sched = on ? 1 : 0; }
+void set_chunk_schedule(int32_t s) { g_chunk_sched = s; }
 
 bool chunk_shape_ok(int32_t type, int64_t pre, int64_t post, int32_t k, int32_t k1, int32_t nl) {
-  const int64_t sp = type == EL_F64 ? (g_chunk_sched ? Cfg<double, 1>::SP : Cfg<double, 0>::SP)
-                                    : (g_chunk_sched ? Cfg<float, 1>::SP : Cfg<float, 0>::SP);
+  const int64_t sp = type == EL_F64 ? Cfg<double>::SP : Cfg<float>::SP;
   if (k < 2 || k > chunk_max_steps(type) || (k1 != 4 && k1 != 16) || (nl != 4 && nl != 16))
     return false;
   if (pre < 1 || post < 1) return false;
@@ -724,13 +600,24 @@ bool chunk_shape_ok(int32_t type, int64_t pre, int64_t post, int32_t k, int32_t 
 hipError_t launch_absorb_chunks(const ChunkArgs* a, int32_t n, const StagedArrays& st,
                                 DevState* state, hipStream_t stream, const char** kname) {
   if (n < 1 || n > kChunkGroup) return hipErrorInvalidValue;
+  ChunkArgs reg[kChunkGroup], lds[kChunkGroup];
+  int32_t nr = 0, nl = 0;
   for (int32_t u = 0; u < n; ++u) {
     if (a[u].type != a[0].type || a[u].arith != a[0].arith) return hipErrorInvalidValue;
     if (!chunk_shape_ok(a[u].type, a[u].pre, a[u].post, a[u].k, a[u].k1, a[u].nl))
       return hipErrorInvalidValue;
+    if (g_chunk_sched != 1 &&
+        chunk_reg_shape_ok(a[u].type, a[u].pre, a[u].post, a[u].k, a[u].k1, a[u].nl))
+      reg[nr++] = a[u];
+    else
+      lds[nl++] = a[u];
   }
-  return g_chunk_sched ? go_chunk_mode<1>(a, n, st, state, stream, kname)
-                       : go_chunk_mode<0>(a, n, st, state, stream, kname);
+  if (nr > 0) {
+    const hipError_t e = launch_absorb_chunks_reg(reg, nr, st, state, stream, kname);
+    if (e != hipSuccess) return e;
+  }
+  if (nl > 0) return go_chunk_lds(lds, nl, st, state, stream, kname);
+  return hipSuccess;
 }
 
 }  // namespace tn

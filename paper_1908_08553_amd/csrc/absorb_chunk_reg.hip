@@ -1,0 +1,590 @@
+// Column chunks held in registers: k consecutive rows (2 <= k <= 4) of one
+// column of a sweep applied to 16 boundary columns by one wavefront, the
+// intermediate results never leaving its registers (paper §4: the pairwise,
+// sequential contraction; only the memory schedule changes).
+//
+// Slice.  As in the LDS chunk kernel the chunk's input, for one spectator
+// fibre s = (p, q), is the run of rows
+//     row = kidx0 * M1 + m,   m = (h_1, ..., h_{k-1}) in base 4, M1 = 4^(k-1)
+// (kidx0 = (v, h_0), the first step's K index; h_0 only at the top edge).  A
+// wavefront takes 16 fibres as the 16 MFMA columns: 16 consecutive q of one p
+// when the suffix is a multiple of 16 (each row a 64- or 128-byte run), or 16
+// consecutive p when the suffix is 1 (each fibre's rows contiguous).
+//
+// Registers.  After step j the wavefront holds Y_j[t][r] in lane group g
+// (lane = 16 g + column): 4^(k-1) tiles t of 16 x 16, where the base-4 digits
+// of t are (h'_0, ..., h'_{j-1}, h_{j+1}, ..., h_{k-1}) (outputs so far, then
+// horizontal legs still to absorb), g = v'_j (the vertical leg just produced)
+// and r = h'_j.  Step j + 1 contracts (v'_j, h_{j+1}) = (g, kk) for kk = 0..3:
+// the four tiles that differ only in the digit h_{j+1} hold, in register a,
+// exactly the B operand of the product for h'_j = a, and the product's output
+// replaces them in place.  This layout is made by the row order of the A
+// operand (the site matrix): MFMA row i holds output n = 4 h' + v' with
+// (lane group, register) of row i equal to (v', h').  The f32 and bf16 16x16
+// MFMAs leave row i in (i / 4, i % 4), so A row i is n = 4 (i % 4) + i / 4;
+// the f64 MFMA leaves row i in (i % 4, i / 4), so A row i is n = i.  No lane
+// exchanges, no LDS, no barriers.
+//
+// K slots.  Lane group g supplies the K indices kidx = 4 g + kk (kk = 0..3)
+// of every step (kidx0 = g at the top edge, one MFMA); bf16x3 concatenates
+// [x_hi s_hi | x_hi s_lo] and [x_lo s_hi | 0] over those four indices in two
+// 16x16x32 MFMAs.
+//
+// Last step: 16 outputs (n = MFMA row) stored as 64-/128-byte row runs, or at
+// the bottom edge 4 outputs n' in the four registers of lane group 0 (f32: A
+// rows 0..3; f64: rows 0, 4, 8, 12), stored as one 16- or 32-byte vector per
+// fibre.
+//
+// Occupancy: 4^(k-1) * 4 accumulator values per lane (256 for a 4-row f32
+// chunk, one wavefront per SIMD; 64 values for 3 rows).  Workgroups are one
+// wavefront, so the phases (loads + first step, inner steps, stores) of the
+// wavefronts on one CU drift apart and overlap.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "absorb_device.hpp"
+#include "chunk_group.hpp"
+#include "kernels.hpp"
+
+namespace tn {
+namespace {
+
+using namespace dev;
+using chunk::GroupRef;
+using chunk::UnitRef;
+
+// Output n of MFMA row i, or -1 for a zero row.  NK: 0 = step feeding the
+// next one in registers; 1 = last step with 16 outputs; 2 = last step with 4.
+template <int MODE, int NK>
+__device__ inline int n_of_row(int i) {
+  if constexpr (NK == 0) return MODE == M_F64 ? i : 4 * (i & 3) + (i >> 2);
+  if constexpr (NK == 1) return i;
+  if constexpr (MODE == M_F64) return (i & 3) ? -1 : (i >> 2);
+  return i < 4 ? i : -1;
+}
+
+// A operands of one step for lane (c, g).  f32/f64: a[kk] = S[4g + kk][n(c)];
+// bf16x3: a0 = [hi(S) | lo(S)], a1 = [hi(S) | 0] over kidx = 4g .. 4g + 3.
+// ONE (one K index per lane group, kidx = g + 4 kq): a[0] = S[kidx][n(c)],
+// bf16x3 a0 = [hi, lo, hi, 0 ...] of that row.
+template <typename T, int MODE>
+struct ROps {
+  T a[4];
+  bf16x8 a0, a1;
+};
+
+template <typename T, int MODE, bool ONE, int NK>
+__device__ inline ROps<T, MODE> reg_ops(const void* Sv, const uint16_t* H, const uint16_t* L,
+                                        int c, int g, int kq = 0) {
+  constexpr int N = NK == 2 ? 4 : 16;
+  const int n = n_of_row<MODE, NK>(c);
+  auto kidx = [&](int kk) { return 4 * g + kk; };
+  ROps<T, MODE> o;
+  if constexpr (MODE == M_BF16X3) {
+    const __bf16 z = __builtin_bit_cast(__bf16, static_cast<uint16_t>(0));
+    auto hb = [&](int k) { return n >= 0 ? __builtin_bit_cast(__bf16, H[k * N + n]) : z; };
+    auto lb = [&](int k) { return n >= 0 ? __builtin_bit_cast(__bf16, L[k * N + n]) : z; };
+    if constexpr (ONE) {
+      const int k = g + 4 * kq;
+      o.a0 = bf16x8{hb(k), lb(k), hb(k), z, z, z, z, z};
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        o.a0[i] = hb(kidx(i));
+        o.a0[4 + i] = lb(kidx(i));
+        o.a1[i] = hb(kidx(i));
+        o.a1[4 + i] = z;
+      }
+    }
+  } else {
+    const T* S = static_cast<const T*>(Sv);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const bool live = n >= 0 && (!ONE || kk == 0);
+      o.a[kk] = live ? S[(ONE ? g + 4 * kq : kidx(kk)) * N + n] : T(0);
+    }
+  }
+  return o;
+}
+
+template <int MODE>
+using RV4 = typename std::conditional<MODE == M_F64, f64x4, f32x4>::type;
+
+// NG independent 16x16 products; xs[q][kk] is slot (g, kk) of product q.
+template <typename T, int MODE, bool TOPF, int NG>
+__device__ inline void reg_mma(const ROps<T, MODE>& o, const T (&xs)[NG][4],
+                               RV4<MODE> (&acc)[NG]) {
+  if constexpr (MODE == M_BF16X3) {
+    // operands built per product, right before its MFMAs (short live ranges)
+    const __bf16 z = __builtin_bit_cast(__bf16, static_cast<uint16_t>(0));
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      bf16x8 b0, b1;
+      if constexpr (TOPF) {
+        const __bf16 h = static_cast<__bf16>(xs[q][0]);
+        const __bf16 l = static_cast<__bf16>(xs[q][0] - static_cast<float>(h));
+        b0 = bf16x8{h, h, l, z, z, z, z, z};
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const __bf16 h = static_cast<__bf16>(xs[q][i]);
+          b0[i] = h;
+          b0[4 + i] = h;
+          b1[i] = static_cast<__bf16>(xs[q][i] - static_cast<float>(h));
+          b1[4 + i] = z;
+        }
+      }
+      acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a0, b0, f32x4{0.f, 0.f, 0.f, 0.f},
+                                                        0, 0, 0);
+      if constexpr (!TOPF)
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a1, b1, acc[q], 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NG; ++q) acc[q] = RV4<MODE>{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < (TOPF ? 1 : 4); ++kk)
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        if constexpr (MODE == M_F64)
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[kk], xs[q][kk], acc[q], 0, 0, 0);
+        else
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[kk], xs[q][kk], acc[q], 0, 0, 0);
+      }
+  }
+}
+
+// The ONE form accumulating into acc: acc += A x over the lane groups' K
+// indices.
+template <typename T, int MODE>
+__device__ inline RV4<MODE> reg_mma_one(const ROps<T, MODE>& o, T x, RV4<MODE> acc) {
+  if constexpr (MODE == M_BF16X3) {
+    const __bf16 z = __builtin_bit_cast(__bf16, static_cast<uint16_t>(0));
+    const __bf16 h = static_cast<__bf16>(x);
+    const __bf16 l = static_cast<__bf16>(x - static_cast<float>(h));
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a0, bf16x8{h, h, l, z, z, z, z, z}, acc,
+                                                   0, 0, 0);
+  } else if constexpr (MODE == M_F64) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[0], x, acc, 0, 0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[0], x, acc, 0, 0, 0);
+  }
+}
+
+// Step J >= 1 in place: tiles t = (P, kk, R) -> (P, a, R), the digit h_J at
+// stride S = 4^(k-1-J).
+template <typename T, int MODE, int K, int J>
+__device__ inline void reg_step(RV4<MODE> (&y)[1 << (2 * (K - 1))], const ROps<T, MODE>& o) {
+  constexpr int S = 1 << (2 * (K - 1 - J)), NP = 1 << (2 * (J - 1));
+#pragma unroll
+  for (int P = 0; P < NP; ++P)
+#pragma unroll
+    for (int R = 0; R < S; ++R) {
+      T xs[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) xs[a][kk] = y[P * 4 * S + kk * S + R][a];
+      RV4<MODE> acc[4];
+      reg_mma<T, MODE, false, 4>(o, xs, acc);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) y[P * 4 * S + a * S + R] = acc[a];
+    }
+}
+
+template <typename T, int MODE, int K, int J, bool P1>
+__device__ inline void reg_steps_from(RV4<MODE> (&y)[1 << (2 * (K - 1))], UnitRef d, int c, int g) {
+  if constexpr (J < K) {
+    constexpr int NK = J + 1 < K ? 0 : (P1 ? 2 : 1);
+    const ROps<T, MODE> o = reg_ops<T, MODE, false, NK>(d.S[J], d.hi[J], d.lo[J], c, g);
+    reg_step<T, MODE, K, J>(y, o);
+    reg_steps_from<T, MODE, K, J + 1, P1>(y, d, c, g);
+  }
+}
+
+template <typename T>
+__device__ inline void publish_wave(T mx, int bad, int32_t* max_slot, int32_t* flags) {
+  double m = static_cast<double>(mx);
+  for (int off = 32; off > 0; off >>= 1) {
+    m = fmax(m, __shfl_xor(m, off));
+    bad |= __shfl_xor(bad, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    const int32_t e = bad ? kExpBad : exp_of_d(m);
+    // the slot only grows during a launch: skip the atomic when it cannot
+    // raise it
+    if (e != kExpZero && e > __hip_atomic_load(max_slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(max_slot, e);
+    if (bad) atomicOr(flags, 1);
+  }
+}
+
+// LDS written by some lanes of the wavefront is read by others (and the other
+// way round): complete the wavefront's LDS operations and keep the compiler
+// from moving memory operations across.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Tile forms (HBM streams at 3.0-3.5 TB/s when the row runs one wavefront
+// instruction touches are 64 bytes long and at 4.7-5.0 TB/s when they are 128
+// bytes, whatever the instruction width or the occupancy: copy kernels of
+// both shapes on MI355X):
+//   FORM_DIRECT (8-byte entries, or a suffix of 16): 16 consecutive q of one
+//     p per one-wavefront workgroup; the registers are loaded and stored
+//     directly (row runs of 16 entries), step 0 with the K slots kidx0 =
+//     4 g + kk of all four MFMAs at once.
+//   FORM_PAIR (4-byte entries, suffix a multiple of 32): 32 consecutive q per
+//     two-wavefront workgroup, wavefront w taking q0 + 16 w + c; the slice
+//     goes through an LDS stage shared by the two, a quarter at a time, with
+//     128-byte row runs.
+//   FORM_BOTTOM (suffix 1): 16 consecutive p whose slices are one contiguous
+//     block, through an LDS stage private to the wavefront.
+// A quarter is QR = 4^k rows: step 0's K indices kidx0 = 4 kk + g (g = 0..3)
+// of quarter kk, or the whole slice at the top edge (kidx0 = g).  Staged
+// forms take step 0 one quarter at a time (one K index per lane group,
+// accumulating) while the next quarter's loads are in flight.
+enum { FORM_DIRECT = 0, FORM_PAIR = 1, FORM_BOTTOM = 2 };
+
+template <int K>
+constexpr int quarter_rows() { return 4 << (2 * (K - 1)); }
+// FORM_BOTTOM stage: fibre i, row j at i * pitch + j.
+template <typename T, int K>
+constexpr int bottom_pitch() { return quarter_rows<K>() + static_cast<int>(16 / sizeof(T)); }
+template <typename T, int K, int FORM>
+constexpr int stage_entries() {
+  return FORM == FORM_PAIR ? 36 * quarter_rows<K>()
+                           : FORM == FORM_BOTTOM ? 16 * bottom_pitch<T, K>() : 1;
+}
+// Quarters whose loads are in flight ahead of the one being multiplied.
+template <int K>
+constexpr int prefetch_depth() { return K >= 4 ? 1 : 2; }
+
+// Uniform 64-bit base plus a 32-bit per-lane byte offset: one VGPR of
+// address per lane for all of a wavefront's accesses.
+template <typename V>
+__device__ inline V ld_at(const void* ubase, uint32_t off) {
+  return *reinterpret_cast<const V*>(static_cast<const char*>(ubase) + static_cast<uint64_t>(off));
+}
+template <typename V>
+__device__ inline void st_at(void* ubase, uint32_t off, V v) {
+  *reinterpret_cast<V*>(static_cast<char*>(ubase) + static_cast<uint64_t>(off)) = v;
+}
+
+// FORM_DIRECT.
+template <typename T, int MODE, int K, bool TOP>
+__device__ inline void tile_direct(UnitRef d, int64_t tile, T& mx, int& bad) {
+  using V4 = RV4<MODE>;
+  constexpr int M1 = 1 << (2 * (K - 1)), KK0 = TOP ? 1 : 4;
+  constexpr int RIN = KK0 * quarter_rows<K>(), ROUT = 16 * M1;
+  constexpr int ES = sizeof(T);
+  const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+  const int32_t shift = shift_of(d.scale_slot);
+  const int64_t post = d.post, tq = post / 16, p = tile / tq, q0 = (tile - p * tq) * 16;
+  const int64_t rowb = post * ES;
+  // rows kidx0 M1 + t, kidx0 = (TOP ? g : 4 g) + kk
+  const char* src = static_cast<const char*>(d.in) + (p * RIN * post + q0) * ES;
+  const uint32_t lin = static_cast<uint32_t>((TOP ? g : 4 * g) * M1 * rowb + c * ES);
+  T x[M1][4];
+#pragma unroll
+  for (int kk = 0; kk < KK0; ++kk)
+#pragma unroll
+    for (int t = 0; t < M1; ++t) x[t][kk] = ld_at<T>(src + (kk * M1 + t) * rowb, lin);
+  if (shift) {
+#pragma unroll
+    for (int t = 0; t < M1; ++t)
+#pragma unroll
+      for (int kk = 0; kk < KK0; ++kk) x[t][kk] = static_cast<T>(ldexp(x[t][kk], -shift));
+  }
+  V4 y[M1];
+  {
+    const ROps<T, MODE> o = reg_ops<T, MODE, TOP, 0>(d.S[0], d.hi[0], d.lo[0], c, g);
+#pragma unroll
+    for (int t = 0; t < M1; t += 4) {
+      T xs[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) xs[q][kk] = kk < KK0 ? x[t + q][kk] : T(0);
+      V4 acc[4];
+      reg_mma<T, MODE, TOP, 4>(o, xs, acc);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) y[t + q] = acc[q];
+    }
+  }
+  reg_steps_from<T, MODE, K, 1, false>(y, d, c, g);
+  // register r of lane (c, g): output n = 4g + r (f32, bf16) or g + 4r (f64)
+  char* dst = static_cast<char*>(d.out) + (p * ROUT * post + q0) * ES;
+  const uint32_t lout = static_cast<uint32_t>((MODE == M_F64 ? g : 4 * g) * rowb + c * ES);
+#pragma unroll
+  for (int t = 0; t < M1; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const T v = static_cast<T>(y[t][r]);
+      st_at<T>(dst + (t * 16 + (MODE == M_F64 ? 4 * r : r)) * rowb, lout, v);
+      track(v, mx, bad);
+    }
+}
+
+// Step 0 of the staged forms, one quarter: y[t] += S_0^T x over lane group g's
+// K index of quarter kk.
+template <typename T, int MODE, int K>
+__device__ inline void step0_quarter(UnitRef d, RV4<MODE> (&y)[1 << (2 * (K - 1))],
+                                     T (&x)[1 << (2 * (K - 1))], int kk, int c, int g,
+                                     int32_t shift) {
+  constexpr int M1 = 1 << (2 * (K - 1));
+  if (shift) {
+#pragma unroll
+    for (int t = 0; t < M1; ++t) x[t] = static_cast<T>(ldexp(x[t], -shift));
+  }
+  const ROps<T, MODE> o = reg_ops<T, MODE, true, 0>(d.S[0], d.hi[0], d.lo[0], c, g, kk);
+#pragma unroll
+  for (int t = 0; t < M1; ++t) y[t] = reg_mma_one<T, MODE>(o, x[t], y[t]);
+}
+
+// FORM_PAIR (4-byte entries).  Stage rows of 32 fibres: input row j at
+// j * 32 + s + 16 (j / M1) (the quarter's four K blocks shifted apart, so the
+// lane groups of an MFMA-layout read fall on different banks), output row j
+// at (j / 4) * 144 + (j % 4) * 32 + s (rows 4 apart, one register of the four
+// lane groups, 16 banks apart).
+template <typename T, int MODE, int K, bool TOP>
+__device__ inline void tile_pair(UnitRef d, int64_t tile, T& mx, int& bad, T* stage) {
+  using V4 = RV4<MODE>;
+  static_assert(sizeof(T) == 4, "4-byte entries");
+  constexpr int M1 = 1 << (2 * (K - 1)), KK0 = TOP ? 1 : 4, QR = quarter_rows<K>();
+  constexpr int RIN = KK0 * QR, ROUT = 16 * M1, NIT = QR / 16, D = prefetch_depth<K>();
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, c = lane & 15, g = lane >> 4;
+  const int32_t shift = shift_of(d.scale_slot);
+  const int64_t post = d.post, tq = post / 32, run = tile / 2, p = run / tq;
+  const int64_t q0 = (run - p * tq) * 32, rowb = post * 4;
+  // vector it of thread tid: row 16 it + tid / 8, fibres 4 (tid % 8) .. + 3
+  const int jr = tid >> 3, s4 = 4 * (tid & 7);
+  const uint32_t lio = static_cast<uint32_t>(jr * rowb + s4 * 4);
+  const char* src = static_cast<const char*>(d.in) + (p * RIN * post + q0) * 4;
+  auto load_q = [&](int kk, V4 (&b)[NIT]) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) b[it] = ld_at<V4>(src + (kk * QR + 16 * it) * rowb, lio);
+  };
+  V4 y[M1];
+#pragma unroll
+  for (int t = 0; t < M1; ++t) y[t] = V4{0, 0, 0, 0};
+  V4 buf[D][NIT];
+#pragma unroll
+  for (int q = 0; q < D && q < KK0; ++q) load_q(q, buf[q]);
+#pragma unroll
+  for (int kk = 0; kk < KK0; ++kk) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int j = 16 * it + jr;
+      *reinterpret_cast<V4*>(stage + j * 32 + s4 + 16 * (j / M1)) = buf[kk % D][it];
+    }
+    __syncthreads();
+    if (kk + D < KK0) load_q(kk + D, buf[kk % D]);
+    T x[M1];
+#pragma unroll
+    for (int t = 0; t < M1; ++t) x[t] = stage[(g * M1 + t) * 32 + 16 * w + c + 16 * g];
+    __syncthreads();
+    step0_quarter<T, MODE, K>(d, y, x, kk, c, g, shift);
+  }
+  reg_steps_from<T, MODE, K, 1, false>(y, d, c, g);
+  // output rows t * 16 + n, a quarter (M1 / 4 tiles, QR rows) at a time;
+  // register r of lane (c, g) is n = 4g + r
+  char* dst = static_cast<char*>(d.out) + (p * ROUT * post + q0) * 4;
+  constexpr int TQ = M1 / 4;
+#pragma unroll
+  for (int qo = 0; qo < 4; ++qo) {
+#pragma unroll
+    for (int tt = 0; tt < TQ; ++tt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = tt * 16 + 4 * g + r;
+        stage[(j >> 2) * 144 + (j & 3) * 32 + 16 * w + c] = y[qo * TQ + tt][r];
+      }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int j = 16 * it + jr;
+      const V4 v = *reinterpret_cast<const V4*>(stage + (j >> 2) * 144 + (j & 3) * 32 + s4);
+      st_at<V4>(dst + (qo * QR + 16 * it) * rowb, lio, v);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) track(static_cast<T>(v[r]), mx, bad);
+    }
+    __syncthreads();
+  }
+}
+
+// FORM_BOTTOM.  Stage: fibre i, row j at i * pitch + j; the outputs (4 rows
+// per tile t, in the four registers of lane group 0) likewise.
+template <typename T, int MODE, int K, bool TOP>
+__device__ inline void tile_bottom(UnitRef d, int64_t tile, T& mx, int& bad, T* stage) {
+  using V4 = RV4<MODE>;
+  constexpr int M1 = 1 << (2 * (K - 1)), KK0 = TOP ? 1 : 4, QR = quarter_rows<K>();
+  constexpr int RIN = KK0 * QR, ROUT = 4 * M1, NIT = QR / 16, D = prefetch_depth<K>();
+  constexpr int PT = bottom_pitch<T, K>(), VQ = QR / 4;
+  static_assert(ROUT == QR, "the output fits the staging rows");
+  const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+  const int32_t shift = shift_of(d.scale_slot);
+  const T* src = static_cast<const T*>(d.in) + tile * 16 * RIN;
+  auto load_q = [&](int kk, V4 (&b)[NIT]) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int v = it * 64 + lane, i = v / VQ, j = 4 * (v - i * VQ);
+      b[it] = *reinterpret_cast<const V4*>(src + i * RIN + kk * QR + j);
+    }
+  };
+  V4 y[M1];
+#pragma unroll
+  for (int t = 0; t < M1; ++t) y[t] = V4{0, 0, 0, 0};
+  V4 buf[D][NIT];
+#pragma unroll
+  for (int q = 0; q < D && q < KK0; ++q) load_q(q, buf[q]);
+#pragma unroll
+  for (int kk = 0; kk < KK0; ++kk) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int v = it * 64 + lane, i = v / VQ, j = 4 * (v - i * VQ);
+      *reinterpret_cast<V4*>(stage + i * PT + j) = buf[kk % D][it];
+    }
+    wave_sync();
+    if (kk + D < KK0) load_q(kk + D, buf[kk % D]);
+    T x[M1];
+#pragma unroll
+    for (int t4 = 0; t4 < M1 / 4; ++t4) {
+      const V4 v = *reinterpret_cast<const V4*>(stage + c * PT + g * M1 + 4 * t4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[4 * t4 + e] = v[e];
+    }
+    wave_sync();
+    step0_quarter<T, MODE, K>(d, y, x, kk, c, g, shift);
+  }
+  reg_steps_from<T, MODE, K, 1, true>(y, d, c, g);
+  if (g == 0) {
+#pragma unroll
+    for (int t = 0; t < M1; ++t) *reinterpret_cast<V4*>(stage + c * PT + 4 * t) = y[t];
+  }
+  wave_sync();
+  T* dst = static_cast<T*>(d.out) + tile * 16 * ROUT;
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int v = it * 64 + lane, i = v / VQ, j = 4 * (v - i * VQ);
+    const V4 val = *reinterpret_cast<const V4*>(stage + i * PT + j);
+    *reinterpret_cast<V4*>(dst + i * ROUT + j) = val;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) track(static_cast<T>(val[r]), mx, bad);
+  }
+}
+
+template <typename T, int MODE, int K, bool TOP, int FORM>
+__global__ __launch_bounds__(FORM == FORM_PAIR ? 128 : 64) void absorb_chunk_reg(chunk::Group arg) {
+  (void)arg;   // read in place below
+  constexpr int NWG = FORM == FORM_PAIR ? 2 : 1;   // tiles (wavefronts) per workgroup
+  __shared__ __attribute__((aligned(16))) T stage[stage_entries<T, K, FORM>()];
+  const GroupRef g = (GroupRef)__builtin_amdgcn_kernarg_segment_ptr();
+  // consecutive workgroups' tiles on one XCD (workgroup b runs on XCD b % 8)
+  const uint32_t nb = gridDim.x;
+  const uint32_t b = (nb % 8 == 0) ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
+  const uint32_t t = b * NWG;   // first tile of the workgroup; units hold whole workgroups
+  if (t >= g->first[chunk::kGroup]) return;
+  const int ui = chunk::unit_index(g, t);
+  UnitRef d = g->u[ui];
+  const int64_t tile = t - g->first[ui];
+  T mx = 0;
+  int bad = 0;
+  if constexpr (FORM == FORM_DIRECT) tile_direct<T, MODE, K, TOP>(d, tile, mx, bad);
+  else if constexpr (FORM == FORM_PAIR) tile_pair<T, MODE, K, TOP>(d, tile, mx, bad, stage);
+  else tile_bottom<T, MODE, K, TOP>(d, tile, mx, bad, stage);
+  if (d.max_slot) publish_wave(mx, bad, d.max_slot, g->flags);
+}
+
+int form_of(const ChunkArgs& a) {
+  if (a.post == 1) return FORM_BOTTOM;
+  return (a.type != EL_F64 && a.post % 32 == 0) ? FORM_PAIR : FORM_DIRECT;
+}
+
+template <typename T, int MODE, int K, bool TOP>
+hipError_t go_reg(const chunk::Group& grp, int form, hipStream_t stream) {
+  const uint32_t tiles = grp.first[chunk::kGroup];
+  if (tiles == 0) return hipSuccess;
+  if (form == FORM_BOTTOM) {
+    hipLaunchKernelGGL((absorb_chunk_reg<T, MODE, K, TOP, FORM_BOTTOM>), dim3(tiles), dim3(64),
+                       0, stream, grp);
+  } else if (form == FORM_PAIR) {
+    if constexpr (sizeof(T) == 4) {
+      hipLaunchKernelGGL((absorb_chunk_reg<T, MODE, K, TOP, FORM_PAIR>), dim3(tiles / 2),
+                         dim3(128), 0, stream, grp);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else {
+    hipLaunchKernelGGL((absorb_chunk_reg<T, MODE, K, TOP, FORM_DIRECT>), dim3(tiles), dim3(64),
+                       0, stream, grp);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int MODE>
+hipError_t go_reg_k(const chunk::Group& grp, int k, bool top, int form, hipStream_t stream) {
+  if (k == 2) return top ? go_reg<T, MODE, 2, true>(grp, form, stream)
+                         : go_reg<T, MODE, 2, false>(grp, form, stream);
+  if (k == 3) return top ? go_reg<T, MODE, 3, true>(grp, form, stream)
+                         : go_reg<T, MODE, 3, false>(grp, form, stream);
+  if constexpr (MODE != M_F64) {
+    if (k == 4) return top ? go_reg<T, MODE, 4, true>(grp, form, stream)
+                           : go_reg<T, MODE, 4, false>(grp, form, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int32_t chunk_reg_max_steps(int32_t type) { return type == EL_F64 ? 3 : 4; }
+
+bool chunk_reg_shape_ok(int32_t type, int64_t pre, int64_t post, int32_t k, int32_t k1,
+                        int32_t nl) {
+  if (k < 2 || k > chunk_reg_max_steps(type) || (k1 != 4 && k1 != 16)) return false;
+  if (pre < 1 || post < 1 || pre > INT_MAX / post) return false;
+  if (post == 1) return nl == 4 && pre % 16 == 0;
+  // per-lane byte offsets within a slice are 32-bit
+  const int64_t es = type == EL_F64 ? 8 : 4;
+  const int64_t span = static_cast<int64_t>(16) << (2 * (k - 1));   // rows of a slice, N = 16
+  if (span * post * es >= (int64_t(1) << 31)) return false;
+  return nl == 16 && post % 16 == 0;
+}
+
+hipError_t launch_absorb_chunks_reg(const ChunkArgs* a, int32_t n, const StagedArrays& st,
+                                    DevState* state, hipStream_t stream, const char** kname) {
+  if (n < 1 || n > chunk::kGroup) return hipErrorInvalidValue;
+  const bool f64 = a[0].type == EL_F64, bf = !f64 && a[0].arith == AR_BF16X3;
+  *kname = f64 ? "absorb_chunk_reg_f64" : bf ? "absorb_chunk_reg_bf16x3" : "absorb_chunk_reg_f32";
+  bool done[chunk::kGroup] = {false, false, false, false};
+  // one launch per (rows, top edge, tile form) among the units
+  for (int32_t u = 0; u < n; ++u) {
+    if (done[u]) continue;
+    if (a[u].type != a[0].type || a[u].arith != a[0].arith ||
+        !chunk_reg_shape_ok(a[u].type, a[u].pre, a[u].post, a[u].k, a[u].k1, a[u].nl))
+      return hipErrorInvalidValue;
+    const bool top = a[u].k1 == 4;
+    const int form = form_of(a[u]);
+    ChunkArgs sel[chunk::kGroup];
+    int32_t ns = 0;
+    for (int32_t v = u; v < n; ++v)
+      if (!done[v] && a[v].k == a[u].k && (a[v].k1 == 4) == top && form_of(a[v]) == form &&
+          a[v].type == a[u].type && a[v].arith == a[u].arith &&
+          chunk_reg_shape_ok(a[v].type, a[v].pre, a[v].post, a[v].k, a[v].k1, a[v].nl)) {
+        sel[ns++] = a[v];
+        done[v] = true;
+      }
+    chunk::Group grp;
+    if (!chunk::fill_group(grp, sel, ns, st, &state->flags, f64)) return hipErrorInvalidValue;
+    const hipError_t e = f64  ? go_reg_k<double, M_F64>(grp, a[u].k, top, form, stream)
+                         : bf ? go_reg_k<float, M_BF16X3>(grp, a[u].k, top, form, stream)
+                              : go_reg_k<float, M_F32>(grp, a[u].k, top, form, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace tn

@@ -121,10 +121,19 @@ struct ChunkArgs {
   int32_t* max_slot;           // measured after the last step (nullable)
 };
 int32_t chunk_max_steps(int32_t type);
-void set_chunk_persistent(int32_t on);
+// 0 = register chunks where the shape allows, else LDS slices; 1 = LDS slices
+// only; 2 = register chunks of at most 3 rows (absorb_chunk_reg.hip)
+void set_chunk_schedule(int32_t s);
 bool chunk_shape_ok(int32_t type, int64_t pre, int64_t post, int32_t k, int32_t k1, int32_t nl);
 hipError_t launch_absorb_chunks(const ChunkArgs* a, int32_t n, const StagedArrays& st,
                                 DevState* state, hipStream_t stream, const char** kname);
+// The register-resident chunk kernel: suffix a multiple of 16 with N = 16 at
+// the last step, or suffix 1 with N = 4 (bottom edge) and 16 | prefix.
+int32_t chunk_reg_max_steps(int32_t type);
+bool chunk_reg_shape_ok(int32_t type, int64_t pre, int64_t post, int32_t k, int32_t k1,
+                        int32_t nl);
+hipError_t launch_absorb_chunks_reg(const ChunkArgs* a, int32_t n, const StagedArrays& st,
+                                    DevState* state, hipStream_t stream, const char** kname);
 
 // Kernel policy: 0 = matrix-core kernels where the shape allows, 1 = vector-ALU
 // kernels only (absorption and ring products).

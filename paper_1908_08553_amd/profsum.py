@@ -28,14 +28,17 @@ KERNELS = OrderedDict([
     ("ring_mfma_f32", (r"ring_mfma_f32_big|ring_mfma<float>",
                        ["paper_1908_08553_amd/csrc/ring_mfma.hip"])),
     ("ring_mfma_bf16x3", (r"ring_bf16x3_nt", ["paper_1908_08553_amd/csrc/ring_mfma.hip"])),
-    ("absorb_chunk_f64", (r"absorb_chunk<double, 1,",
+    ("absorb_chunk_f64", (r"absorb_chunk(_reg)?<double, 1,",
                           ["paper_1908_08553_amd/csrc/absorb_chunk.hip",
+                           "paper_1908_08553_amd/csrc/absorb_chunk_reg.hip",
                            "paper_1908_08553_amd/csrc/absorb_device.hpp"])),
-    ("absorb_chunk_f32", (r"absorb_chunk<float, 0,",
+    ("absorb_chunk_f32", (r"absorb_chunk(_reg)?<float, 0,",
                           ["paper_1908_08553_amd/csrc/absorb_chunk.hip",
+                           "paper_1908_08553_amd/csrc/absorb_chunk_reg.hip",
                            "paper_1908_08553_amd/csrc/absorb_device.hpp"])),
-    ("absorb_chunk_bf16x3", (r"absorb_chunk<float, 2,",
+    ("absorb_chunk_bf16x3", (r"absorb_chunk(_reg)?<float, 2,",
                              ["paper_1908_08553_amd/csrc/absorb_chunk.hip",
+                              "paper_1908_08553_amd/csrc/absorb_chunk_reg.hip",
                               "paper_1908_08553_amd/csrc/absorb_device.hpp"])),
 ])
 COPY_KERNEL = "__amd_rocclr_copyBuffer"

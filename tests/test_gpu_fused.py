@@ -8,7 +8,10 @@ not the launch structure).
 * Column chunks (TN_OPT_FUSE_STEPS = 2, the default): up to 4 rows (3 in
   FP64) on a slice held on chip, products in a different order; checked
   against the FP64 oracle at the stated tolerances and against the
-  transfer-matrix value of the Ising network."""
+  transfer-matrix value of the Ising network.  Two chunk kernels: the slice
+  in one wavefront's registers (TN_OPT_CHUNK_SCHEDULE 0, the default, where
+  the suffix is 1 or a multiple of 16; 2 = at most 3 rows) and the slice in
+  LDS (schedule 1, and the fallback for other suffixes)."""
 import numpy as np
 import pytest
 
@@ -50,6 +53,22 @@ def pair_launches(names):
 
 def chunk_launches(names):
     return sum(v for k, v in names.items() if k.startswith("absorb_chunk_"))
+
+
+def reg_launches(names):
+    return sum(v for k, v in names.items() if k.startswith("absorb_chunk_reg_"))
+
+
+def lds_launches(names):
+    return chunk_launches(names) - reg_launches(names)
+
+
+def run_sched(tn, sched, *args, **kw):
+    tn.tn_set_option(tn.TN_OPT_CHUNK_SCHEDULE, sched)
+    try:
+        return run(tn, *args, **kw)
+    finally:
+        tn.tn_set_option(tn.TN_OPT_CHUNK_SCHEDULE, 0)
 
 
 def close(got, ref, prec):
@@ -169,4 +188,67 @@ def test_chunks_thin_and_odd_lattices(tn, rows, cols, prec):
     ref = C.contract_grid(s, rows, cols, P.QUADRANT, 0, 0)
     for order in (P.COLSWEEP, P.HEURISTIC):
         got, _ = run(tn, s, rows, cols, order, prec, 2)
+        close(got, ref, prec)
+
+
+@pytest.mark.parametrize("sched", [1, 2])
+@pytest.mark.parametrize("order", [P.COLSWEEP, P.HEURISTIC])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "f64"])
+def test_chunk_schedules_12x12_d4_vs_oracle(tn, uniform12, oracle12, sched, order, prec):
+    got, names = run_sched(tn, sched, uniform12, 12, 12, order, prec, 2)
+    print(f"  sched {sched} {prec} order={order}: {got.log_abs!r} oracle {oracle12.log_abs!r}")
+    if sched == 1:
+        assert reg_launches(names) == 0 and lds_launches(names) > 0, names
+    else:
+        assert reg_launches(names) > 0, names
+        if order == P.COLSWEEP:   # suffixes 4^9, 4^6, 4^3 and 1: all register shapes
+            assert lds_launches(names) == 0, names
+    close(got, oracle12, prec)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "f64"])
+def test_register_chunks_take_the_sweep(tn, uniform12, prec):
+    # 12 rows: every chunk of the middle columns has suffix 4^8, 4^4 (or 4^9,
+    # 4^6, 4^3 in FP64) or 1 at the bottom edge, all register-kernel shapes
+    _, names = run(tn, uniform12, 12, 12, P.COLSWEEP, prec, 2)
+    assert reg_launches(names) == chunk_launches(names) > 0, names
+
+
+def test_register_and_lds_chunks_in_one_sweep(tn):
+    # 9 rows in FP32: rows 0-3 (suffix 4^5) in registers, rows 4-7 (suffix 4,
+    # the bottom row below) on the LDS kernel, row 8 alone
+    s = li.uniform(9, 7, 4, 163)
+    ref = C.contract_grid(s, 9, 7, P.QUADRANT, 0, 0)
+    got, names = run(tn, s, 9, 7, P.COLSWEEP, "f32", 2)
+    assert reg_launches(names) > 0 and lds_launches(names) > 0, names
+    close(got, ref, "f32")
+
+
+@pytest.mark.parametrize("sched", [0, 1, 2])
+def test_chunk_schedules_mixed_dims_and_ising(tn, mixed10, sched):
+    s, h, v, ref = mixed10
+    for order in (P.COLSWEEP, P.QUADRANT):
+        for prec in ("f64", "f32", "bf16x3"):
+            got, names = run_sched(tn, sched, s, 10, 10, order, prec, 2, hdim=h, vdim=v)
+            assert chunk_launches(names) > 0, names
+            close(got, ref, prec)
+    import os
+    gold = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "ising_logz.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                r, c, K, val = line.split()
+                gold[(int(r), int(c), float(K))] = float(val)
+    tm = 2 * gold[(13, 13, 0.44)]
+    got, _ = run_sched(tn, sched, li.ising_d4(13, 13, 0.44), 13, 13, P.COLSWEEP, "f64", 2)
+    assert got.sign == 1 and abs(got.log_abs - tm) <= 1e-12, (sched, got.log_abs, tm)
+
+
+@pytest.mark.parametrize("rows,cols", [(6, 12), (12, 6), (9, 7), (5, 13), (13, 4)])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "f64"])
+def test_chunk_schedule_2_thin_and_odd_lattices(tn, rows, cols, prec):
+    s = li.uniform(rows, cols, 4, 200 + rows * cols)
+    ref = C.contract_grid(s, rows, cols, P.QUADRANT, 0, 0)
+    for order in (P.COLSWEEP, P.HEURISTIC):
+        got, _ = run_sched(tn, 2, s, rows, cols, order, prec, 2)
         close(got, ref, prec)
