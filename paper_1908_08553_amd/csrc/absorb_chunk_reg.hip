@@ -65,10 +65,23 @@ __device__ inline int n_of_row(int i) {
   return i < 4 ? i : -1;
 }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// bf16 high and low parts of x0, x1 (round to nearest even, as one packed
+// conversion each): hi = [hi(x0) | hi(x1) << 16], lo likewise of x - hi.
+__device__ inline void split_bf16(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+  hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{x0, x1}, bf16x2));
+  const float h0 = __uint_as_float(hi << 16), h1 = __uint_as_float(hi & 0xffff0000u);
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{x0 - h0, x1 - h1}, bf16x2));
+}
+
 // A operands of one step for lane (c, g).  f32/f64: a[kk] = S[4g + kk][n(c)];
-// bf16x3: a0 = [hi(S) | lo(S)], a1 = [hi(S) | 0] over kidx = 4g .. 4g + 3.
-// ONE (one K index per lane group, kidx = g + 4 kq): a[0] = S[kidx][n(c)],
-// bf16x3 a0 = [hi, lo, hi, 0 ...] of that row.
+// bf16x3 against B = [hi(x) | lo(x)] over kidx = 4g .. 4g + 3: a0 = [hi(S) |
+// hi(S)], a1 = [lo(S) | 0] (the three products hi hi, hi lo, lo hi).  ONE (one
+// K index per lane group, kidx = g + 4 kq): a[0] = S[kidx][n(c)]; bf16x3 a0 =
+// [hi, hi, lo, 0 ...] against B = [hi(x), lo(x), hi(x), 0 ...].
 template <typename T, int MODE>
 struct ROps {
   T a[4];
@@ -88,13 +101,13 @@ __device__ inline ROps<T, MODE> reg_ops(const void* Sv, const uint16_t* H, const
     auto lb = [&](int k) { return n >= 0 ? __builtin_bit_cast(__bf16, L[k * N + n]) : z; };
     if constexpr (ONE) {
       const int k = g + 4 * kq;
-      o.a0 = bf16x8{hb(k), lb(k), hb(k), z, z, z, z, z};
+      o.a0 = bf16x8{hb(k), hb(k), lb(k), z, z, z, z, z};
     } else {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         o.a0[i] = hb(kidx(i));
-        o.a0[4 + i] = lb(kidx(i));
-        o.a1[i] = hb(kidx(i));
+        o.a0[4 + i] = hb(kidx(i));
+        o.a1[i] = lb(kidx(i));
         o.a1[4 + i] = z;
       }
     }
@@ -112,34 +125,67 @@ __device__ inline ROps<T, MODE> reg_ops(const void* Sv, const uint16_t* H, const
 template <int MODE>
 using RV4 = typename std::conditional<MODE == M_F64, f64x4, f32x4>::type;
 
+// The ONE form accumulating into acc: acc += A x over the lane groups' K
+// indices.
+template <typename T, int MODE>
+__device__ inline RV4<MODE> reg_mma_one(const ROps<T, MODE>& o, T x, RV4<MODE> acc) {
+  if constexpr (MODE == M_BF16X3) {
+    uint32_t h, l;
+    split_bf16(x, x, h, l);
+    // [hi, lo, hi, 0 ...]: word 0 = hi | lo << 16, word 1 = hi
+    const u32x4 w0 = {(h & 0xffffu) | (l << 16), h & 0xffffu, 0u, 0u};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a0, __builtin_bit_cast(bf16x8, w0), acc,
+                                                   0, 0, 0);
+  } else if constexpr (MODE == M_F64) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[0], x, acc, 0, 0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[0], x, acc, 0, 0, 0);
+  }
+}
+
+// Two ONE-form products (tiles with entries x0, x1) sharing the bf16 splits.
+template <typename T, int MODE>
+__device__ inline void reg_mma_one2(const ROps<T, MODE>& o, T x0, T x1, RV4<MODE>& acc0,
+                                    RV4<MODE>& acc1) {
+  if constexpr (MODE == M_BF16X3) {
+    uint32_t h, l;
+    split_bf16(x0, x1, h, l);
+    const u32x4 w0 = {(h & 0xffffu) | (l << 16), h & 0xffffu, 0u, 0u};
+    const u32x4 w1 = {(h >> 16) | (l & 0xffff0000u), h >> 16, 0u, 0u};
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a0, __builtin_bit_cast(bf16x8, w0), acc0,
+                                                   0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a0, __builtin_bit_cast(bf16x8, w1), acc1,
+                                                   0, 0, 0);
+  } else {
+    acc0 = reg_mma_one<T, MODE>(o, x0, acc0);
+    acc1 = reg_mma_one<T, MODE>(o, x1, acc1);
+  }
+}
+
 // NG independent 16x16 products; xs[q][kk] is slot (g, kk) of product q.
 template <typename T, int MODE, bool TOPF, int NG>
 __device__ inline void reg_mma(const ROps<T, MODE>& o, const T (&xs)[NG][4],
                                RV4<MODE> (&acc)[NG]) {
   if constexpr (MODE == M_BF16X3) {
-    // operands built per product, right before its MFMAs (short live ranges)
-    const __bf16 z = __builtin_bit_cast(__bf16, static_cast<uint16_t>(0));
+    // operands built per product, right before its MFMAs (short live ranges),
+    // two entries per conversion
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
-      bf16x8 b0, b1;
       if constexpr (TOPF) {
-        const __bf16 h = static_cast<__bf16>(xs[q][0]);
-        const __bf16 l = static_cast<__bf16>(xs[q][0] - static_cast<float>(h));
-        b0 = bf16x8{h, h, l, z, z, z, z, z};
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const __bf16 h = static_cast<__bf16>(xs[q][i]);
-          b0[i] = h;
-          b0[4 + i] = h;
-          b1[i] = static_cast<__bf16>(xs[q][i] - static_cast<float>(h));
-          b1[4 + i] = z;
+        if (q % 2 == 0) {
+          acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+          acc[q + 1] = f32x4{0.f, 0.f, 0.f, 0.f};
+          reg_mma_one2<T, MODE>(o, xs[q][0], xs[q + 1][0], acc[q], acc[q + 1]);
         }
+      } else {
+        uint32_t h01, l01, h23, l23;
+        split_bf16(xs[q][0], xs[q][1], h01, l01);
+        split_bf16(xs[q][2], xs[q][3], h23, l23);
+        const bf16x8 b = __builtin_bit_cast(bf16x8, u32x4{h01, h23, l01, l23});
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a0, b, f32x4{0.f, 0.f, 0.f, 0.f}, 0,
+                                                          0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a1, b, acc[q], 0, 0, 0);
       }
-      acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a0, b0, f32x4{0.f, 0.f, 0.f, 0.f},
-                                                        0, 0, 0);
-      if constexpr (!TOPF)
-        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a1, b1, acc[q], 0, 0, 0);
     }
   } else {
 #pragma unroll
@@ -153,23 +199,6 @@ __device__ inline void reg_mma(const ROps<T, MODE>& o, const T (&xs)[NG][4],
         else
           acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[kk], xs[q][kk], acc[q], 0, 0, 0);
       }
-  }
-}
-
-// The ONE form accumulating into acc: acc += A x over the lane groups' K
-// indices.
-template <typename T, int MODE>
-__device__ inline RV4<MODE> reg_mma_one(const ROps<T, MODE>& o, T x, RV4<MODE> acc) {
-  if constexpr (MODE == M_BF16X3) {
-    const __bf16 z = __builtin_bit_cast(__bf16, static_cast<uint16_t>(0));
-    const __bf16 h = static_cast<__bf16>(x);
-    const __bf16 l = static_cast<__bf16>(x - static_cast<float>(h));
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a0, bf16x8{h, h, l, z, z, z, z, z}, acc,
-                                                   0, 0, 0);
-  } else if constexpr (MODE == M_F64) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(o.a[0], x, acc, 0, 0, 0);
-  } else {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(o.a[0], x, acc, 0, 0, 0);
   }
 }
 
@@ -221,14 +250,6 @@ __device__ inline void publish_wave(T mx, int bad, int32_t* max_slot, int32_t* f
   }
 }
 
-// LDS written by some lanes of the wavefront is read by others (and the other
-// way round): complete the wavefront's LDS operations and keep the compiler
-// from moving memory operations across.
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
 // Tile forms (HBM streams at 3.0-3.5 TB/s when the row runs one wavefront
 // instruction touches are 64 bytes long and at 4.7-5.0 TB/s when they are 128
 // bytes, whatever the instruction width or the occupancy: copy kernels of
@@ -246,7 +267,7 @@ __device__ inline void wave_sync() {
 // A quarter is QR = 4^k rows: step 0's K indices kidx0 = 4 kk + g (g = 0..3)
 // of quarter kk, or the whole slice at the top edge (kidx0 = g).  Staged
 // forms take step 0 one quarter at a time (one K index per lane group,
-// accumulating) while the next quarter's loads are in flight.
+// accumulating) while the next two quarters' loads are in flight.
 enum { FORM_DIRECT = 0, FORM_PAIR = 1, FORM_BOTTOM = 2 };
 
 template <int K>
@@ -256,12 +277,9 @@ template <typename T, int K>
 constexpr int bottom_pitch() { return quarter_rows<K>() + static_cast<int>(16 / sizeof(T)); }
 template <typename T, int K, int FORM>
 constexpr int stage_entries() {
-  return FORM == FORM_PAIR ? 36 * quarter_rows<K>()
-                           : FORM == FORM_BOTTOM ? 16 * bottom_pitch<T, K>() : 1;
+  return FORM == FORM_PAIR ? 2 * (32 * quarter_rows<K>() + 64)
+                           : FORM == FORM_BOTTOM ? 2 * 16 * bottom_pitch<T, K>() : 1;
 }
-// Quarters whose loads are in flight ahead of the one being multiplied.
-template <int K>
-constexpr int prefetch_depth() { return K >= 4 ? 1 : 2; }
 
 // Uniform 64-bit base plus a 32-bit per-lane byte offset: one VGPR of
 // address per lane for all of a wavefront's accesses.
@@ -330,69 +348,115 @@ __device__ inline void tile_direct(UnitRef d, int64_t tile, T& mx, int& bad) {
 }
 
 // Step 0 of the staged forms, one quarter: y[t] += S_0^T x over lane group g's
-// K index of quarter kk.
+// K index of the quarter (operands o of that quarter).
 template <typename T, int MODE, int K>
-__device__ inline void step0_quarter(UnitRef d, RV4<MODE> (&y)[1 << (2 * (K - 1))],
-                                     T (&x)[1 << (2 * (K - 1))], int kk, int c, int g,
-                                     int32_t shift) {
+__device__ inline void step0_quarter(const ROps<T, MODE>& o, RV4<MODE> (&y)[1 << (2 * (K - 1))],
+                                     T (&x)[1 << (2 * (K - 1))], int32_t shift) {
   constexpr int M1 = 1 << (2 * (K - 1));
   if (shift) {
 #pragma unroll
     for (int t = 0; t < M1; ++t) x[t] = static_cast<T>(ldexp(x[t], -shift));
   }
-  const ROps<T, MODE> o = reg_ops<T, MODE, true, 0>(d.S[0], d.hi[0], d.lo[0], c, g, kk);
 #pragma unroll
-  for (int t = 0; t < M1; ++t) y[t] = reg_mma_one<T, MODE>(o, x[t], y[t]);
+  for (int t = 0; t < M1; t += 2) reg_mma_one2<T, MODE>(o, x[t], x[t + 1], y[t], y[t + 1]);
 }
 
-// FORM_PAIR (4-byte entries).  Stage rows of 32 fibres: input row j at
-// j * 32 + s + 16 (j / M1) (the quarter's four K blocks shifted apart, so the
-// lane groups of an MFMA-layout read fall on different banks), output row j
-// at (j / 4) * 144 + (j % 4) * 32 + s (rows 4 apart, one register of the four
-// lane groups, 16 banks apart).
+// Asynchronous fills of the stage: global_load_lds with 16 bytes per lane
+// writes lane L's 16 bytes to LDS at (uniform base) + 16 L, without passing
+// through registers, so two quarters can be in flight while a third is
+// multiplied.  The compiler does not see these writes: the waits below are
+// explicit (s_waitcnt on the number of fills issued after the ones needed;
+// fills complete in issue order), followed by a compiler memory barrier.  The
+// workgroup barrier is the bare s_barrier: the fence of __syncthreads would
+// also wait for the fills still in flight.
+typedef __attribute__((address_space(3))) void* LdsPtr;
+__device__ inline void lds_fill16(const void* g, void* lds) {
+#if __HIP_DEVICE_COMPILE__
+  __builtin_amdgcn_global_load_lds(g, (LdsPtr)(lds), 16, 0, 0);
+#else
+  (void)g;
+  (void)lds;
+#endif
+}
+// s_waitcnt immediates: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8;
+// the fields not waited on hold their maxima.
+template <int N>
+__device__ inline void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | (((N >> 4) & 3) << 14));
+  asm volatile("" ::: "memory");
+}
+__device__ inline void wait_lds() {
+  __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));
+  asm volatile("" ::: "memory");
+}
+__device__ inline void wg_barrier() {
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// FORM_PAIR (4-byte entries).  Two input buffers of rows of 32 fibres: row j
+// at j * 32 + s + 16 (j / SB), SB = max(M1, 8) (the quarter's K blocks
+// shifted apart so the lane groups of an MFMA-layout read fall on different
+// banks; a fill covers 8 rows); output row j at (j / 4) * 144 + (j % 4) * 32
+// + s (rows 4 apart, one register of the four lane groups, 16 banks apart).
 template <typename T, int MODE, int K, bool TOP>
 __device__ inline void tile_pair(UnitRef d, int64_t tile, T& mx, int& bad, T* stage) {
   using V4 = RV4<MODE>;
   static_assert(sizeof(T) == 4, "4-byte entries");
   constexpr int M1 = 1 << (2 * (K - 1)), KK0 = TOP ? 1 : 4, QR = quarter_rows<K>();
-  constexpr int RIN = KK0 * QR, ROUT = 16 * M1, NIT = QR / 16, D = prefetch_depth<K>();
+  constexpr int RIN = KK0 * QR, ROUT = 16 * M1, NIT = QR / 16;
+  constexpr int SB = M1 >= 8 ? M1 : 8, IB = 32 * QR + 64;
+  constexpr int LPW = QR / 16;   // 1 KiB fills per wavefront and quarter (8 rows each)
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, c = lane & 15, g = lane >> 4;
   const int32_t shift = shift_of(d.scale_slot);
   const int64_t post = d.post, tq = post / 32, run = tile / 2, p = run / tq;
   const int64_t q0 = (run - p * tq) * 32, rowb = post * 4;
-  // vector it of thread tid: row 16 it + tid / 8, fibres 4 (tid % 8) .. + 3
-  const int jr = tid >> 3, s4 = 4 * (tid & 7);
-  const uint32_t lio = static_cast<uint32_t>(jr * rowb + s4 * 4);
   const char* src = static_cast<const char*>(d.in) + (p * RIN * post + q0) * 4;
-  auto load_q = [&](int kk, V4 (&b)[NIT]) {
+  // step 0's operands for every quarter, complete before the first fill (a
+  // later wait for them would also wait for the fills issued before them)
+  ROps<T, MODE> o0[KK0];
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) b[it] = ld_at<V4>(src + (kk * QR + 16 * it) * rowb, lio);
+  for (int kk = 0; kk < KK0; ++kk) o0[kk] = reg_ops<T, MODE, true, 0>(d.S[0], d.hi[0], d.lo[0], c, g, kk);
+  wait_vm<0>();
+  // fill i of wavefront w: rows j0 = 8 (2i + w) .. j0 + 7; lane L takes row
+  // j0 + L / 8, fibres 4 (L % 8) .. + 3
+  const uint32_t lfill = static_cast<uint32_t>((lane >> 3) * rowb + 16 * (lane & 7));
+  auto fill_q = [&](int kk, T* buf) {
+#pragma unroll
+    for (int i = 0; i < LPW; ++i) {
+      const int j0 = 8 * (2 * i + w);
+      lds_fill16(src + (kk * QR + j0) * rowb + lfill, buf + j0 * 32 + 16 * (j0 / SB));
+    }
   };
   V4 y[M1];
 #pragma unroll
   for (int t = 0; t < M1; ++t) y[t] = V4{0, 0, 0, 0};
-  V4 buf[D][NIT];
-#pragma unroll
-  for (int q = 0; q < D && q < KK0; ++q) load_q(q, buf[q]);
+  fill_q(0, stage);
+  if (KK0 > 1) fill_q(1, stage + IB);
 #pragma unroll
   for (int kk = 0; kk < KK0; ++kk) {
-#pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-      const int j = 16 * it + jr;
-      *reinterpret_cast<V4*>(stage + j * 32 + s4 + 16 * (j / M1)) = buf[kk % D][it];
-    }
-    __syncthreads();
-    if (kk + D < KK0) load_q(kk + D, buf[kk % D]);
+    T* buf = stage + (kk & 1) * IB;
+    if (kk + 1 < KK0) wait_vm<LPW>();
+    else wait_vm<0>();
+    wg_barrier();
     T x[M1];
 #pragma unroll
-    for (int t = 0; t < M1; ++t) x[t] = stage[(g * M1 + t) * 32 + 16 * w + c + 16 * g];
-    __syncthreads();
-    step0_quarter<T, MODE, K>(d, y, x, kk, c, g, shift);
+    for (int t = 0; t < M1; ++t) {
+      const int j = g * M1 + t;
+      x[t] = buf[j * 32 + 16 * w + c + 16 * (j / SB)];
+    }
+    wait_lds();
+    wg_barrier();
+    if (kk + 2 < KK0) fill_q(kk + 2, buf);
+    step0_quarter<T, MODE, K>(o0[kk], y, x, shift);
   }
   reg_steps_from<T, MODE, K, 1, false>(y, d, c, g);
   // output rows t * 16 + n, a quarter (M1 / 4 tiles, QR rows) at a time;
   // register r of lane (c, g) is n = 4g + r
   char* dst = static_cast<char*>(d.out) + (p * ROUT * post + q0) * 4;
+  const int jr = tid >> 3, s4 = 4 * (tid & 7);
+  const uint32_t lio = static_cast<uint32_t>(jr * rowb + s4 * 4);
   constexpr int TQ = M1 / 4;
 #pragma unroll
   for (int qo = 0; qo < 4; ++qo) {
@@ -403,7 +467,8 @@ __device__ inline void tile_pair(UnitRef d, int64_t tile, T& mx, int& bad, T* st
         const int j = tt * 16 + 4 * g + r;
         stage[(j >> 2) * 144 + (j & 3) * 32 + 16 * w + c] = y[qo * TQ + tt][r];
       }
-    __syncthreads();
+    wait_lds();
+    wg_barrier();
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       const int j = 16 * it + jr;
@@ -412,60 +477,70 @@ __device__ inline void tile_pair(UnitRef d, int64_t tile, T& mx, int& bad, T* st
 #pragma unroll
       for (int r = 0; r < 4; ++r) track(static_cast<T>(v[r]), mx, bad);
     }
-    __syncthreads();
+    wait_lds();
+    wg_barrier();
   }
 }
 
-// FORM_BOTTOM.  Stage: fibre i, row j at i * pitch + j; the outputs (4 rows
-// per tile t, in the four registers of lane group 0) likewise.
+// FORM_BOTTOM.  Two input buffers, fibre i's rows at i * pitch + j (each
+// fibre's quarter filled by its own fills, or by the first QR ES / 16 lanes
+// of one when it is under 1 KiB); the outputs (4 rows per tile t, in the four
+// registers of lane group 0) through the first buffer.
 template <typename T, int MODE, int K, bool TOP>
 __device__ inline void tile_bottom(UnitRef d, int64_t tile, T& mx, int& bad, T* stage) {
   using V4 = RV4<MODE>;
   constexpr int M1 = 1 << (2 * (K - 1)), KK0 = TOP ? 1 : 4, QR = quarter_rows<K>();
-  constexpr int RIN = KK0 * QR, ROUT = 4 * M1, NIT = QR / 16, D = prefetch_depth<K>();
-  constexpr int PT = bottom_pitch<T, K>(), VQ = QR / 4;
+  constexpr int RIN = KK0 * QR, ROUT = 4 * M1, NIT = QR / 16, ES = sizeof(T);
+  constexpr int PT = bottom_pitch<T, K>(), VQ = QR / 4, BB = 16 * PT;
+  constexpr int FB = QR * ES;                             // bytes of one fibre's quarter
+  constexpr int PIECES = FB >= 1024 ? FB / 1024 : 1;      // fills per fibre
+  constexpr int LANES = FB >= 1024 ? 64 : FB / 16;        // active lanes of a fill
+  constexpr int LPW = 16 * PIECES;                        // fills per quarter
   static_assert(ROUT == QR, "the output fits the staging rows");
+  static_assert(LPW < 64, "vmcnt range");
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
   const int32_t shift = shift_of(d.scale_slot);
-  const T* src = static_cast<const T*>(d.in) + tile * 16 * RIN;
-  auto load_q = [&](int kk, V4 (&b)[NIT]) {
+  const char* src = static_cast<const char*>(d.in) + tile * 16 * RIN * ES;
+  ROps<T, MODE> o0[KK0];
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-      const int v = it * 64 + lane, i = v / VQ, j = 4 * (v - i * VQ);
-      b[it] = *reinterpret_cast<const V4*>(src + i * RIN + kk * QR + j);
-    }
+  for (int kk = 0; kk < KK0; ++kk) o0[kk] = reg_ops<T, MODE, true, 0>(d.S[0], d.hi[0], d.lo[0], c, g, kk);
+  wait_vm<0>();
+  auto fill_q = [&](int kk, T* buf) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+#pragma unroll
+      for (int pc = 0; pc < PIECES; ++pc)
+        if (lane < LANES)
+          lds_fill16(src + (i * RIN + kk * QR) * ES + pc * 1024 + 16 * lane,
+                     buf + i * PT + pc * (1024 / ES));
   };
   V4 y[M1];
 #pragma unroll
   for (int t = 0; t < M1; ++t) y[t] = V4{0, 0, 0, 0};
-  V4 buf[D][NIT];
-#pragma unroll
-  for (int q = 0; q < D && q < KK0; ++q) load_q(q, buf[q]);
+  fill_q(0, stage);
+  if (KK0 > 1) fill_q(1, stage + BB);
 #pragma unroll
   for (int kk = 0; kk < KK0; ++kk) {
-#pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-      const int v = it * 64 + lane, i = v / VQ, j = 4 * (v - i * VQ);
-      *reinterpret_cast<V4*>(stage + i * PT + j) = buf[kk % D][it];
-    }
-    wave_sync();
-    if (kk + D < KK0) load_q(kk + D, buf[kk % D]);
+    T* buf = stage + (kk & 1) * BB;
+    if (kk + 1 < KK0) wait_vm<LPW>();
+    else wait_vm<0>();
     T x[M1];
 #pragma unroll
     for (int t4 = 0; t4 < M1 / 4; ++t4) {
-      const V4 v = *reinterpret_cast<const V4*>(stage + c * PT + g * M1 + 4 * t4);
+      const V4 v = *reinterpret_cast<const V4*>(buf + c * PT + g * M1 + 4 * t4);
 #pragma unroll
       for (int e = 0; e < 4; ++e) x[4 * t4 + e] = v[e];
     }
-    wave_sync();
-    step0_quarter<T, MODE, K>(d, y, x, kk, c, g, shift);
+    wait_lds();
+    if (kk + 2 < KK0) fill_q(kk + 2, buf);
+    step0_quarter<T, MODE, K>(o0[kk], y, x, shift);
   }
   reg_steps_from<T, MODE, K, 1, true>(y, d, c, g);
   if (g == 0) {
 #pragma unroll
     for (int t = 0; t < M1; ++t) *reinterpret_cast<V4*>(stage + c * PT + 4 * t) = y[t];
   }
-  wave_sync();
+  wait_lds();
   T* dst = static_cast<T*>(d.out) + tile * 16 * ROUT;
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
