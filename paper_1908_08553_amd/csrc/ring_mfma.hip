@@ -549,78 +549,92 @@ __global__ __launch_bounds__(kThreads) void ring_bf16x3_nt(
 }
 
 // ------------------------------------------- bf16x3 NT, 256 x 256 tiles
-// ring_bf16x3_nt on a 256 x 256 tile: eight waves (2 x 4), each 128 x 64, so
-// every staged k-slice feeds twice the MFMA work.  The four 256 x 32 operand
-// slices (80 KiB of LDS) are single-buffered with a register prefetch of the
-// next slice.  Used without split-K, when the output alone fills the chip.
-__global__ __launch_bounds__(kBThreads) void ring_bf16x3_nt_big(
+// ring_bf16x3_nt on a 256 x 256 tile: sixteen waves (4 x 4), each 64 x 64
+// (four waves per SIMD to hide LDS latency), so every staged k-slice feeds
+// four times the MFMA work of a 128 x 128 tile.  The four 256 x 32 operand
+// slices (64 KiB) are double-buffered in LDS and filled with global_load_lds
+// (16 bytes per lane straight into LDS, 1 KiB = 16 rows per instruction, no
+// registers): the next slice is in flight while the current one is
+// multiplied, and one barrier per slice separates the two.  The 16-byte
+// chunk j of row r sits at position j ^ ((r / 4) % 4) of its 64-byte row, so
+// the 16 lanes of an MFMA-layout read (rows base + c, one chunk) cover all 64
+// banks.  Rows past M or N are filled from row M - 1 (N - 1); their products
+// are never stored.  Used without split-K, when the output alone fills the
+// chip.
+typedef __attribute__((address_space(3))) void* LdsPtrR;
+__device__ inline void ring_fill16(const void* g, void* lds) {
+#if __HIP_DEVICE_COMPILE__
+  __builtin_amdgcn_global_load_lds(g, (LdsPtrR)(lds), 16, 0, 0);
+#else
+  (void)g;
+  (void)lds;
+#endif
+}
+
+constexpr int kB16Threads = 1024;   // 16 waves, 64 x 64 each
+__global__ __launch_bounds__(kB16Threads) void ring_bf16x3_nt_big(
     const uint16_t* __restrict__ Ah, const uint16_t* __restrict__ Al,
     const uint16_t* __restrict__ Bh, const uint16_t* __restrict__ Bl, int64_t M, int64_t N,
     int64_t kp, float* __restrict__ C, const float* __restrict__ W, int32_t w_slices,
     double* __restrict__ partials) {
-  __shared__ __attribute__((aligned(16))) uint16_t sAh[kBT][kLdk];
-  __shared__ __attribute__((aligned(16))) uint16_t sAl[kBT][kLdk];
-  __shared__ __attribute__((aligned(16))) uint16_t sBh[kBT][kLdk];
-  __shared__ __attribute__((aligned(16))) uint16_t sBl[kBT][kLdk];
+  constexpr int SL = kBT * kBK16;   // entries of one operand slice
+  __shared__ __attribute__((aligned(16))) uint16_t sbuf[2][4][SL];
   const uint32_t ntm = static_cast<uint32_t>((M + kBT - 1) / kBT);
   const uint32_t ntn = static_cast<uint32_t>((N + kBT - 1) / kBT);
   uint32_t tm, tn;
   tile_of(tm, tn, ntm, ntn, blockIdx.x);
   const int64_t m0 = static_cast<int64_t>(tm) * kBT, n0 = static_cast<int64_t>(tn) * kBT;
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
-  const int wm = (w >> 2) * 128, wn = (w & 3) * 64;
+  const int wm = (w >> 2) * 64, wn = (w & 3) * 64;
 
-  // 256 rows x 4 chunks of 16 bytes per operand slice, 2 per thread
-  u16x8 rah[2], ral[2], rbh[2], rbl[2];
-  auto fetch = [&](int64_t k0) {
+  // fills of one slice: 4 operands x 16 instructions, wave w issuing q = w + 16 i
+  // (operand q / 16, rows 16 (q % 16) ..); lane L takes row + L / 4 and puts
+  // its chunk at position L % 4, i.e. chunk (L % 4) ^ ((row / 4) % 4)
+  const uint16_t* ops[4] = {Ah, Al, Bh, Bl};
+  auto fill = [&](int64_t k0, int b) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int q = threadIdx.x + i * kBThreads;
-      const int row = q >> 2, j = q & 3;
-      const int64_t ma = m0 + row, nb = n0 + row, k = k0 + 8 * j;
-      const u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
-      rah[i] = ma < M ? *reinterpret_cast<const u16x8*>(Ah + ma * kp + k) : z;
-      ral[i] = ma < M ? *reinterpret_cast<const u16x8*>(Al + ma * kp + k) : z;
-      rbh[i] = nb < N ? *reinterpret_cast<const u16x8*>(Bh + nb * kp + k) : z;
-      rbl[i] = nb < N ? *reinterpret_cast<const u16x8*>(Bl + nb * kp + k) : z;
-    }
-  };
-  auto stash = [&]() {
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int q = threadIdx.x + i * kBThreads;
-      const int row = q >> 2, j = q & 3;
-      *reinterpret_cast<u16x8*>(&sAh[row][8 * j]) = rah[i];
-      *reinterpret_cast<u16x8*>(&sAl[row][8 * j]) = ral[i];
-      *reinterpret_cast<u16x8*>(&sBh[row][8 * j]) = rbh[i];
-      *reinterpret_cast<u16x8*>(&sBl[row][8 * j]) = rbl[i];
+    for (int i = 0; i < 4; ++i) {
+      const int q = w + 16 * i, o = q >> 4, r = 16 * (q & 15) + (lane >> 2);
+      const int64_t lim = o < 2 ? M : N;
+      const int64_t row = std::min<int64_t>((o < 2 ? m0 : n0) + r, lim - 1);
+      const int j = (lane & 3) ^ ((r >> 2) & 3);
+      ring_fill16(ops[o] + row * kp + k0 + 8 * j, &sbuf[b][o][16 * (q & 15) * kBK16]);
     }
   };
 
-  f32x4 acc[8][4];
+  f32x4 acc[4][4];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  fetch(0);
-  for (int64_t k0 = 0; k0 < kp; k0 += kBK16) {
-    __syncthreads();
-    stash();
-    __syncthreads();
-    if (k0 + kBK16 < kp) fetch(k0 + kBK16);
+  // position of chunk g in rows base + c (base a multiple of 16)
+  const int pos = 8 * (g ^ ((c >> 2) & 3));
+  fill(0, 0);
+  int b = 0;
+  for (int64_t k0 = 0; k0 < kp; k0 += kBK16, b ^= 1) {
+    // this slice's fills (the only memory operations in flight) are done in
+    // every wave, and every wave has finished reading the other buffer
+    __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8) | (0 << 14));
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (k0 + kBK16 < kp) fill(k0 + kBK16, b ^ 1);
+    const uint16_t* sAh = sbuf[b][0];
+    const uint16_t* sAl = sbuf[b][1];
+    const uint16_t* sBh = sbuf[b][2];
+    const uint16_t* sBl = sbuf[b][3];
     bf16x8 bh[4], bl[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      bh[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sBh[wn + 16 * t + c][8 * g]));
-      bl[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sBl[wn + 16 * t + c][8 * g]));
+      const int row = wn + 16 * t + c;
+      bh[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(sBh + row * kBK16 + pos));
+      bl[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(sBl + row * kBK16 + pos));
     }
 #pragma unroll
-    for (int mt = 0; mt < 8; ++mt) {
-      const bf16x8 ah =
-          __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sAh[wm + 16 * mt + c][8 * g]));
-      const bf16x8 al =
-          __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sAl[wm + 16 * mt + c][8 * g]));
+    for (int mt = 0; mt < 4; ++mt) {
+      const int row = wm + 16 * mt + c;
+      const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(sAh + row * kBK16 + pos));
+      const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(sAl + row * kBK16 + pos));
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
         f32x4 a = acc[mt][nt];
@@ -634,7 +648,7 @@ __global__ __launch_bounds__(kBThreads) void ring_bf16x3_nt_big(
 
   double part = 0.0;
 #pragma unroll
-  for (int mt = 0; mt < 8; ++mt)
+  for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       const int64_t mb = m0 + wm + 16 * mt + 4 * g, n = n0 + wn + 16 * nt + c;
@@ -647,13 +661,13 @@ __global__ __launch_bounds__(kBThreads) void ring_bf16x3_nt_big(
       }
     }
   if (W) {
-    __shared__ double red[kBThreads / 64];
+    __shared__ double red[kB16Threads / 64];
     for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
     if (lane == 0) red[w] = part;
     __syncthreads();
     if (threadIdx.x == 0) {
       double sum = 0.0;
-      for (int i = 0; i < kBThreads / 64; ++i) sum += red[i];
+      for (int i = 0; i < kB16Threads / 64; ++i) sum += red[i];
       partials[static_cast<int64_t>(tm) * ntn + tn] = sum;
     }
   }
@@ -775,7 +789,7 @@ hipError_t launch_ring_bf16x3_nt(const NtArgs& a, hipStream_t stream, int64_t* n
     if (tiles > INT_MAX || (dot && tiles > a.partials_cap)) return hipErrorInvalidValue;
     *n_partials = dot ? tiles : 0;
     *c_slices = 1;
-    hipLaunchKernelGGL(ring_bf16x3_nt_big, dim3(static_cast<uint32_t>(tiles)), dim3(kBThreads), 0,
+    hipLaunchKernelGGL(ring_bf16x3_nt_big, dim3(static_cast<uint32_t>(tiles)), dim3(kB16Threads), 0,
                        stream, a.Ah, a.Al, a.Bh, a.Bl, a.m, a.n, a.kp, a.c_out, a.dot_with,
                        a.w_slices, a.partials);
     return hipGetLastError();
