@@ -4,6 +4,7 @@
                     [--no-batch] [--no-serve] [--leg NAME ...] [--calibrate]
     python bench.py --summarize-stats DIR OUT.txt   (rocprofv3 --stats CSV -> text)
     python bench.py --summarize-traffic FETCH_DIR WRITE_DIR OUT.json
+    python bench.py --summarize-mfma DIR OUT.txt   (rocprofv3 --pmc MFMA/CU busy -> text)
                                                     (rocprofv3 --pmc CSVs -> traffic)
 
 One step = one full contraction through the C ABI -- site staging, every
@@ -526,16 +527,21 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"),
                     default=None, help="reduce two rocprofv3 --pmc runs (FETCH_SIZE, "
                     "WRITE_SIZE) with --calibrate to per-launch HBM bytes")
+    ap.add_argument("--summarize-mfma", nargs=2, metavar=("DIR", "OUT"), default=None,
+                    help="reduce a rocprofv3 --pmc run of SQ_VALU_MFMA_BUSY_CYCLES "
+                    "SQ_BUSY_CU_CYCLES GRBM_GUI_ACTIVE to per-kernel busy fractions")
     ap.add_argument("--chunk-schedule", type=int, default=None,
                     help="TN_OPT_CHUNK_SCHEDULE for every contraction of the run")
     ap.add_argument("--command", default="", help="command line recorded in a summary")
     ap.add_argument("--workload", default="quadrant",
                     help="workload key of a traffic record (quadrant / sweep)")
     args = ap.parse_args()
-    if args.summarize_stats or args.summarize_traffic:
+    if args.summarize_stats or args.summarize_traffic or args.summarize_mfma:
         from paper_1908_08553_amd import profsum
         if args.summarize_stats:
             profsum.write_stats(args.summarize_stats[0], args.summarize_stats[1], args.command)
+        if args.summarize_mfma:
+            profsum.write_mfma(args.summarize_mfma[0], args.summarize_mfma[1], args.command)
         if args.summarize_traffic:
             profsum.write_traffic(*args.summarize_traffic, command=args.command, root=ROOT,
                                   workload=args.workload)

@@ -28,17 +28,23 @@ KERNELS = OrderedDict([
     ("ring_mfma_f32", (r"ring_mfma_f32_big|ring_mfma<float>",
                        ["paper_1908_08553_amd/csrc/ring_mfma.hip"])),
     ("ring_mfma_bf16x3", (r"ring_bf16x3_nt", ["paper_1908_08553_amd/csrc/ring_mfma.hip"])),
-    ("absorb_chunk_f64", (r"absorb_chunk(_reg)?<double, 1,",
+    ("absorb_chunk_reg_f64", (r"absorb_chunk_reg<double, 1,",
+                              ["paper_1908_08553_amd/csrc/absorb_chunk_reg.hip",
+                               "paper_1908_08553_amd/csrc/absorb_device.hpp"])),
+    ("absorb_chunk_reg_f32", (r"absorb_chunk_reg<float, 0,",
+                              ["paper_1908_08553_amd/csrc/absorb_chunk_reg.hip",
+                               "paper_1908_08553_amd/csrc/absorb_device.hpp"])),
+    ("absorb_chunk_reg_bf16x3", (r"absorb_chunk_reg<float, 2,",
+                                 ["paper_1908_08553_amd/csrc/absorb_chunk_reg.hip",
+                                  "paper_1908_08553_amd/csrc/absorb_device.hpp"])),
+    ("absorb_chunk_f64", (r"absorb_chunk<double, 1>",
                           ["paper_1908_08553_amd/csrc/absorb_chunk.hip",
-                           "paper_1908_08553_amd/csrc/absorb_chunk_reg.hip",
                            "paper_1908_08553_amd/csrc/absorb_device.hpp"])),
-    ("absorb_chunk_f32", (r"absorb_chunk(_reg)?<float, 0,",
+    ("absorb_chunk_f32", (r"absorb_chunk<float, 0>",
                           ["paper_1908_08553_amd/csrc/absorb_chunk.hip",
-                           "paper_1908_08553_amd/csrc/absorb_chunk_reg.hip",
                            "paper_1908_08553_amd/csrc/absorb_device.hpp"])),
-    ("absorb_chunk_bf16x3", (r"absorb_chunk(_reg)?<float, 2,",
+    ("absorb_chunk_bf16x3", (r"absorb_chunk<float, 2>",
                              ["paper_1908_08553_amd/csrc/absorb_chunk.hip",
-                              "paper_1908_08553_amd/csrc/absorb_chunk_reg.hip",
                               "paper_1908_08553_amd/csrc/absorb_device.hpp"])),
 ])
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
@@ -192,3 +198,58 @@ def write_traffic(fetch_dir, write_dir, out, command="", root=".", workload="qua
         json.dump(rec, f, indent=1)
         f.write("\n")
     return t
+
+
+MFMA_COUNTERS = ("SQ_VALU_MFMA_BUSY_CYCLES", "SQ_BUSY_CU_CYCLES", "GRBM_GUI_ACTIVE")
+
+
+def write_mfma(d, out, command="", min_us=20.0):
+    """Matrix-core and CU busy fractions and the shader clock per kernel, from
+    one ``rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CU_CYCLES
+    GRBM_GUI_ACTIVE --kernel-trace`` run: cycles = GRBM_GUI_ACTIVE / 8 (the
+    counter sums the 8 XCDs), MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024
+    SIMDs x cycles), CU busy = SQ_BUSY_CU_CYCLES / (256 CUs x cycles), clock =
+    cycles / kernel duration.  Kernels averaging under ``min_us`` are left out."""
+    per = {}
+    for path in _find(d, "counter_collection.csv"):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                key = (path, int(r["Dispatch_Id"]))
+                e = per.setdefault(key, {"name": _short(r["Kernel_Name"]),
+                                         "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"]),
+                                         "c": {}})
+                e["c"][r["Counter_Name"]] = e["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    agg = OrderedDict()
+    for e in per.values():
+        a = agg.setdefault(e["name"], [0, 0.0, 0.0, 0.0, 0.0])
+        a[0] += 1
+        a[1] += e["ns"]
+        for i, c in enumerate(MFMA_COUNTERS):
+            a[2 + i] += e["c"].get(c, 0.0)
+    lines = ["# MFMA utilisation per kernel (rocprofv3 counters)", ""]
+    if command:
+        lines += ["Command (repository root on an MI355X, ROCm 7.2):", "    " + command, ""]
+    lines += ["MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (1024 SIMDs x cycles), CU busy = "
+              "SQ_BUSY_CU_CYCLES /",
+              "(256 CUs x cycles), cycles = GRBM_GUI_ACTIVE / 8 (the counter sums the 8 XCDs), "
+              "clock = cycles",
+              "per ns of the kernel-trace duration.  Every dispatch also counts a fixed window "
+              "around the",
+              "kernel, which lowers both fractions for kernels much shorter than a millisecond; "
+              "the counters",
+              f"slow the kernels a little.  Kernels of at least {min_us:g} us:", ""]
+    rows = []
+    for name, (n, ns, mf, cu, gr) in agg.items():
+        if n == 0 or ns / n / 1e3 < min_us or gr <= 0:
+            continue
+        cyc = gr / 8.0
+        rows.append((ns, f"{name[:44]:44s} n={n:5d} avg={ns / n / 1e3:9.1f} us  MFMA busy "
+                         f"{100 * mf / (1024 * cyc):5.1f} %  CU busy {100 * cu / (256 * cyc):5.1f} %  "
+                         f"clock {cyc / ns:4.2f} GHz"))
+    rows.sort(key=lambda x: -x[0])
+    lines += [r for _, r in rows]
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as f:
+        f.write(text)
+    print(text, end="")
+    return rows
