@@ -1,5 +1,5 @@
 // Single-site absorption kernels on the gfx950 matrix cores; the per-wave
-// bodies live in absorb_device.hpp (shared with the batched persistent kernel).
+// bodies live in absorb_device.hpp (shared with the batch kernel).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -26,7 +26,7 @@
 // lets the compiler merge them across the back-edge into an inner loop that
 // only lane 0 can leave, which livelocks the workgroup.  Per-column rescaling is a workgroup reduction, the exponent sum is
 // kept in registers and the result record is assembled by the workgroup that
-// finished the lattice.  Staging + the persistent kernel are captured once in a
+// finished the lattice.  Staging + the batch kernels are captured once in a
 // hipGraph and replayed; only the site pointers change between runs.
 #include <hip/hip_runtime.h>
 

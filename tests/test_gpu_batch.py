@@ -1,5 +1,6 @@
-"""Batched persistent contraction (one launch, hipGraph replay) vs the CPU
-oracle and vs single contractions, through the C ABI."""
+"""Batched contraction (one captured hipGraph: one workgroup per lattice plus
+lock-step launches for the costliest) vs the CPU oracle and vs single
+contractions, through the C ABI."""
 import math
 
 import numpy as np
