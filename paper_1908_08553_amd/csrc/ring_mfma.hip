@@ -140,6 +140,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   const KRange kr = k_range(Kd, S, s, kBK);
   const int64_t m0 = static_cast<int64_t>(tm) * kT, n0 = static_cast<int64_t>(tn) * kT;
   const int ea = shift_of(sa), eb = shift_of(sb);
+  // FP64: the 2^-(ea+eb) factor is applied once to the results instead of to
+  // every staged operand (double-precision vector work slows the FP64 matrix
+  // pipe).  Powers of two scale exactly, so both orders give the same bits
+  // while the unscaled sums stay normal: |ea + eb| <= 512 leaves them more
+  // than 2^400 from either end of the double range.
+  const bool late = F64 && ea + eb <= 512 && ea + eb >= -512;
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
   const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
 
@@ -158,16 +164,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       rb[i] = vb;
     }
   };
-  auto stash = [&](int buf) {
+  // PS: scale each staged operand (the k loop is compiled once per mode, so
+  // the late-scaled loop carries no ldexp)
+  auto stash = [&](int buf, auto ps) {
+    constexpr bool PS = decltype(ps)::value;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const int q = threadIdx.x + i * kThreads;
       const int kk = q / (kT / kVec), cc = (q % (kT / kVec)) * kVec;
       C16 va = ra[i], vb = rb[i];
+      if constexpr (PS) {
 #pragma unroll
-      for (int e = 0; e < kVec; ++e) {
-        va[e] = ldexp(va[e], -ea);
-        vb[e] = ldexp(vb[e], -eb);
+        for (int e = 0; e < kVec; ++e) {
+          va[e] = ldexp(va[e], -ea);
+          vb[e] = ldexp(vb[e], -eb);
+        }
       }
       *reinterpret_cast<C16*>(&As[buf][kk][cc]) = va;
       *reinterpret_cast<C16*>(&Bs[buf][kk][cc]) = vb;
@@ -180,31 +191,39 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
-  fetch(kr.b);
-  stash(0);
-  __syncthreads();
-  int buf = 0;
-  for (int64_t k0 = kr.b; k0 < kr.e; k0 += kBK) {
-    const bool more = k0 + kBK < kr.e;
-    if (more) fetch(k0 + kBK);
-#pragma unroll
-    for (int kb = 0; kb < kBK; kb += 4) {
-      const V4 a4 = *reinterpret_cast<const V4*>(&As[buf][kb + g][wm + 4 * c]);
-      const V4 b4 = *reinterpret_cast<const V4*>(&Bs[buf][kb + g][wn + 4 * c]);
-#pragma unroll
-      for (int mm = 0; mm < 4; ++mm)
-#pragma unroll
-        for (int nn = 0; nn < 4; ++nn) {
-          if constexpr (F64)
-            acc[mm][nn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a4[mm], b4[nn], acc[mm][nn], 0, 0, 0);
-          else
-            acc[mm][nn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[mm], b4[nn], acc[mm][nn], 0, 0, 0);
-        }
-    }
-    if (more) stash(buf ^ 1);   // the other buffer: last read before the previous barrier
+  auto k_loop = [&](auto ps) {
+    fetch(kr.b);
+    stash(0, ps);
     __syncthreads();
-    buf ^= 1;
-  }
+    int buf = 0;
+    for (int64_t k0 = kr.b; k0 < kr.e; k0 += kBK) {
+      const bool more = k0 + kBK < kr.e;
+      if (more) fetch(k0 + kBK);
+#pragma unroll
+      for (int kb = 0; kb < kBK; kb += 4) {
+        const V4 a4 = *reinterpret_cast<const V4*>(&As[buf][kb + g][wm + 4 * c]);
+        const V4 b4 = *reinterpret_cast<const V4*>(&Bs[buf][kb + g][wn + 4 * c]);
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm)
+#pragma unroll
+          for (int nn = 0; nn < 4; ++nn) {
+            if constexpr (F64)
+              acc[mm][nn] =
+                  __builtin_amdgcn_mfma_f64_16x16x4f64(a4[mm], b4[nn], acc[mm][nn], 0, 0, 0);
+            else
+              acc[mm][nn] =
+                  __builtin_amdgcn_mfma_f32_16x16x4f32(a4[mm], b4[nn], acc[mm][nn], 0, 0, 0);
+          }
+      }
+      if (more) stash(buf ^ 1, ps);   // the other buffer: last read before the previous barrier
+      __syncthreads();
+      buf ^= 1;
+    }
+  };
+  if (late)
+    k_loop(std::false_type{});
+  else
+    k_loop(std::true_type{});
 
   // epilogue: lane (c, g) register r of tile (mm, nn) holds
   //   m = wm + 4*i + mm with i = 4g + r (f32) or g + 4r (f64),  n = wn + 4c + nn
@@ -218,7 +237,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       const int i = F64 ? (g + 4 * r) : (4 * g + r);
       const int64_t m = m0 + wm + 4 * i + mm;
       if (m >= M || nb >= N) continue;
-      const V4 v = {acc[mm][0][r], acc[mm][1][r], acc[mm][2][r], acc[mm][3][r]};
+      V4 v = {acc[mm][0][r], acc[mm][1][r], acc[mm][2][r], acc[mm][3][r]};
+      if (late && !W) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = ldexp(v[e], -(ea + eb));
+      }
       if (W) {
         double y[4];
         w_sum(W, M * N, w_slices, m * N + nb, y);
@@ -230,6 +253,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     }
   }
   if (W) {
+    if (late) part = ldexp(part, -(ea + eb));
     const double sum = block_sum(part);
     if (threadIdx.x == 0) partials[static_cast<int64_t>(s) * tiles + tm * ntn + tn] = sum;
   }
