@@ -74,6 +74,26 @@ bool chunk_ok(const Plan& p, const Layout& L, int32_t k0, int32_t len) {
                         static_cast<int32_t>(z.N));
 }
 
+// Steps k, k+1 that absorb_edge fuses: 1 = the last two rows of a column with
+// suffix 1 (a sweep's first column), 2 = the first two rows of a column with
+// prefix 1 (its last column); D = 4 legs, no rescale between them, and large
+// enough for the saved pass to matter (smaller pairs stay in chained launches).
+int32_t edge_kind(const Plan& p, int32_t k, int32_t end) {
+  if (k + 1 >= end) return 0;
+  const Step& s1 = p.steps[k];
+  const Step& s2 = p.steps[k + 1];
+  if (s1.kind != STEP_ABSORB || s2.kind != STEP_ABSORB) return 0;
+  if (s1.unit != s2.unit || s1.col != s2.col || s1.rescale >= 0 || s2.scale_in >= 0) return 0;
+  if (s1.pre * s1.K * s1.post + s2.out < (int64_t{1} << 18)) return 0;
+  if (s1.post == 1 && s2.post == 1 && s1.K == 4 && s1.N == 16 && s2.K == 4 && s2.N == 4 &&
+      s2.pre == 4 * s1.pre && (k + 2 >= end || p.steps[k + 2].col != s2.col))
+    return 1;
+  if (s1.pre == 1 && s2.pre == 1 && s1.K == 4 && s1.N == 4 && s2.K == 16 && s2.N == 4 &&
+      s1.post == 4 * s2.post && s2.post % 4 == 0)
+    return 2;
+  return 0;
+}
+
 struct KStat { int64_t launches = 0; double ms = 0, bytes = 0, flops = 0; };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
@@ -465,8 +485,29 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
   // the next one (first step index of each action; pair flag).
   // Per unit, the absorption steps in order: alone, fused with the next one
   // (pair), or the first of a column chunk of `len` steps.
-  enum { ACT_ONE = 0, ACT_PAIR = 1, ACT_CHUNK = 2, ACT_CHAIN = 3 };
-  struct Action { int32_t k, kind, len; };
+  enum { ACT_ONE = 0, ACT_PAIR = 1, ACT_CHUNK = 2, ACT_CHAIN = 3, ACT_EDGE = 4 };
+  // the fused edge pair starting at step k of unit u (kind from edge_kind)
+  auto edge_args = [&](size_t u, int32_t k, int32_t kind) {
+    const Step& s1 = p.steps[k];
+    const Step& s2 = p.steps[k + 1];
+    const AbsorbArgs a = args_of(u, k);
+    EdgeArgs e;
+    e.in = a.in;
+    e.out = a.out;
+    e.in_type = L.out_type[k - 1];
+    e.out_type = L.out_type[k + 1];
+    e.arith = arith;
+    e.head = kind == 1;
+    e.n2 = static_cast<int32_t>(s2.N);
+    e.pre1 = s1.pre;
+    e.post2 = s2.post;
+    e.s_off1 = L.s_off[k];
+    e.s_off2 = L.s_off[k + 1];
+    e.scale_slot = a.scale_slot;
+    e.max_slot = s2.rescale >= 0 ? slot_exp + s2.rescale : nullptr;
+    return e;
+  };
+  struct Action { int32_t k, kind, len, sub = 0; };   // sub: edge_kind of an ACT_EDGE
   std::vector<std::vector<Action>> acts(nu);
   size_t max_acts = 0;
   const int32_t fuse = absorb_policy() == 0 ? fuse_steps() : 0;
@@ -477,7 +518,10 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
       Action a{k, ACT_ONE, 1};
       const bool pair = k + 1 < end && pair_ok(p.steps[k], p.steps[k + 1]) &&
                         L.out_type[k - 1] == L.out_type[k] && L.out_type[k] == L.out_type[k + 1];
-      if (fuse == 2) {
+      const int32_t ek = fuse == 2 ? edge_kind(p, k, end) : 0;
+      if (ek && L.out_type[k] == L.out_type[k + 1] && edge_pair_supported(edge_args(u, k, ek))) {
+        a = {k, ACT_EDGE, 2, ek};
+      } else if (fuse == 2) {
         // chunks of 3 or more rows; two rows go to the pair kernel where it
         // applies (a 2-row slice is too small to amortise a chunk workgroup)
         for (int32_t len = std::min(chunk_max_steps(L.out_type[k - 1]), end - k); len >= 2; --len)
@@ -529,9 +573,10 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
     PairArgs pairs[4];
     ChunkArgs chunks[4];
     ChainUnit chains[4];
+    EdgeArgs edges[4];
     double pair_bytes = 0.0, pair_flops = 0.0, chunk_bytes = 0.0, chunk_flops = 0.0;
-    double chain_bytes = 0.0, chain_flops = 0.0;
-    int32_t n = 0, np = 0, nc = 0, nch = 0;
+    double chain_bytes = 0.0, chain_flops = 0.0, edge_bytes[4], edge_flops[4];
+    int32_t n = 0, np = 0, nc = 0, nch = 0, ne = 0;
     for (size_t u : units) {
       if (t >= acts[u].size()) continue;
       const Action& ac = acts[u][t];
@@ -584,6 +629,15 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
           chunk_bytes += static_cast<double>(sj.K * sj.N) * eb;
           chunk_flops += static_cast<double>(sj.flops);
         }
+      } else if (ac.kind == ACT_EDGE) {
+        const Step& s1 = p.steps[ac.k];
+        const Step& s2 = p.steps[ac.k + 1];
+        EdgeArgs e = edge_args(u, ac.k, ac.sub);
+        e.in = a.in;
+        edge_bytes[ne] = static_cast<double>(s1.pre * s1.K * s1.post) * elem_bytes(e.in_type) +
+                         static_cast<double>(s2.out) * elem_bytes(e.out_type);
+        edge_flops[ne] = static_cast<double>(s1.flops + s2.flops);
+        edges[ne++] = e;
       } else if (ac.kind == ACT_PAIR) {
         const Step& s1 = p.steps[ac.k];
         const Step& s2 = p.steps[ac.k + 1];
@@ -616,6 +670,25 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
       tm.after(cname, chunk_bytes, chunk_flops);
     }
     const char* kname = "";
+    if (ne > 0) {
+      bool same = true;
+      for (int32_t i = 1; i < ne; ++i)
+        same = same && edges[i].head == edges[0].head && edges[i].n2 == edges[0].n2 &&
+               edges[i].in_type == edges[0].in_type && edges[i].out_type == edges[0].out_type;
+      if (same) {
+        double b = 0.0, f = 0.0;
+        for (int32_t i = 0; i < ne; ++i) { b += edge_bytes[i]; f += edge_flops[i]; }
+        tm.before();
+        TN_HIP_L(launch_absorb_edges(edges, ne, sa, state, st, &kname));
+        tm.after(kname, b, f);
+      } else {
+        for (int32_t i = 0; i < ne; ++i) {
+          tm.before();
+          TN_HIP_L(launch_absorb_edges(&edges[i], 1, sa, state, st, &kname));
+          tm.after(kname, edge_bytes[i], edge_flops[i]);
+        }
+      }
+    }
     if (np > 0) {
       tm.before();
       TN_HIP_L(launch_absorb_pairs(pairs, np, sa, state, st, &kname));

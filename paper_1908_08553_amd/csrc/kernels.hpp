@@ -105,6 +105,28 @@ struct PairArgs {
 hipError_t launch_absorb_pairs(const PairArgs* a, int32_t n, const StagedArrays& st,
                                DevState* state, hipStream_t stream, const char** kname);
 
+// Two consecutive steps at an edge of a column sweep, fused (absorb_edge.hip):
+//   head (first column, suffix 1): s1 = (pre1, 4, 16, 1), s2 = (4 pre1, 4, 4, 1);
+//   tail (last column, prefix 1): s1 = (1, 4, 4, 4 post2), s2 = (1, 16, 4, post2)
+//   with 4 | post2 (n2 = 4 in both).
+// Input of s1 in in_type, output of s2 (and the intermediate) in out_type;
+// arithmetic in double when out_type is F64, else float (not BF16x3).
+struct EdgeArgs {
+  const void* in;
+  void* out;
+  int32_t in_type, out_type;   // ElemType
+  int32_t arith;
+  bool head;
+  int32_t n2;
+  int64_t pre1, post2;
+  int64_t s_off1, s_off2;
+  const int32_t* scale_slot;   // scales s1's input (nullable)
+  int32_t* max_slot;           // measured after s2 (nullable)
+};
+bool edge_pair_supported(const EdgeArgs& a);
+hipError_t launch_absorb_edges(const EdgeArgs* a, int32_t n, const StagedArrays& st,
+                               DevState* state, hipStream_t stream, const char** kname);
+
 // Up to kChunkMax consecutive rows of one column (see absorb_chunk.hip): the
 // first step has K = 4 or 16, inner steps K = N = 16 with D = 4 legs between
 // them, the last N = 4 or 16; the boundary slice stays in LDS for the chunk.

@@ -206,6 +206,41 @@ def test_chunk_schedules_12x12_d4_vs_oracle(tn, uniform12, oracle12, sched, orde
     close(got, oracle12, prec)
 
 
+def edge_launches(names):
+    return {k: v for k, v in names.items() if k.startswith("absorb_edge_")}
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "f64"])
+def test_edge_pairs_12x12_d4(tn, uniform12, oracle12, prec):
+    # the first column's rows 10-11 (suffix 1) and the last column's rows 0-1
+    # (prefix 1) run as fused pairs; the last column is FP64 in every
+    # precision, the first column's pair has no BF16x3 form
+    got, names = run(tn, uniform12, 12, 12, P.COLSWEEP, prec, 2)
+    want = {"f64": {"absorb_edge_f64": 2},
+            "f32": {"absorb_edge_f32": 1, "absorb_edge_f64": 1},
+            "bf16x3": {"absorb_edge_f64": 1}}[prec]
+    assert edge_launches(names) == want, names
+    close(got, oracle12, prec)
+    plain, pn = run(tn, uniform12, 12, 12, P.COLSWEEP, prec, 0)
+    assert not edge_launches(pn), pn
+    tol = 1e-12 if prec == "f64" else 1e-5 * abs(plain.log_abs)
+    assert got.sign == plain.sign and abs(got.log_abs - plain.log_abs) <= tol
+
+
+@pytest.mark.parametrize("rows,cols", [(13, 5), (10, 3), (11, 11)])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_edge_pairs_ragged_and_signed(tn, rows, cols, prec):
+    # N(0,1) sites (signs, cancellation) on odd sizes: both pairs fuse, and
+    # the rescale slot the bottom pair measures feeds the next column
+    s = li.normal(rows, cols, 4, 300 + rows * cols)
+    ref = C.contract_grid(s, rows, cols, P.QUADRANT, 0, 0)
+    got, names = run(tn, s, rows, cols, P.COLSWEEP, prec, 2)
+    assert sum(edge_launches(names).values()) == 2, names
+    assert got.status == 0 and got.sign == ref.sign
+    tol = 1e-12 if prec == "f64" else 1e-5 * max(1.0, abs(ref.log_abs))
+    assert abs(got.log_abs - ref.log_abs) <= tol, (got.log_abs, ref.log_abs)
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16x3", "f64"])
 def test_register_chunks_take_the_sweep(tn, uniform12, prec):
     # 12 rows: every chunk of the middle columns has suffix 4^8, 4^4 (or 4^9,
