@@ -1,6 +1,7 @@
 """ctypes marshalling for include/tn.h (no arithmetic happens here)."""
 from __future__ import annotations
 
+import collections.abc as _abc
 import ctypes as C
 import math
 import os
@@ -134,6 +135,39 @@ class Result:
     @classmethod
     def from_c(cls, r: tn_result) -> "Result":
         return cls(r.sign, r.status, r.log_abs, r.value, r.mantissa, r.exp2_sum)
+
+
+class Results(_abc.Sequence):
+    """The records of a batch of contractions, in the C array the library
+    wrote: one numpy array per field (``.log_abs``, ``.mantissa``, ...) and a
+    Result per index, built when it is read."""
+
+    _DT = None
+
+    def __init__(self, outs):
+        import numpy as np
+        if Results._DT is None:
+            Results._DT = np.dtype([("sign", np.int32), ("status", np.int32),
+                                    ("log_abs", np.float64), ("value", np.float64),
+                                    ("mantissa", np.float64), ("exp2_sum", np.int64)])
+            assert Results._DT.itemsize == C.sizeof(tn_result)
+        self._outs = outs
+        self._a = np.frombuffer(outs, dtype=Results._DT)
+
+    def __len__(self):
+        return len(self._a)
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[j] for j in range(*i.indices(len(self)))]
+        r = self._a[i]
+        return Result(int(r["sign"]), int(r["status"]), float(r["log_abs"]), float(r["value"]),
+                      float(r["mantissa"]), int(r["exp2_sum"]))
+
+    def __getattr__(self, name):
+        if name in ("sign", "status", "log_abs", "value", "mantissa", "exp2_sum"):
+            return self._a[name]
+        raise AttributeError(name)
 
 
 def _int_array(v) -> Optional[C.Array]:
@@ -405,7 +439,7 @@ class Batch:
         if status not in (TN_OK, TN_ENONFINITE):
             _check(status)
         del keep
-        return [Result.from_c(o) for o in outs]
+        return Results(outs)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -433,7 +467,7 @@ def tn_contract_batch(plans, site_lists, precision="f32", workspace=None, stream
     if status not in (TN_OK, TN_ENONFINITE):
         _check(status)
     del keep
-    return [Result.from_c(o) for o in outs]
+    return Results(outs)
 
 
 # ------------------------------------------------------- cached environments
@@ -515,7 +549,7 @@ class EnvSet:
         if status not in (TN_OK, TN_ENONFINITE):
             _check(status)
         del keep
-        return [Result.from_c(o) for o in outs]
+        return Results(outs)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -568,9 +602,12 @@ def tn_observables(results, rows: int, cols: int):
     pairs = rows * (cols - 1) + (rows - 1) * cols
     if len(results) != 1 + 2 * n + pairs:
         raise ValueError("need 1 + 2 rows cols + pairs results")
-    res = (tn_result * len(results))()
-    for i, r in enumerate(results):
-        res[i] = tn_result(r.sign, r.status, r.log_abs, r.value, r.mantissa, r.exp2_sum)
+    if isinstance(results, Results):
+        res = results._outs
+    else:
+        res = (tn_result * len(results))()
+        for i, r in enumerate(results):
+            res[i] = tn_result(r.sign, r.status, r.log_abs, r.value, r.mantissa, r.exp2_sum)
     mx = (C.c_double * n)()
     mz = (C.c_double * n)()
     czz = (C.c_double * max(pairs, 1))()

@@ -385,6 +385,11 @@ struct BatchImpl {
   std::vector<int32_t> step_base;       // first global step per lattice
   std::vector<std::vector<char*>> init_dst;
   std::vector<StageDesc> descs;
+  // the site pointers the device descriptors were last built from (the
+  // descriptor table in the reserved workspace only changes with them)
+  std::vector<const double*> desc_sites;
+  bool descs_valid = false;
+  tn_result* host_res = nullptr;        // pinned landing buffer of the results
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -476,6 +481,13 @@ tn_status batch_create(const Plan* const* plans, int32_t n, int32_t prec, int32_
   }
   b->ws = static_cast<char*>(ws);
   b->ws_bytes = ws_bytes;
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->host_res), sizeof(tn_result) * n) !=
+      hipSuccess) {
+    err = "pinned result buffer";
+    b->host_res = nullptr;
+    delete b;
+    return TN_ENOMEM;
+  }
 
   // tables
   std::vector<BLattice> lats(n);
@@ -665,22 +677,48 @@ tn_status batch_create(const Plan* const* plans, int32_t n, int32_t prec, int32_
 tn_status batch_run(BatchImpl* b, const double* const* const* sites, hipStream_t stream,
                     tn_result* outs, std::string& err) {
   const int32_t n = static_cast<int32_t>(b->plans.size());
+  // the staging descriptors depend only on the site pointers: rebuild and
+  // upload them when a lattice's pointers changed since the last run
+  bool dirty = !b->descs_valid;
+  if (b->desc_sites.empty()) {
+    size_t total = 0;
+    for (int32_t i = 0; i < n; ++i) total += b->plans[i]->rows * b->plans[i]->cols;
+    b->desc_sites.assign(total, nullptr);
+  }
   for (int32_t i = 0; i < n; ++i) {
     if (!sites[i]) { err = "null site array"; return TN_EINVAL; }
     const Plan& p = *b->plans[i];
     for (int32_t s = 0; s < p.rows * p.cols; ++s)
       if (!sites[i][s]) { err = "null site pointer"; return TN_EINVAL; }
-    fill_stage_descs(p, b->layouts[i], b->s_base[i], sites[i], b->init_dst[i].data(),
-                     b->descs.data() + b->step_base[i]);
   }
-  hipError_t e = hipMemcpyAsync(b->ws + b->off_descs, b->descs.data(),
-                                sizeof(StageDesc) * b->descs.size(), hipMemcpyHostToDevice, stream);
+  size_t o = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const Plan& p = *b->plans[i];
+    const int32_t ns = p.rows * p.cols;
+    bool same = b->descs_valid;
+    for (int32_t s = 0; same && s < ns; ++s) same = b->desc_sites[o + s] == sites[i][s];
+    if (!same) {
+      fill_stage_descs(p, b->layouts[i], b->s_base[i], sites[i], b->init_dst[i].data(),
+                       b->descs.data() + b->step_base[i]);
+      std::copy(sites[i], sites[i] + ns, b->desc_sites.begin() + o);
+      dirty = true;
+    }
+    o += ns;
+  }
+  hipError_t e = hipSuccess;
+  if (dirty) {
+    b->descs_valid = false;
+    e = hipMemcpyAsync(b->ws + b->off_descs, b->descs.data(), sizeof(StageDesc) * b->descs.size(),
+                       hipMemcpyHostToDevice, stream);
+  }
   if (e == hipSuccess) e = hipGraphLaunch(b->exec, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(outs, b->ws + b->off_results, sizeof(tn_result) * n, hipMemcpyDeviceToHost,
-                       stream);
+    e = hipMemcpyAsync(b->host_res, b->ws + b->off_results, sizeof(tn_result) * n,
+                       hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) { err = hipGetErrorString(e); return TN_EDEVICE; }
+  b->descs_valid = true;
+  std::memcpy(outs, b->host_res, sizeof(tn_result) * n);
   for (int32_t i = 0; i < n; ++i)
     if (outs[i].status != TN_OK) {
       err = "non-finite value in lattice " + std::to_string(i);
@@ -693,6 +731,7 @@ void batch_destroy(BatchImpl* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->host_res) (void)hipHostFree(b->host_res);
   delete b;
 }
 

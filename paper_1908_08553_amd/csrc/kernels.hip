@@ -77,11 +77,14 @@ __device__ inline void block_max_bad(T& m, int& bad) {
 }
 
 // ---------------------------------------------------------------- staging
+// One wavefront per site tensor, kBlock / 64 sites per workgroup (a batch
+// stages tens of thousands of sites of at most a few hundred entries: one
+// workgroup each left the GPU dispatching rather than copying).
+constexpr int kStageSites = kBlock / 64;
+
 __global__ __launch_bounds__(kBlock) void stage_kernel(const StageDesc* __restrict__ descs,
-                                                       StagedArrays st, StageTargets tg) {
-  const StageDesc d = descs[blockIdx.x];
-  int32_t* site_exp = tg.site_exp;
-  int32_t* site_bad = tg.site_bad;
+                                                       int32_t n_sites, StagedArrays st,
+                                                       StageTargets tg) {
   if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < tg.n_slots; i += blockDim.x) tg.slot_exp[i] = kExpZero;
     if (threadIdx.x == 0) {
@@ -96,24 +99,26 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageDesc* __restri
       }
     }
   }
+  const int lane = threadIdx.x & 63;
+  const int32_t site = blockIdx.x * kStageSites + (threadIdx.x >> 6);
+  if (site >= n_sites) return;
+  const StageDesc d = descs[site];
   double m = 0.0;
   int bad = 0;
-  for (int64_t q = threadIdx.x; q < d.entries; q += blockDim.x) {
+  for (int64_t q = lane; q < d.entries; q += 64) {
     const double x = d.src[q];
     bad |= !isfinite(x);
     m = fmax(m, fabs(x));
   }
-  block_max_bad(m, bad);
-  __shared__ int32_t sh_e;
-  if (threadIdx.x == 0) {
-    const int32_t e = bad ? 0 : exp_of(m);
-    sh_e = (e == kExpZero) ? 0 : e;
-    site_exp[blockIdx.x] = sh_e;
-    site_bad[blockIdx.x] = bad;
+  m = wave_max(m);
+  bad = wave_or(bad);
+  const int32_t e0 = bad ? 0 : exp_of(m);
+  const int32_t e = (e0 == kExpZero) ? 0 : e0;
+  if (lane == 0) {
+    tg.site_exp[site] = e;
+    tg.site_bad[site] = bad;
   }
-  __syncthreads();
-  const int32_t e = sh_e;
-  for (int64_t q = threadIdx.x; q < d.entries; q += blockDim.x) {
+  for (int64_t q = lane; q < d.entries; q += 64) {
     int64_t rem = q, off = 0;
     for (int a = d.ndim - 1; a >= 0; --a) {
       const int64_t i = rem % d.dims[a];
@@ -527,7 +532,8 @@ __global__ __launch_bounds__(kBlock) void site_dots_kernel(SiteEnvArgs a, SiteDo
 hipError_t launch_stage(const StageDesc* descs, int32_t n_steps, StagedArrays st, StageTargets t,
                         hipStream_t stream) {
   if (n_steps <= 0) return hipSuccess;
-  hipLaunchKernelGGL(stage_kernel, dim3(n_steps), dim3(kBlock), 0, stream, descs, st, t);
+  hipLaunchKernelGGL(stage_kernel, dim3((n_steps + kStageSites - 1) / kStageSites), dim3(kBlock),
+                     0, stream, descs, n_steps, st, t);
   return hipGetLastError();
 }
 

@@ -71,6 +71,30 @@ def test_graph_replays_match_eager(tn, mix48):
     b.close()
 
 
+def test_changed_site_pointers_rebuild_their_descriptors(tn):
+    # the staging descriptors are rebuilt only for lattices whose site
+    # pointers changed since the previous run: A, then A with one lattice's
+    # sites swapped for new tensors, then A again
+    mix = li.batch_mix(10, 31)
+    plans, sites_a = build(tn, mix)
+    r, c, D, _ = mix[4]
+    other = li.uniform(r, c, D, 4321)
+    sites_b = list(sites_a)
+    sites_b[4] = tn.device_sites(other)
+    b = tn.Batch(plans, "f64", split=3)
+    first = b.run(sites_a)
+    second = b.run(sites_b)
+    third = b.run(sites_a)
+    assert abs(second[4].log_abs - OC.contract_grid(other, r, c).log_abs) <= 1e-12
+    for i in range(10):
+        assert (third[i].mantissa, third[i].exp2_sum) == (first[i].mantissa, first[i].exp2_sum)
+        if i != 4:
+            assert (second[i].mantissa, second[i].exp2_sum) == \
+                   (first[i].mantissa, first[i].exp2_sum)
+    assert np.array_equal(third.log_abs, first.log_abs) and len(third) == 10
+    b.close()
+
+
 def test_configs_are_bitwise_identical(tn, mix48):
     mix, _ = mix48
     plans, sites = build(tn, mix)
