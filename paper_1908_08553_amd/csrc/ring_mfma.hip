@@ -112,6 +112,23 @@ __device__ inline void w_sum(const T* __restrict__ W, int64_t slice, int32_t w_s
   }
 }
 
+template <typename X>
+struct TypeTag {
+  using type = X;
+};
+
+// 16 bytes per lane from global memory straight into LDS: one instruction
+// fills 1 KiB at lds + 16 * lane.
+typedef __attribute__((address_space(3))) void* LdsPtrR;
+__device__ inline void ring_fill16(const void* g, void* lds) {
+#if __HIP_DEVICE_COMPILE__
+  __builtin_amdgcn_global_load_lds(g, (LdsPtrR)(lds), 16, 0, 0);
+#else
+  (void)g;
+  (void)lds;
+#endif
+}
+
 // ------------------------------------------------------------ f32 / f64
 // The register budget (two waves per SIMD) keeps the 64 (f32) or 128 (f64)
 // accumulator registers in VGPRs; with more live registers the compiler parks
@@ -128,8 +145,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   using C16 = typename std::conditional<F64, f64x2, f32x4>::type;
   constexpr int kVec = 16 / sizeof(T);                 // elements per 16-byte chunk
   constexpr int kPer = kBK * kT / kVec / kThreads;     // 16-byte chunks per thread per operand
-  __shared__ __attribute__((aligned(32))) T As[2][kBK][kT];
-  __shared__ __attribute__((aligned(32))) T Bs[2][kBK][kT];
+  // two buffers per operand, declared apart: the compiler tracks the
+  // asynchronous fills of one against reads of the other only for distinct
+  // LDS variables
+  __shared__ __attribute__((aligned(32))) T As0[kBK][kT];
+  __shared__ __attribute__((aligned(32))) T As1[kBK][kT];
+  __shared__ __attribute__((aligned(32))) T Bs0[kBK][kT];
+  __shared__ __attribute__((aligned(32))) T Bs1[kBK][kT];
+  auto a_buf = [&](int b) -> T (*)[kT] { return b ? As1 : As0; };
+  auto b_buf = [&](int b) -> T (*)[kT] { return b ? Bs1 : Bs0; };
 
   const uint32_t ntm = static_cast<uint32_t>((M + kT - 1) / kT);
   const uint32_t ntn = static_cast<uint32_t>((N + kT - 1) / kT);
@@ -180,8 +204,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
           vb[e] = ldexp(vb[e], -eb);
         }
       }
-      *reinterpret_cast<C16*>(&As[buf][kk][cc]) = va;
-      *reinterpret_cast<C16*>(&Bs[buf][kk][cc]) = vb;
+      *reinterpret_cast<C16*>(&a_buf(buf)[kk][cc]) = va;
+      *reinterpret_cast<C16*>(&b_buf(buf)[kk][cc]) = vb;
     }
   };
 
@@ -201,8 +225,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       if (more) fetch(k0 + kBK);
 #pragma unroll
       for (int kb = 0; kb < kBK; kb += 4) {
-        const V4 a4 = *reinterpret_cast<const V4*>(&As[buf][kb + g][wm + 4 * c]);
-        const V4 b4 = *reinterpret_cast<const V4*>(&Bs[buf][kb + g][wn + 4 * c]);
+        const V4 a4 = *reinterpret_cast<const V4*>(&a_buf(buf)[kb + g][wm + 4 * c]);
+        const V4 b4 = *reinterpret_cast<const V4*>(&b_buf(buf)[kb + g][wn + 4 * c]);
 #pragma unroll
         for (int mm = 0; mm < 4; ++mm)
 #pragma unroll
@@ -220,10 +244,69 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
       buf ^= 1;
     }
   };
-  if (late)
-    k_loop(std::false_type{});
-  else
+  // FP64 with the scaling applied to the results: each k row of A and B (128
+  // doubles, 1 KiB) goes from global memory straight into LDS with one
+  // instruction, wave w filling rows w, w + 4, ...; rows past the k range
+  // are zeroed, columns past M or N are filled from column M - 2 (N - 2) and
+  // their products never stored.  The next slice is in flight while the
+  // current one is multiplied; one wait and barrier per slice.
+  auto k_loop_async = [&](auto f64_tag) {
+    using D4 = typename decltype(f64_tag)::type;
+    const int64_t cm = std::min<int64_t>(m0 + 2 * lane, M - 2);
+    const int64_t cn = std::min<int64_t>(n0 + 2 * lane, N - 2);
+    auto fill = [&](int64_t k0, T (*sa)[kT], T (*sb)[kT]) {
+#pragma unroll
+      for (int i = 0; i < kBK / 4; ++i) {
+        const int r = w + 4 * i;
+        const int64_t kg = k0 + r;
+        if (kg < kr.e) {
+          ring_fill16(A + kg * M + cm, &sa[r][0]);
+          ring_fill16(B + kg * N + cn, &sb[r][0]);
+        } else {
+          *reinterpret_cast<C16*>(&sa[r][2 * lane]) = C16{};
+          *reinterpret_cast<C16*>(&sb[r][2 * lane]) = C16{};
+        }
+      }
+    };
+    // one slice from (sa, sb) while the next one fills (na, nb)
+    auto slice = [&](int64_t k0, T (*sa)[kT], T (*sb)[kT], T (*na)[kT], T (*nb)[kT]) {
+      // this slice's fills are done in every wave, and every wave has
+      // finished reading the other buffers
+      __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (0 << 8) | (0 << 14));
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+      // the slice's operands are read before the next fills are issued: an
+      // LDS read behind an asynchronous fill waits for that fill
+      D4 a4[kBK / 4], b4[kBK / 4];
+#pragma unroll
+      for (int t = 0; t < kBK / 4; ++t) {
+        a4[t] = *reinterpret_cast<const D4*>(&sa[4 * t + g][wm + 4 * c]);
+        b4[t] = *reinterpret_cast<const D4*>(&sb[4 * t + g][wn + 4 * c]);
+      }
+      if (k0 + kBK < kr.e) fill(k0 + kBK, na, nb);
+#pragma unroll
+      for (int t = 0; t < kBK / 4; ++t)
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm)
+#pragma unroll
+          for (int nn = 0; nn < 4; ++nn)
+            acc[mm][nn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a4[t][mm], b4[t][nn],
+                                                               acc[mm][nn], 0, 0, 0);
+    };
+    fill(kr.b, As0, Bs0);
+    for (int64_t k0 = kr.b; k0 < kr.e; k0 += 2 * kBK) {
+      slice(k0, As0, Bs0, As1, Bs1);
+      if (k0 + kBK < kr.e) slice(k0 + kBK, As1, Bs1, As0, Bs0);
+    }
+  };
+  if constexpr (F64) {
+    if (late)
+      k_loop_async(TypeTag<f64x4>{});
+    else
+      k_loop(std::true_type{});
+  } else {
     k_loop(std::true_type{});
+  }
 
   // epilogue: lane (c, g) register r of tile (mm, nn) holds
   //   m = wm + 4*i + mm with i = 4g + r (f32) or g + 4r (f64),  n = wn + 4c + nn
@@ -585,13 +668,29 @@ __global__ __launch_bounds__(kThreads) void ring_bf16x3_nt(
 // banks.  Rows past M or N are filled from row M - 1 (N - 1); their products
 // are never stored.  Used without split-K, when the output alone fills the
 // chip.
-typedef __attribute__((address_space(3))) void* LdsPtrR;
-__device__ inline void ring_fill16(const void* g, void* lds) {
+
+// LDS reads that wait for their own results inside the asm block: the
+// compiler does not count them as LDS loads, so they do not wait for the
+// asynchronous fills of the other buffer that are in flight meanwhile.
+typedef __attribute__((address_space(3))) const void* LdsCPtr;
+typedef uint32_t u32x4r __attribute__((ext_vector_type(4)));
+__device__ inline void lds_read2(const void* p0, const void* p1, u16x8& r0, u16x8& r1) {
 #if __HIP_DEVICE_COMPILE__
-  __builtin_amdgcn_global_load_lds(g, (LdsPtrR)(lds), 16, 0, 0);
+  u32x4r a, b;
+  asm volatile(
+      "ds_read_b128 %0, %2\n\t"
+      "ds_read_b128 %1, %3\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(a), "=&v"(b)
+      : "v"((LdsCPtr)p0), "v"((LdsCPtr)p1)
+      : "memory");
+  r0 = __builtin_bit_cast(u16x8, a);
+  r1 = __builtin_bit_cast(u16x8, b);
 #else
-  (void)g;
-  (void)lds;
+  (void)p0;
+  (void)p1;
+  r0 = u16x8{};
+  r1 = u16x8{};
 #endif
 }
 
@@ -651,14 +750,18 @@ __global__ __launch_bounds__(kB16Threads) void ring_bf16x3_nt_big(
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int row = wn + 16 * t + c;
-      bh[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(sBh + row * kBK16 + pos));
-      bl[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(sBl + row * kBK16 + pos));
+      u16x8 h, l;
+      lds_read2(sBh + row * kBK16 + pos, sBl + row * kBK16 + pos, h, l);
+      bh[t] = __builtin_bit_cast(bf16x8, h);
+      bl[t] = __builtin_bit_cast(bf16x8, l);
     }
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
       const int row = wm + 16 * mt + c;
-      const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(sAh + row * kBK16 + pos));
-      const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(sAl + row * kBK16 + pos));
+      u16x8 h, l;
+      lds_read2(sAh + row * kBK16 + pos, sAl + row * kBK16 + pos, h, l);
+      const bf16x8 ah = __builtin_bit_cast(bf16x8, h);
+      const bf16x8 al = __builtin_bit_cast(bf16x8, l);
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
         f32x4 a = acc[mt][nt];
