@@ -77,14 +77,20 @@ __device__ inline void block_max_bad(T& m, int& bad) {
 }
 
 // ---------------------------------------------------------------- staging
-// One wavefront per site tensor, kBlock / 64 sites per workgroup (a batch
-// stages tens of thousands of sites of at most a few hundred entries: one
-// workgroup each left the GPU dispatching rather than copying).
-constexpr int kStageSites = kBlock / 64;
+// SPB site tensors per workgroup, kBlock / SPB threads each: one workgroup
+// per site for a single lattice (144 sites at 12 x 12 keep every CU busy),
+// one wavefront per site for batches (tens of thousands of sites of at most a
+// few hundred entries: one workgroup each left the GPU dispatching rather
+// than copying).
+constexpr int kStagePer = 4;          // entries per thread per round
+constexpr int kStageWaveSites = 1024; // from this many sites on, one wavefront per site
 
+template <int SPB>
 __global__ __launch_bounds__(kBlock) void stage_kernel(const StageDesc* __restrict__ descs,
                                                        int32_t n_sites, StagedArrays st,
                                                        StageTargets tg) {
+  constexpr int TPS = kBlock / SPB;
+  static_assert(TPS == 64 || SPB == 1, "a site takes one wavefront or the workgroup");
   if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < tg.n_slots; i += blockDim.x) tg.slot_exp[i] = kExpZero;
     if (threadIdx.x == 0) {
@@ -99,43 +105,77 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(const StageDesc* __restri
       }
     }
   }
-  const int lane = threadIdx.x & 63;
-  const int32_t site = blockIdx.x * kStageSites + (threadIdx.x >> 6);
-  if (site >= n_sites) return;
-  const StageDesc d = descs[site];
+  const int t = threadIdx.x % TPS;
+  const int32_t site = blockIdx.x * SPB + threadIdx.x / TPS;
+  if (SPB > 1 && site >= n_sites) return;   // whole wavefronts
+  const StageDesc& d = descs[site];   // read in place: its arrays are indexed by axis
+  // kStagePer entries per thread per round, their loads issued together
   double m = 0.0;
   int bad = 0;
-  for (int64_t q = lane; q < d.entries; q += 64) {
-    const double x = d.src[q];
-    bad |= !isfinite(x);
-    m = fmax(m, fabs(x));
-  }
-  m = wave_max(m);
-  bad = wave_or(bad);
-  const int32_t e0 = bad ? 0 : exp_of(m);
-  const int32_t e = (e0 == kExpZero) ? 0 : e0;
-  if (lane == 0) {
-    tg.site_exp[site] = e;
-    tg.site_bad[site] = bad;
-  }
-  for (int64_t q = lane; q < d.entries; q += 64) {
-    int64_t rem = q, off = 0;
-    for (int a = d.ndim - 1; a >= 0; --a) {
-      const int64_t i = rem % d.dims[a];
-      rem /= d.dims[a];
-      off += i * d.cstride[a];
+  for (int64_t q0 = 0; q0 < d.entries; q0 += TPS * kStagePer) {
+    double x[kStagePer];
+#pragma unroll
+    for (int j = 0; j < kStagePer; ++j) {
+      const int64_t q = q0 + TPS * j + t;
+      x[j] = q < d.entries ? d.src[q] : 0.0;
     }
-    const double x = ldexp(d.src[off], -e);
-    const float f = static_cast<float>(x);
-    const uint16_t hi = bf16_bits(f);
-    const uint16_t lo = bf16_bits(f - bf16_float(hi));
-    st.s64[d.s_off + q] = x;
-    st.s32[d.s_off + q] = f;
-    st.shi[d.s_off + q] = hi;
-    st.slo[d.s_off + q] = lo;
-    if (d.init_dst) {
-      if (d.init_double) static_cast<double*>(d.init_dst)[q] = x;
-      else static_cast<float*>(d.init_dst)[q] = f;
+#pragma unroll
+    for (int j = 0; j < kStagePer; ++j) {
+      bad |= !isfinite(x[j]);
+      m = fmax(m, fabs(x[j]));
+    }
+  }
+  __shared__ int32_t sh_e;
+  int32_t e;
+  if constexpr (SPB == 1) {
+    block_max_bad(m, bad);   // valid in thread 0
+    if (threadIdx.x == 0) {
+      const int32_t e0 = bad ? 0 : exp_of(m);
+      sh_e = (e0 == kExpZero) ? 0 : e0;
+      tg.site_exp[site] = sh_e;
+      tg.site_bad[site] = bad;
+    }
+    __syncthreads();
+    e = sh_e;
+  } else {
+    m = wave_max(m);
+    bad = wave_or(bad);
+    const int32_t e0 = bad ? 0 : exp_of(m);
+    e = (e0 == kExpZero) ? 0 : e0;
+    if (t == 0) {
+      tg.site_exp[site] = e;
+      tg.site_bad[site] = bad;
+    }
+  }
+  for (int64_t q0 = 0; q0 < d.entries; q0 += TPS * kStagePer) {
+    double x[kStagePer];
+#pragma unroll
+    for (int j = 0; j < kStagePer; ++j) {
+      const int64_t q = q0 + TPS * j + t;
+      int64_t rem = q, off = 0;
+      for (int a = d.ndim - 1; a >= 0; --a) {
+        const int64_t i = rem % d.dims[a];
+        rem /= d.dims[a];
+        off += i * d.cstride[a];
+      }
+      x[j] = q < d.entries ? d.src[off] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kStagePer; ++j) {
+      const int64_t q = q0 + TPS * j + t;
+      if (q >= d.entries) break;
+      const double v = ldexp(x[j], -e);
+      const float f = static_cast<float>(v);
+      const uint16_t hi = bf16_bits(f);
+      const uint16_t lo = bf16_bits(f - bf16_float(hi));
+      st.s64[d.s_off + q] = v;
+      st.s32[d.s_off + q] = f;
+      st.shi[d.s_off + q] = hi;
+      st.slo[d.s_off + q] = lo;
+      if (d.init_dst) {
+        if (d.init_double) static_cast<double*>(d.init_dst)[q] = v;
+        else static_cast<float*>(d.init_dst)[q] = f;
+      }
     }
   }
 }
@@ -532,8 +572,14 @@ __global__ __launch_bounds__(kBlock) void site_dots_kernel(SiteEnvArgs a, SiteDo
 hipError_t launch_stage(const StageDesc* descs, int32_t n_steps, StagedArrays st, StageTargets t,
                         hipStream_t stream) {
   if (n_steps <= 0) return hipSuccess;
-  hipLaunchKernelGGL(stage_kernel, dim3((n_steps + kStageSites - 1) / kStageSites), dim3(kBlock),
-                     0, stream, descs, n_steps, st, t);
+  if (n_steps < kStageWaveSites) {
+    hipLaunchKernelGGL(stage_kernel<1>, dim3(n_steps), dim3(kBlock), 0, stream, descs, n_steps, st,
+                       t);
+  } else {
+    constexpr int spb = kBlock / 64;
+    hipLaunchKernelGGL(stage_kernel<spb>, dim3((n_steps + spb - 1) / spb), dim3(kBlock), 0, stream,
+                       descs, n_steps, st, t);
+  }
   return hipGetLastError();
 }
 
