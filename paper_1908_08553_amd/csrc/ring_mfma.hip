@@ -674,23 +674,47 @@ __global__ __launch_bounds__(kThreads) void ring_bf16x3_nt(
 // asynchronous fills of the other buffer that are in flight meanwhile.
 typedef __attribute__((address_space(3))) const void* LdsCPtr;
 typedef uint32_t u32x4r __attribute__((ext_vector_type(4)));
-__device__ inline void lds_read2(const void* p0, const void* p1, u16x8& r0, u16x8& r1) {
+// Two 16-byte reads at p + O0 and p + O1 (immediate offsets).
+template <int O0, int O1>
+__device__ inline void lds_read2(const void* p, u16x8& r0, u16x8& r1) {
 #if __HIP_DEVICE_COMPILE__
   u32x4r a, b;
   asm volatile(
-      "ds_read_b128 %0, %2\n\t"
-      "ds_read_b128 %1, %3\n\t"
+      "ds_read_b128 %0, %2 offset:%3\n\t"
+      "ds_read_b128 %1, %2 offset:%4\n\t"
       "s_waitcnt lgkmcnt(0)"
       : "=&v"(a), "=&v"(b)
-      : "v"((LdsCPtr)p0), "v"((LdsCPtr)p1)
+      : "v"((LdsCPtr)p), "i"(O0), "i"(O1)
       : "memory");
   r0 = __builtin_bit_cast(u16x8, a);
   r1 = __builtin_bit_cast(u16x8, b);
 #else
-  (void)p0;
-  (void)p1;
-  r0 = u16x8{};
-  r1 = u16x8{};
+  (void)p;
+  r0 = r1 = u16x8{};
+#endif
+}
+
+// Four 16-byte reads at p + O0 .. p + O3 (immediate offsets).
+template <int O0, int O1, int O2, int O3>
+__device__ inline void lds_read4(const void* p, u16x8 (&r)[4]) {
+#if __HIP_DEVICE_COMPILE__
+  u32x4r a, b, c, d;
+  asm volatile(
+      "ds_read_b128 %0, %4 offset:%5\n\t"
+      "ds_read_b128 %1, %4 offset:%6\n\t"
+      "ds_read_b128 %2, %4 offset:%7\n\t"
+      "ds_read_b128 %3, %4 offset:%8\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(d)
+      : "v"((LdsCPtr)p), "i"(O0), "i"(O1), "i"(O2), "i"(O3)
+      : "memory");
+  r[0] = __builtin_bit_cast(u16x8, a);
+  r[1] = __builtin_bit_cast(u16x8, b);
+  r[2] = __builtin_bit_cast(u16x8, c);
+  r[3] = __builtin_bit_cast(u16x8, d);
+#else
+  (void)p;
+  for (int i = 0; i < 4; ++i) r[i] = u16x8{};
 #endif
 }
 
@@ -743,23 +767,29 @@ __global__ __launch_bounds__(kB16Threads) void ring_bf16x3_nt_big(
     asm volatile("" ::: "memory");
     if (k0 + kBK16 < kp) fill(k0 + kBK16, b ^ 1);
     const uint16_t* sAh = sbuf[b][0];
-    const uint16_t* sAl = sbuf[b][1];
     const uint16_t* sBh = sbuf[b][2];
-    const uint16_t* sBl = sbuf[b][3];
+    // operand rows 16 apart are 1 KiB apart, the low parts (sbuf[b][1],
+    // sbuf[b][3]) one 16 KiB slice after the high parts: one base address per
+    // operand, immediate offsets
+    static_assert(16 * kBK16 * 2 == 1024 && SL * 2 == 16384, "operand offsets");
+    const uint16_t* pa = sAh + (wm + c) * kBK16 + pos;
+    const uint16_t* pb = sBh + (wn + c) * kBK16 + pos;
+    u16x8 rh[4], rl[4];
+    lds_read4<0, 1024, 2048, 3072>(pb, rh);
+    lds_read4<16384, 17408, 18432, 19456>(pb, rl);
     bf16x8 bh[4], bl[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int row = wn + 16 * t + c;
-      u16x8 h, l;
-      lds_read2(sBh + row * kBK16 + pos, sBl + row * kBK16 + pos, h, l);
-      bh[t] = __builtin_bit_cast(bf16x8, h);
-      bl[t] = __builtin_bit_cast(bf16x8, l);
+      bh[t] = __builtin_bit_cast(bf16x8, rh[t]);
+      bl[t] = __builtin_bit_cast(bf16x8, rl[t]);
     }
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-      const int row = wm + 16 * mt + c;
       u16x8 h, l;
-      lds_read2(sAh + row * kBK16 + pos, sAl + row * kBK16 + pos, h, l);
+      if (mt == 0) lds_read2<0, 16384>(pa, h, l);
+      if (mt == 1) lds_read2<1024, 17408>(pa, h, l);
+      if (mt == 2) lds_read2<2048, 18432>(pa, h, l);
+      if (mt == 3) lds_read2<3072, 19456>(pa, h, l);
       const bf16x8 ah = __builtin_bit_cast(bf16x8, h);
       const bf16x8 al = __builtin_bit_cast(bf16x8, l);
 #pragma unroll
