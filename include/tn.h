@@ -541,6 +541,14 @@ tn_status tn_server_destroy(tn_server* server);
  *                        and closed against the boundary after it.  Read
  *                        when the set is created.                           */
 #define TN_OPT_ENV_SITES 8
+/*   TN_OPT_RING_OPERAND_SCALE : 1 = the FP64 ring products scale every staged
+ *                        operand by its power of two (the path they take by
+ *                        themselves when the two exponents sum beyond
+ *                        +-512); 0 (default) = automatic: within that range
+ *                        the factor is applied once to the results.  Both
+ *                        give the same bits (power-of-two scaling is exact
+ *                        while nothing leaves the normal range).           */
+#define TN_OPT_RING_OPERAND_SCALE 9
 tn_status tn_set_option(int32_t option, int64_t value);
 
 /* ------------------------------------------------------------ profiling

@@ -281,6 +281,7 @@ TN_OPT_CHAIN_STEPS = 5
 TN_OPT_ENV_STREAMS = 6
 TN_OPT_ENV_ROWS = 7
 TN_OPT_ENV_SITES = 8
+TN_OPT_RING_OPERAND_SCALE = 9
 
 
 class tn_kernel_stat(C.Structure):

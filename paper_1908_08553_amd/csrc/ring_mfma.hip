@@ -50,6 +50,7 @@ constexpr int kThreads = 256;
 constexpr int kXcd = 8;
 constexpr int kMaxSplits = 8;
 constexpr int64_t kFillGroups = 512;   // two workgroups per CU
+int32_t g_ring_operand_scale = 0;      // TN_OPT_RING_OPERAND_SCALE
 
 __device__ inline int32_t shift_of(const int32_t* slot) {
   if (!slot) return 0;
@@ -139,7 +140,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void ring_mfma(
     const T* __restrict__ A, const T* __restrict__ B, int64_t M, int64_t N, int64_t Kd, int32_t S,
     const int32_t* sa, const int32_t* sb, T* __restrict__ C, const T* __restrict__ W,
-    int32_t w_slices, double* __restrict__ partials) {
+    int32_t w_slices, double* __restrict__ partials, int32_t operand_scale) {
   constexpr bool F64 = std::is_same<T, double>::value;
   using V4 = typename std::conditional<F64, f64x4, f32x4>::type;
   using C16 = typename std::conditional<F64, f64x2, f32x4>::type;
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
   // pipe).  Powers of two scale exactly, so both orders give the same bits
   // while the unscaled sums stay normal: |ea + eb| <= 512 leaves them more
   // than 2^400 from either end of the double range.
-  const bool late = F64 && ea + eb <= 512 && ea + eb >= -512;
+  const bool late = F64 && !operand_scale && ea + eb <= 512 && ea + eb >= -512;
   const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
   const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
 
@@ -856,6 +857,8 @@ int32_t capped(int32_t s, int64_t tiles, bool dot, int32_t c_cap, int64_t p_cap)
 
 }  // namespace
 
+void set_ring_operand_scale(int32_t on) { g_ring_operand_scale = on ? 1 : 0; }
+
 bool ring_mfma_supported(const RingArgs& a) {
   return a.m % 4 == 0 && a.n % 4 == 0 && a.m >= 1 && a.n >= 1 && a.k >= 1;
 }
@@ -900,7 +903,8 @@ hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** 
     hipLaunchKernelGGL((ring_mfma<double>), grid, block, 0, stream,
                        static_cast<const double*>(a.A), static_cast<const double*>(a.B), a.m, a.n,
                        a.k, S, a.sa, a.sb, static_cast<double*>(a.c_out),
-                       static_cast<const double*>(a.dot_with), a.w_slices, a.partials);
+                       static_cast<const double*>(a.dot_with), a.w_slices, a.partials,
+                       g_ring_operand_scale);
   } else if (a.arith == AR_BF16X3) {
     return hipErrorInvalidValue;   // split BF16x3 rings go through launch_ring_bf16x3_nt
   } else {
@@ -908,7 +912,7 @@ hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** 
     hipLaunchKernelGGL((ring_mfma<float>), grid, block, 0, stream,
                        static_cast<const float*>(a.A), static_cast<const float*>(a.B), a.m, a.n,
                        a.k, S, a.sa, a.sb, static_cast<float*>(a.c_out),
-                       static_cast<const float*>(a.dot_with), a.w_slices, a.partials);
+                       static_cast<const float*>(a.dot_with), a.w_slices, a.partials, 1);
   }
   return hipGetLastError();
 }

@@ -97,3 +97,24 @@ def test_split_ring_with_ragged_tiles(tn, prec):
     tn.tn_set_option(tn.TN_OPT_KERNEL_IMPL, 0)
     got = tn.contract_grid(plan, tn.device_sites(s), prec)
     close(got, ref, prec)
+
+
+@pytest.mark.parametrize("rows,cols,kind", [(12, 12, "uniform"), (10, 10, "normal"),
+                                            (9, 7, "normal")])
+def test_ring_operand_scaling_paths_agree(tn, rows, cols, kind):
+    # The FP64 ring products apply 2^-(ea+eb) to their results, or to every
+    # staged operand (TN_OPT_RING_OPERAND_SCALE = 1: the path they take by
+    # themselves for exponent sums beyond +-512, which normalised inputs never
+    # reach).  Power-of-two scaling is exact: the same bits either way, split
+    # (10x10, 9x7) and unsplit (12x12) products alike.
+    s = li.make(kind, rows, cols, 4, 31 + rows)
+    ref = C.contract_grid(s, rows, cols, P.QUADRANT, 0, 0)
+    a, sa, _ = run(tn, s, rows, cols, "f64")
+    tn.tn_set_option(tn.TN_OPT_RING_OPERAND_SCALE, 1)
+    try:
+        b, sb, _ = run(tn, s, rows, cols, "f64")
+    finally:
+        tn.tn_set_option(tn.TN_OPT_RING_OPERAND_SCALE, 0)
+    assert sa["ring_mfma_f64"]["launches"] == sb["ring_mfma_f64"]["launches"] == 2
+    assert (a.status, a.sign, a.mantissa, a.exp2_sum) == (b.status, b.sign, b.mantissa, b.exp2_sum)
+    close(a, ref, "f64")
