@@ -522,9 +522,17 @@ tn_status enqueue(const Plan& p, const double* const* sites, bool on_device, int
       if (ek && L.out_type[k] == L.out_type[k + 1] && edge_pair_supported(edge_args(u, k, ek))) {
         a = {k, ACT_EDGE, 2, ek};
       } else if (fuse == 2) {
-        // chunks of 3 or more rows; two rows go to the pair kernel where it
+        // the rest of the column in as few chunks as the longest chunk
+        // allows, their lengths as equal as possible (6 rows: 3 + 3, not
+        // 4 + 2; 12 rows: 4 + 4 + 4); two rows go to the pair kernel where it
         // applies (a 2-row slice is too small to amortise a chunk workgroup)
-        for (int32_t len = std::min(chunk_max_steps(L.out_type[k - 1]), end - k); len >= 2; --len)
+        int32_t ce = k;
+        while (ce < end && p.steps[ce].kind == STEP_ABSORB && p.steps[ce].col == p.steps[k].col)
+          ++ce;
+        const int32_t kmax = chunk_max_steps(L.out_type[k - 1]);
+        const int32_t passes = (ce - k + kmax - 1) / kmax;
+        const int32_t even = passes > 0 ? (ce - k + passes - 1) / passes : kmax;
+        for (int32_t len = std::min(std::max(even, 2), end - k); len >= 2; --len)
           if (chunk_ok(p, L, k, len)) { a = {k, ACT_CHUNK, len}; break; }
         if (a.kind == ACT_CHUNK && a.len == 2 && pair) a = {k, ACT_PAIR, 2};
       } else if (fuse == 1 && pair) {

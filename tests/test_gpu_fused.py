@@ -172,13 +172,12 @@ def test_chunk_partition_of_the_sweep(tn, uniform12, prec, per_column):
 
 
 def test_chunk_quadrant_launches_are_grouped(tn, uniform12):
-    # 6x6 quadrants: columns 1..5 of each unit as a chunk of rows 0-3 and
-    # rows 4-5 fused, the four units' work in one launch each; rows 4-5 take
-    # the pair kernel where the suffix (4^j in column j) is a multiple of 64
-    # (j >= 3) and a 2-row chunk otherwise
+    # 6x6 quadrants: columns 1..5 of each unit as two chunks of 3 rows (the
+    # fewest passes a 4-row chunk allows, lengths as equal as possible), the
+    # four units' work in one launch each
     _, names = run(tn, uniform12, 12, 12, P.QUADRANT, "f32", 2)
-    assert chunk_launches(names) == 5 + 2, names
-    assert pair_launches(names) == 3, names
+    assert chunk_launches(names) == 5 * 2, names
+    assert pair_launches(names) == 0, names
 
 
 @pytest.mark.parametrize("rows,cols", [(6, 12), (12, 6), (9, 7), (5, 13)])
@@ -249,14 +248,12 @@ def test_register_chunks_take_the_sweep(tn, uniform12, prec):
     assert reg_launches(names) == chunk_launches(names) > 0, names
 
 
-def test_register_and_lds_chunks_in_one_sweep(tn):
-    # 9 rows in FP32: rows 0-3 (suffix 4^5) in registers, rows 4-7 (suffix 4,
-    # the bottom row below) on the LDS kernel, row 8 alone
-    s = li.uniform(9, 7, 4, 163)
-    ref = C.contract_grid(s, 9, 7, P.QUADRANT, 0, 0)
-    got, names = run(tn, s, 9, 7, P.COLSWEEP, "f32", 2)
+def test_register_and_lds_chunks_in_one_contraction(tn, uniform12, oracle12):
+    # 12x12 quadrant order in FP32: the 3-row chunks of the quadrant columns
+    # in registers, the first chunked column's short suffix on the LDS kernel
+    got, names = run(tn, uniform12, 12, 12, P.QUADRANT, "f32", 2)
     assert reg_launches(names) > 0 and lds_launches(names) > 0, names
-    close(got, ref, "f32")
+    close(got, oracle12, "f32")
 
 
 @pytest.mark.parametrize("sched", [0, 1, 2])
