@@ -17,7 +17,7 @@ from ._native import (  # noqa: F401
     tn_contract_grid_static, TN_STATIC_SCRATCH_BYTES,
     TN_OPT_KERNEL_IMPL, TN_OPT_BATCH_THREADS, TN_OPT_FUSE_STEPS, TN_OPT_CHUNK_SCHEDULE,
     TN_OPT_QUADRANT_STREAMS, TN_OPT_CHAIN_STEPS, TN_OPT_ENV_STREAMS, TN_OPT_ENV_ROWS,
-    TN_OPT_ENV_SITES, TN_OPT_RING_OPERAND_SCALE,
+    TN_OPT_ENV_SITES, TN_OPT_RING_OPERAND_SCALE, TN_OPT_CHUNK_STREAM,
     tn_profile_enable, tn_profile_read,
     Batch, tn_batch_workspace, tn_contract_batch, Server, EnvSet, Ite,
     plan_grid, contract_grid, device_sites, workspace_for,

@@ -282,6 +282,7 @@ TN_OPT_ENV_STREAMS = 6
 TN_OPT_ENV_ROWS = 7
 TN_OPT_ENV_SITES = 8
 TN_OPT_RING_OPERAND_SCALE = 9
+TN_OPT_CHUNK_STREAM = 10
 
 
 class tn_kernel_stat(C.Structure):

@@ -449,6 +449,11 @@ tn_status tn_set_option(int32_t option, int64_t value) {
     tn::set_ring_operand_scale(static_cast<int32_t>(value));
     return TN_OK;
   }
+  if (option == TN_OPT_CHUNK_STREAM) {
+    if (value < 0 || value > 65536) return fail(TN_EINVAL, "TN_OPT_CHUNK_STREAM must be 0..65536");
+    tn::set_chunk_stream(static_cast<int32_t>(value));
+    return TN_OK;
+  }
   if (option == TN_OPT_FUSE_STEPS) {
     if (value < 0 || value > 2) return fail(TN_EINVAL, "TN_OPT_FUSE_STEPS must be 0, 1 or 2");
     tn::set_fuse_steps(static_cast<int32_t>(value));

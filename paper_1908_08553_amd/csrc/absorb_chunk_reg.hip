@@ -42,6 +42,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include "absorb_device.hpp"
@@ -88,38 +89,81 @@ struct ROps {
   bf16x8 a0, a1;
 };
 
+// The loads of reg_ops apart from its arithmetic: raw values as loaded (f32 /
+// f64 entries; bf16x3 bit patterns of the hi and lo parts; lanes of zero rows
+// load row 0 and are zeroed when built), so a kernel can issue them early and
+// use them after a wait of its own.
+template <typename T, int MODE>
+struct RawOps {
+  T a[4];
+  uint32_t h[4], l[4];
+  bool live;
+};
+
 template <typename T, int MODE, bool ONE, int NK>
-__device__ inline ROps<T, MODE> reg_ops(const void* Sv, const uint16_t* H, const uint16_t* L,
-                                        int c, int g, int kq = 0) {
+__device__ inline RawOps<T, MODE> reg_ops_load(const void* Sv, const uint16_t* H,
+                                               const uint16_t* L, int c, int g, int kq = 0) {
   constexpr int N = NK == 2 ? 4 : 16;
-  const int n = n_of_row<MODE, NK>(c);
-  auto kidx = [&](int kk) { return 4 * g + kk; };
-  ROps<T, MODE> o;
+  const int n = n_of_row<MODE, NK>(c), nn = n >= 0 ? n : 0;
+  RawOps<T, MODE> r;
+  r.live = n >= 0;
   if constexpr (MODE == M_BF16X3) {
-    const __bf16 z = __builtin_bit_cast(__bf16, static_cast<uint16_t>(0));
-    auto hb = [&](int k) { return n >= 0 ? __builtin_bit_cast(__bf16, H[k * N + n]) : z; };
-    auto lb = [&](int k) { return n >= 0 ? __builtin_bit_cast(__bf16, L[k * N + n]) : z; };
-    if constexpr (ONE) {
-      const int k = g + 4 * kq;
-      o.a0 = bf16x8{hb(k), hb(k), lb(k), z, z, z, z, z};
-    } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        o.a0[i] = hb(kidx(i));
-        o.a0[4 + i] = hb(kidx(i));
-        o.a1[i] = lb(kidx(i));
-        o.a1[4 + i] = z;
-      }
+    for (int i = 0; i < (ONE ? 1 : 4); ++i) {
+      const int k = ONE ? g + 4 * kq : 4 * g + i;
+      r.h[i] = H[k * N + nn];
+      r.l[i] = L[k * N + nn];
     }
   } else {
     const T* S = static_cast<const T*>(Sv);
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const bool live = n >= 0 && (!ONE || kk == 0);
-      o.a[kk] = live ? S[(ONE ? g + 4 * kq : kidx(kk)) * N + n] : T(0);
+    for (int kk = 0; kk < 4; ++kk)
+      r.a[kk] = (!ONE || kk == 0) ? S[(ONE ? g + 4 * kq : 4 * g + kk) * N + nn] : T(0);
+  }
+  return r;
+}
+
+template <typename T, int MODE, bool ONE>
+__device__ inline ROps<T, MODE> reg_ops_build(const RawOps<T, MODE>& r) {
+  ROps<T, MODE> o;
+  if constexpr (MODE == M_BF16X3) {
+    const __bf16 z = __builtin_bit_cast(__bf16, static_cast<uint16_t>(0));
+    auto bf = [&](uint32_t v) { return r.live ? __builtin_bit_cast(__bf16, static_cast<uint16_t>(v)) : z; };
+    if constexpr (ONE) {
+      o.a0 = bf16x8{bf(r.h[0]), bf(r.h[0]), bf(r.l[0]), z, z, z, z, z};
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        o.a0[i] = bf(r.h[i]);
+        o.a0[4 + i] = bf(r.h[i]);
+        o.a1[i] = bf(r.l[i]);
+        o.a1[4 + i] = z;
+      }
     }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) o.a[kk] = r.live ? r.a[kk] : T(0);
   }
   return o;
+}
+
+// The values pass through an empty asm block: nothing that uses them can be
+// scheduled before this point.
+template <typename T, int MODE, bool ONE>
+__device__ inline void launder(RawOps<T, MODE>& r) {
+  if constexpr (MODE == M_BF16X3) {
+#pragma unroll
+    for (int i = 0; i < (ONE ? 1 : 4); ++i) asm volatile("" : "+v"(r.h[i]), "+v"(r.l[i]));
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < (ONE ? 1 : 4); ++kk) asm volatile("" : "+v"(r.a[kk]));
+  }
+}
+
+template <typename T, int MODE, bool ONE, int NK>
+__device__ inline ROps<T, MODE> reg_ops(const void* Sv, const uint16_t* H, const uint16_t* L,
+                                        int c, int g, int kq = 0) {
+  return reg_ops_build<T, MODE, ONE>(reg_ops_load<T, MODE, ONE, NK>(Sv, H, L, c, g, kq));
 }
 
 template <int MODE>
@@ -552,6 +596,178 @@ __device__ inline void tile_bottom(UnitRef d, int64_t tile, T& mx, int& bad, T* 
   }
 }
 
+// FORM_BOTTOM streamed over tiles, for 4-row chunks of 4-byte entries: 256
+// accumulators per lane leave one wavefront per SIMD, so in the one-tile form
+// a wavefront's loads wait for its own matrix work and the reverse.  Here a
+// wavefront takes tiles b, b + G, b + 2G, ... of one unit (G wavefronts, four
+// per CU).  Once step 0 has read the last quarter of a tile's slice, the first
+// two quarters of its next tile are filled into the two stage buffers; they
+// arrive during the register-only steps 1..k-1 and the stores.  Step 0's
+// operands and the scale are loaded once; those of steps 1..k-1 are loaded
+// while the last quarter is in flight and first used after the wait for it
+// (the compiler's own wait for a register load issued among stage fills
+// waits for every fill).  The outputs leave through a third, small buffer, a
+// quarter of each fibre at a time.  Waits: at quarter 0 at most min(LPW, NST)
+// operations may be outstanding (the previous tile's stores, or the first
+// tile's quarter 1), at quarter 1 LPW + NST after a previous tile (its stores
+// and the fills of quarter 2), else as in the one-tile form.
+template <int K>
+constexpr int stream_out_pitch() { return (1 << (2 * (K - 1))) + 4; }
+
+// Sixteen 16-byte LDS reads at p + 16 i into v[i], in one asm block that waits
+// for its own results.  The compiler does not count it as an LDS load, so it
+// adds no wait for the stage fills in flight (it cannot tell which buffer a
+// fill targets and would wait for all of them).
+typedef __attribute__((address_space(3))) const void* LdsCPtr;
+__device__ inline void lds_read16(const void* p, f32x4 (&v)[16]) {
+#if __HIP_DEVICE_COMPILE__
+  asm volatile(
+      "ds_read_b128 %0, %16\n\t"
+      "ds_read_b128 %1, %16 offset:16\n\t"
+      "ds_read_b128 %2, %16 offset:32\n\t"
+      "ds_read_b128 %3, %16 offset:48\n\t"
+      "ds_read_b128 %4, %16 offset:64\n\t"
+      "ds_read_b128 %5, %16 offset:80\n\t"
+      "ds_read_b128 %6, %16 offset:96\n\t"
+      "ds_read_b128 %7, %16 offset:112\n\t"
+      "ds_read_b128 %8, %16 offset:128\n\t"
+      "ds_read_b128 %9, %16 offset:144\n\t"
+      "ds_read_b128 %10, %16 offset:160\n\t"
+      "ds_read_b128 %11, %16 offset:176\n\t"
+      "ds_read_b128 %12, %16 offset:192\n\t"
+      "ds_read_b128 %13, %16 offset:208\n\t"
+      "ds_read_b128 %14, %16 offset:224\n\t"
+      "ds_read_b128 %15, %16 offset:240\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]), "=&v"(v[5]),
+        "=&v"(v[6]), "=&v"(v[7]), "=&v"(v[8]), "=&v"(v[9]), "=&v"(v[10]), "=&v"(v[11]),
+        "=&v"(v[12]), "=&v"(v[13]), "=&v"(v[14]), "=&v"(v[15])
+      : "v"((LdsCPtr)p)
+      : "memory");
+#else
+  (void)p;
+  for (int i = 0; i < 16; ++i) v[i] = f32x4{};
+#endif
+}
+
+template <typename T, int MODE, int K>
+__global__ __launch_bounds__(64) void absorb_chunk_reg_stream(chunk::Group arg) {
+  (void)arg;   // read in place below
+  static_assert(sizeof(T) == 4 && K == 4, "4-row chunks of 4-byte entries");
+  using V4 = RV4<MODE>;
+  constexpr int M1 = 1 << (2 * (K - 1)), QR = quarter_rows<K>();
+  static_assert(M1 == 64, "sixteen 16-byte reads per lane and quarter");
+  constexpr int RIN = 4 * QR, ROUT = 4 * M1, ES = sizeof(T);
+  constexpr int PT = bottom_pitch<T, K>(), BB = 16 * PT, OPT = stream_out_pitch<K>();
+  constexpr int FB = QR * ES;
+  constexpr int PIECES = FB >= 1024 ? FB / 1024 : 1;
+  constexpr int LPW = 16 * PIECES;            // fills per quarter
+  constexpr int TQ = M1 / 4;                  // tiles t per output quarter
+  constexpr int NIT = 16 * M1 / 256;          // 16-byte stores per lane and output quarter
+  constexpr int NST = 4 * NIT;                // stores per tile
+  constexpr int W0 = LPW < NST ? LPW : NST;
+  static_assert(FB % 1024 == 0 && LPW + NST < 64, "fills of whole KiB, vmcnt range");
+  __shared__ __attribute__((aligned(16))) T stage[2 * BB];
+  __shared__ __attribute__((aligned(16))) T ostage[16 * OPT];
+  const GroupRef g = (GroupRef)__builtin_amdgcn_kernarg_segment_ptr();
+  UnitRef d = g->u[0];
+  const uint32_t ntiles = g->first[chunk::kGroup], G = gridDim.x;
+  uint32_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  const int lane = threadIdx.x & 63, c = lane & 15, gl = lane >> 4;
+  auto fill_q = [&](const char* src, int kk, T* buf) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+#pragma unroll
+      for (int pc = 0; pc < PIECES; ++pc)
+        lds_fill16(src + (i * RIN + kk * QR) * ES + pc * 1024 + 16 * lane, buf + i * PT + pc * (1024 / ES));
+  };
+  auto src_of = [&](uint32_t tt) {
+    return static_cast<const char*>(d.in) + static_cast<int64_t>(tt) * 16 * RIN * ES;
+  };
+  ROps<T, MODE> o0[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) o0[kk] = reg_ops<T, MODE, true, 0>(d.S[0], d.hi[0], d.lo[0], c, gl, kk);
+  const int32_t shift = shift_of(d.scale_slot);
+  wait_vm<0>();
+  const char* src = src_of(t);
+  fill_q(src, 0, stage);
+  fill_q(src, 1, stage + BB);
+  T mx = 0;
+  int bad = 0;
+  for (bool first = true;; first = false) {
+    const uint32_t next = t + G;
+    const bool more = next < ntiles;
+    V4 y[M1];
+#pragma unroll
+    for (int q = 0; q < M1; ++q) y[q] = V4{0, 0, 0, 0};
+    RawOps<T, MODE> r1, r2, r3;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      T* buf = stage + (kk & 1) * BB;
+      if (kk == 0) wait_vm<W0>();
+      else if (kk == 1) {
+        if (first) wait_vm<LPW>();
+        else wait_vm<LPW + NST>();
+      } else if (kk == 2) wait_vm<LPW>();
+      else wait_vm<0>();
+      T x[M1];
+      {
+        f32x4 v[16];
+        lds_read16(buf + c * PT + gl * M1, v);
+#pragma unroll
+        for (int t4 = 0; t4 < 16; ++t4)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) x[4 * t4 + e] = v[t4][e];
+      }
+      if (kk < 2) fill_q(src, kk + 2, buf);
+      if (kk == 2) {
+        r1 = reg_ops_load<T, MODE, false, 0>(d.S[1], d.hi[1], d.lo[1], c, gl);
+        r2 = reg_ops_load<T, MODE, false, 0>(d.S[2], d.hi[2], d.lo[2], c, gl);
+        r3 = reg_ops_load<T, MODE, false, 2>(d.S[3], d.hi[3], d.lo[3], c, gl);
+      }
+      if (kk == 3) {
+        launder<T, MODE, false>(r1);
+        launder<T, MODE, false>(r2);
+        launder<T, MODE, false>(r3);
+        // issued on every path (after the last tile they re-read its first
+        // two quarters, from L2) so that no compiler wait depends on the path
+        if (more) src = src_of(next);
+        fill_q(src, 0, stage);
+        fill_q(src, 1, stage + BB);
+      }
+      step0_quarter<T, MODE, K>(o0[kk], y, x, shift);
+    }
+    reg_step<T, MODE, K, 1>(y, reg_ops_build<T, MODE, false>(r1));
+    reg_step<T, MODE, K, 2>(y, reg_ops_build<T, MODE, false>(r2));
+    reg_step<T, MODE, K, 3>(y, reg_ops_build<T, MODE, false>(r3));
+    // outputs: fibre i's row j = 4 t + r at i * ROUT + j; output quarter qo
+    // holds t in [qo TQ, (qo + 1) TQ), M1 entries of each fibre
+    T* dst = static_cast<T*>(d.out) + static_cast<int64_t>(t) * 16 * ROUT;
+#pragma unroll
+    for (int qo = 0; qo < 4; ++qo) {
+      if (gl == 0) {
+#pragma unroll
+        for (int tt = 0; tt < TQ; ++tt) *reinterpret_cast<V4*>(ostage + c * OPT + 4 * tt) = y[qo * TQ + tt];
+      }
+      wait_lds();
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int v = it * 64 + lane, i = v / TQ, j = 4 * (v - i * TQ);
+        const V4 val = *reinterpret_cast<const V4*>(ostage + i * OPT + j);
+        *reinterpret_cast<V4*>(dst + i * ROUT + qo * M1 + j) = val;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) track(static_cast<T>(val[r]), mx, bad);
+      }
+      wait_lds();
+    }
+    if (!more) break;
+    t = next;
+  }
+  wait_vm<0>();   // no fill may land in LDS after the workgroup ends
+  if (d.max_slot) publish_wave(mx, bad, d.max_slot, g->flags);
+}
+
 template <typename T, int MODE, int K, bool TOP, int FORM>
 __global__ __launch_bounds__(FORM == FORM_PAIR ? 128 : 64) void absorb_chunk_reg(chunk::Group arg) {
   (void)arg;   // read in place below
@@ -579,10 +795,40 @@ int form_of(const ChunkArgs& a) {
   return (a.type != EL_F64 && a.post % 32 == 0) ? FORM_PAIR : FORM_DIRECT;
 }
 
+int32_t g_chunk_stream = 1;   // TN_OPT_CHUNK_STREAM: 0 off, 1 four per CU, n >= 2 at most n
+
+// Compute units of the current device (cached per device).
+uint32_t cu_count() {
+  static std::atomic<int32_t> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 256;
+  if (dev < 64) {
+    const int32_t v = cache[dev].load(std::memory_order_relaxed);
+    if (v > 0) return static_cast<uint32_t>(v);
+  }
+  int n = 0;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+    n = 256;
+  if (dev < 64) cache[dev].store(n, std::memory_order_relaxed);
+  return static_cast<uint32_t>(n);
+}
+
 template <typename T, int MODE, int K, bool TOP>
-hipError_t go_reg(const chunk::Group& grp, int form, hipStream_t stream) {
+hipError_t go_reg(const chunk::Group& grp, int form, hipStream_t stream, bool* streamed) {
   const uint32_t tiles = grp.first[chunk::kGroup];
   if (tiles == 0) return hipSuccess;
+  if constexpr (K == 4 && !TOP && sizeof(T) == 4) {
+    if (form == FORM_BOTTOM && g_chunk_stream && grp.n == 1) {
+      *streamed = true;
+      // four one-wavefront workgroups per CU (one per SIMD), each over
+      // tiles / G tiles; or at most the number the option names
+      const uint32_t cap = g_chunk_stream == 1 ? 4 * cu_count() : static_cast<uint32_t>(g_chunk_stream);
+      const uint32_t grid = std::min(tiles, cap);
+      hipLaunchKernelGGL((absorb_chunk_reg_stream<T, MODE, K>), dim3(grid), dim3(64), 0, stream,
+                         grp);
+      return hipGetLastError();
+    }
+  }
   if (form == FORM_BOTTOM) {
     hipLaunchKernelGGL((absorb_chunk_reg<T, MODE, K, TOP, FORM_BOTTOM>), dim3(tiles), dim3(64),
                        0, stream, grp);
@@ -601,19 +847,22 @@ hipError_t go_reg(const chunk::Group& grp, int form, hipStream_t stream) {
 }
 
 template <typename T, int MODE>
-hipError_t go_reg_k(const chunk::Group& grp, int k, bool top, int form, hipStream_t stream) {
-  if (k == 2) return top ? go_reg<T, MODE, 2, true>(grp, form, stream)
-                         : go_reg<T, MODE, 2, false>(grp, form, stream);
-  if (k == 3) return top ? go_reg<T, MODE, 3, true>(grp, form, stream)
-                         : go_reg<T, MODE, 3, false>(grp, form, stream);
+hipError_t go_reg_k(const chunk::Group& grp, int k, bool top, int form, hipStream_t stream,
+                    bool* streamed) {
+  if (k == 2) return top ? go_reg<T, MODE, 2, true>(grp, form, stream, streamed)
+                         : go_reg<T, MODE, 2, false>(grp, form, stream, streamed);
+  if (k == 3) return top ? go_reg<T, MODE, 3, true>(grp, form, stream, streamed)
+                         : go_reg<T, MODE, 3, false>(grp, form, stream, streamed);
   if constexpr (MODE != M_F64) {
-    if (k == 4) return top ? go_reg<T, MODE, 4, true>(grp, form, stream)
-                           : go_reg<T, MODE, 4, false>(grp, form, stream);
+    if (k == 4) return top ? go_reg<T, MODE, 4, true>(grp, form, stream, streamed)
+                           : go_reg<T, MODE, 4, false>(grp, form, stream, streamed);
   }
   return hipErrorInvalidValue;
 }
 
 }  // namespace
+
+void set_chunk_stream(int32_t v) { g_chunk_stream = v; }
 
 int32_t chunk_reg_max_steps(int32_t type) { return type == EL_F64 ? 3 : 4; }
 
@@ -635,6 +884,7 @@ hipError_t launch_absorb_chunks_reg(const ChunkArgs* a, int32_t n, const StagedA
   const bool f64 = a[0].type == EL_F64, bf = !f64 && a[0].arith == AR_BF16X3;
   *kname = f64 ? "absorb_chunk_reg_f64" : bf ? "absorb_chunk_reg_bf16x3" : "absorb_chunk_reg_f32";
   bool done[chunk::kGroup] = {false, false, false, false};
+  bool streamed = false;
   // one launch per (rows, top edge, tile form) among the units
   for (int32_t u = 0; u < n; ++u) {
     if (done[u]) continue;
@@ -654,11 +904,12 @@ hipError_t launch_absorb_chunks_reg(const ChunkArgs* a, int32_t n, const StagedA
       }
     chunk::Group grp;
     if (!chunk::fill_group(grp, sel, ns, st, &state->flags, f64)) return hipErrorInvalidValue;
-    const hipError_t e = f64  ? go_reg_k<double, M_F64>(grp, a[u].k, top, form, stream)
-                         : bf ? go_reg_k<float, M_BF16X3>(grp, a[u].k, top, form, stream)
-                              : go_reg_k<float, M_F32>(grp, a[u].k, top, form, stream);
+    const hipError_t e = f64  ? go_reg_k<double, M_F64>(grp, a[u].k, top, form, stream, &streamed)
+                         : bf ? go_reg_k<float, M_BF16X3>(grp, a[u].k, top, form, stream, &streamed)
+                              : go_reg_k<float, M_F32>(grp, a[u].k, top, form, stream, &streamed);
     if (e != hipSuccess) return e;
   }
+  if (streamed) *kname = bf ? "absorb_chunk_reg_stream_bf16x3" : "absorb_chunk_reg_stream_f32";
   return hipSuccess;
 }
 

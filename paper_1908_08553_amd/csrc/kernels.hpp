@@ -205,6 +205,7 @@ int32_t ring_mfma_splits(const RingArgs& a);
 int64_t ring_mfma_partials_for(const RingArgs& a);
 // 1: FP64 ring products scale every staged operand (else automatic)
 void set_ring_operand_scale(int32_t on);
+void set_chunk_stream(int32_t v);
 hipError_t launch_ring_mfma(const RingArgs& a, hipStream_t stream, const char** kname,
                             int64_t* n_partials, int32_t* c_slices);
 

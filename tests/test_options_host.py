@@ -15,10 +15,12 @@ RANGES = {
     tn.TN_OPT_QUADRANT_STREAMS: ([0, 1], [-1, 2]),
     tn.TN_OPT_CHAIN_STEPS: ([0, 1], [-1, 2]),
     tn.TN_OPT_RING_OPERAND_SCALE: ([0, 1], [-1, 2]),
+    tn.TN_OPT_CHUNK_STREAM: ([0, 1, 2, 65536], [-1, 65537]),
 }
 DEFAULTS = {tn.TN_OPT_KERNEL_IMPL: 0, tn.TN_OPT_BATCH_THREADS: 512, tn.TN_OPT_FUSE_STEPS: 2,
             tn.TN_OPT_CHUNK_SCHEDULE: 0, tn.TN_OPT_QUADRANT_STREAMS: 0,
-            tn.TN_OPT_CHAIN_STEPS: 1, tn.TN_OPT_RING_OPERAND_SCALE: 0}
+            tn.TN_OPT_CHAIN_STEPS: 1, tn.TN_OPT_RING_OPERAND_SCALE: 0,
+            tn.TN_OPT_CHUNK_STREAM: 1}
 
 
 @pytest.mark.parametrize("opt", sorted(RANGES))
