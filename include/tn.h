@@ -549,12 +549,13 @@ tn_status tn_server_destroy(tn_server* server);
  *                        give the same bits (power-of-two scaling is exact
  *                        while nothing leaves the normal range).           */
 #define TN_OPT_RING_OPERAND_SCALE 9
-/*   TN_OPT_CHUNK_STREAM : 1 (default) = the 4-row register chunks that end a
- *                        column (suffix 1) in FP32 and BF16x3 run streamed:
- *                        one wavefront per SIMD (four per CU) takes several
- *                        tiles and fills the first half of its next tile's
- *                        slice while the current tile's register-only steps
- *                        and stores run; n = 2..65536: streamed with at most
+/*   TN_OPT_CHUNK_STREAM : 1 (default) = the register chunks that end a
+ *                        column (suffix 1) with the most rows (4 in FP32 and
+ *                        BF16x3, 3 in FP64) run streamed: each wavefront
+ *                        (as many as fit on the CUs) takes several tiles and
+ *                        fills the first half of its next tile's slice while
+ *                        the current tile's register-only steps and stores
+ *                        run; n = 2..65536: streamed with at most
  *                        n wavefronts (more tiles each); 0 = one tile per
  *                        wavefront.  All give the same bits (the same
  *                        products in the same order).                      */

@@ -596,29 +596,52 @@ __device__ inline void tile_bottom(UnitRef d, int64_t tile, T& mx, int& bad, T* 
   }
 }
 
-// FORM_BOTTOM streamed over tiles, for 4-row chunks of 4-byte entries: 256
-// accumulators per lane leave one wavefront per SIMD, so in the one-tile form
-// a wavefront's loads wait for its own matrix work and the reverse.  Here a
-// wavefront takes tiles b, b + G, b + 2G, ... of one unit (G wavefronts, four
-// per CU).  Once step 0 has read the last quarter of a tile's slice, the first
+// FORM_BOTTOM streamed over tiles, for the longest chunks (4 rows of 4-byte
+// entries, 3 rows of 8-byte ones): their accumulators leave one or two
+// wavefronts per SIMD, so in the one-tile form a wavefront's loads wait for
+// its own matrix work and the reverse.  Here a wavefront takes tiles b,
+// b + G, b + 2G, ... of one unit (G wavefronts, as many as fit on the CUs).  Once step 0 has read the last quarter of a tile's slice, the first
 // two quarters of its next tile are filled into the two stage buffers; they
 // arrive during the register-only steps 1..k-1 and the stores.  Step 0's
 // operands and the scale are loaded once; those of steps 1..k-1 are loaded
 // while the last quarter is in flight and first used after the wait for it
 // (the compiler's own wait for a register load issued among stage fills
 // waits for every fill).  The outputs leave through a third, small buffer, a
-// quarter of each fibre at a time.  Waits: at quarter 0 at most min(LPW, NST)
-// operations may be outstanding (the previous tile's stores, or the first
-// tile's quarter 1), at quarter 1 LPW + NST after a previous tile (its stores
+// quarter of each fibre at a time.  Waits: at quarter 0 at most LPW
+// operations may be outstanding (the fills of quarter 1, then the previous
+// tile's stores), at quarter 1 LPW + NST after a previous tile (its stores
 // and the fills of quarter 2), else as in the one-tile form.
-template <int K>
-constexpr int stream_out_pitch() { return (1 << (2 * (K - 1))) + 4; }
+template <typename T, int K>
+constexpr int stream_out_pitch() { return (1 << (2 * (K - 1))) + static_cast<int>(16 / sizeof(T)); }
+
+// Eight 16-byte LDS reads at p + 16 i into v[i] (as lds_read16 below).
+typedef __attribute__((address_space(3))) const void* LdsCPtr;
+__device__ inline void lds_read8(const void* p, f32x4 (&v)[8]) {
+#if __HIP_DEVICE_COMPILE__
+  asm volatile(
+      "ds_read_b128 %0, %8\n\t"
+      "ds_read_b128 %1, %8 offset:16\n\t"
+      "ds_read_b128 %2, %8 offset:32\n\t"
+      "ds_read_b128 %3, %8 offset:48\n\t"
+      "ds_read_b128 %4, %8 offset:64\n\t"
+      "ds_read_b128 %5, %8 offset:80\n\t"
+      "ds_read_b128 %6, %8 offset:96\n\t"
+      "ds_read_b128 %7, %8 offset:112\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]), "=&v"(v[5]),
+        "=&v"(v[6]), "=&v"(v[7])
+      : "v"((LdsCPtr)p)
+      : "memory");
+#else
+  (void)p;
+  for (int i = 0; i < 8; ++i) v[i] = f32x4{};
+#endif
+}
 
 // Sixteen 16-byte LDS reads at p + 16 i into v[i], in one asm block that waits
 // for its own results.  The compiler does not count it as an LDS load, so it
 // adds no wait for the stage fills in flight (it cannot tell which buffer a
 // fill targets and would wait for all of them).
-typedef __attribute__((address_space(3))) const void* LdsCPtr;
 __device__ inline void lds_read16(const void* p, f32x4 (&v)[16]) {
 #if __HIP_DEVICE_COMPILE__
   asm volatile(
@@ -653,20 +676,20 @@ __device__ inline void lds_read16(const void* p, f32x4 (&v)[16]) {
 template <typename T, int MODE, int K>
 __global__ __launch_bounds__(64) void absorb_chunk_reg_stream(chunk::Group arg) {
   (void)arg;   // read in place below
-  static_assert(sizeof(T) == 4 && K == 4, "4-row chunks of 4-byte entries");
+  static_assert((sizeof(T) == 4 && K == 4) || (sizeof(T) == 8 && K == 3),
+                "4-row chunks of 4-byte entries or 3-row chunks of 8-byte ones");
   using V4 = RV4<MODE>;
   constexpr int M1 = 1 << (2 * (K - 1)), QR = quarter_rows<K>();
-  static_assert(M1 == 64, "sixteen 16-byte reads per lane and quarter");
   constexpr int RIN = 4 * QR, ROUT = 4 * M1, ES = sizeof(T);
-  constexpr int PT = bottom_pitch<T, K>(), BB = 16 * PT, OPT = stream_out_pitch<K>();
-  constexpr int FB = QR * ES;
-  constexpr int PIECES = FB >= 1024 ? FB / 1024 : 1;
-  constexpr int LPW = 16 * PIECES;            // fills per quarter
+  constexpr int PT = bottom_pitch<T, K>(), BB = 16 * PT, OPT = stream_out_pitch<T, K>();
+  constexpr int FB = QR * ES;                 // bytes of one fibre's quarter
+  constexpr int LANES = FB >= 1024 ? 64 : FB / 16;   // active lanes of a fill
+  constexpr int LPW = 16;                     // fills per quarter (one per fibre)
+  constexpr int NR = M1 * ES / 16;            // 16-byte LDS reads per lane and quarter
   constexpr int TQ = M1 / 4;                  // tiles t per output quarter
-  constexpr int NIT = 16 * M1 / 256;          // 16-byte stores per lane and output quarter
+  constexpr int NIT = M1 / 16;                // stores per lane and output quarter
   constexpr int NST = 4 * NIT;                // stores per tile
-  constexpr int W0 = LPW < NST ? LPW : NST;
-  static_assert(FB % 1024 == 0 && LPW + NST < 64, "fills of whole KiB, vmcnt range");
+  static_assert(FB <= 1024 && (NR == 16 || NR == 8) && LPW + NST < 64, "shapes");
   __shared__ __attribute__((aligned(16))) T stage[2 * BB];
   __shared__ __attribute__((aligned(16))) T ostage[16 * OPT];
   const GroupRef g = (GroupRef)__builtin_amdgcn_kernarg_segment_ptr();
@@ -678,9 +701,7 @@ __global__ __launch_bounds__(64) void absorb_chunk_reg_stream(chunk::Group arg) 
   auto fill_q = [&](const char* src, int kk, T* buf) {
 #pragma unroll
     for (int i = 0; i < 16; ++i)
-#pragma unroll
-      for (int pc = 0; pc < PIECES; ++pc)
-        lds_fill16(src + (i * RIN + kk * QR) * ES + pc * 1024 + 16 * lane, buf + i * PT + pc * (1024 / ES));
+      if (lane < LANES) lds_fill16(src + (i * RIN + kk * QR) * ES + 16 * lane, buf + i * PT);
   };
   auto src_of = [&](uint32_t tt) {
     return static_cast<const char*>(d.in) + static_cast<int64_t>(tt) * 16 * RIN * ES;
@@ -705,7 +726,7 @@ __global__ __launch_bounds__(64) void absorb_chunk_reg_stream(chunk::Group arg) 
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       T* buf = stage + (kk & 1) * BB;
-      if (kk == 0) wait_vm<W0>();
+      if (kk == 0) wait_vm<LPW>();
       else if (kk == 1) {
         if (first) wait_vm<LPW>();
         else wait_vm<LPW + NST>();
@@ -713,23 +734,32 @@ __global__ __launch_bounds__(64) void absorb_chunk_reg_stream(chunk::Group arg) 
       else wait_vm<0>();
       T x[M1];
       {
-        f32x4 v[16];
-        lds_read16(buf + c * PT + gl * M1, v);
+        f32x4 v[NR];
+        if constexpr (NR == 16) lds_read16(buf + c * PT + gl * M1, v);
+        else lds_read8(buf + c * PT + gl * M1, v);
+        constexpr int PER = 16 / ES;   // entries per 16-byte read
 #pragma unroll
-        for (int t4 = 0; t4 < 16; ++t4)
+        for (int i = 0; i < NR; ++i) {
+          typedef T TV __attribute__((ext_vector_type(PER)));
+          const TV tv = __builtin_bit_cast(TV, v[i]);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) x[4 * t4 + e] = v[t4][e];
+          for (int e = 0; e < PER; ++e) x[PER * i + e] = tv[e];
+        }
       }
       if (kk < 2) fill_q(src, kk + 2, buf);
       if (kk == 2) {
         r1 = reg_ops_load<T, MODE, false, 0>(d.S[1], d.hi[1], d.lo[1], c, gl);
-        r2 = reg_ops_load<T, MODE, false, 0>(d.S[2], d.hi[2], d.lo[2], c, gl);
-        r3 = reg_ops_load<T, MODE, false, 2>(d.S[3], d.hi[3], d.lo[3], c, gl);
+        if constexpr (K == 4) {
+          r2 = reg_ops_load<T, MODE, false, 0>(d.S[2], d.hi[2], d.lo[2], c, gl);
+          r3 = reg_ops_load<T, MODE, false, 2>(d.S[3], d.hi[3], d.lo[3], c, gl);
+        } else {
+          r2 = reg_ops_load<T, MODE, false, 2>(d.S[2], d.hi[2], d.lo[2], c, gl);
+        }
       }
       if (kk == 3) {
         launder<T, MODE, false>(r1);
         launder<T, MODE, false>(r2);
-        launder<T, MODE, false>(r3);
+        if constexpr (K == 4) launder<T, MODE, false>(r3);
         // issued on every path (after the last tile they re-read its first
         // two quarters, from L2) so that no compiler wait depends on the path
         if (more) src = src_of(next);
@@ -740,7 +770,7 @@ __global__ __launch_bounds__(64) void absorb_chunk_reg_stream(chunk::Group arg) 
     }
     reg_step<T, MODE, K, 1>(y, reg_ops_build<T, MODE, false>(r1));
     reg_step<T, MODE, K, 2>(y, reg_ops_build<T, MODE, false>(r2));
-    reg_step<T, MODE, K, 3>(y, reg_ops_build<T, MODE, false>(r3));
+    if constexpr (K == 4) reg_step<T, MODE, K, 3>(y, reg_ops_build<T, MODE, false>(r3));
     // outputs: fibre i's row j = 4 t + r at i * ROUT + j; output quarter qo
     // holds t in [qo TQ, (qo + 1) TQ), M1 entries of each fibre
     T* dst = static_cast<T*>(d.out) + static_cast<int64_t>(t) * 16 * ROUT;
@@ -817,12 +847,14 @@ template <typename T, int MODE, int K, bool TOP>
 hipError_t go_reg(const chunk::Group& grp, int form, hipStream_t stream, bool* streamed) {
   const uint32_t tiles = grp.first[chunk::kGroup];
   if (tiles == 0) return hipSuccess;
-  if constexpr (K == 4 && !TOP && sizeof(T) == 4) {
+  if constexpr (!TOP && ((K == 4 && sizeof(T) == 4) || (K == 3 && sizeof(T) == 8))) {
     if (form == FORM_BOTTOM && g_chunk_stream && grp.n == 1) {
       *streamed = true;
-      // four one-wavefront workgroups per CU (one per SIMD), each over
+      // one-wavefront workgroups, as many per CU as the registers allow (one
+      // per SIMD with 4-byte entries, two with 8-byte ones), each over
       // tiles / G tiles; or at most the number the option names
-      const uint32_t cap = g_chunk_stream == 1 ? 4 * cu_count() : static_cast<uint32_t>(g_chunk_stream);
+      constexpr uint32_t kPerCU = sizeof(T) == 4 ? 4 : 8;
+      const uint32_t cap = g_chunk_stream == 1 ? kPerCU * cu_count() : static_cast<uint32_t>(g_chunk_stream);
       const uint32_t grid = std::min(tiles, cap);
       hipLaunchKernelGGL((absorb_chunk_reg_stream<T, MODE, K>), dim3(grid), dim3(64), 0, stream,
                          grp);
@@ -909,7 +941,9 @@ hipError_t launch_absorb_chunks_reg(const ChunkArgs* a, int32_t n, const StagedA
                               : go_reg_k<float, M_F32>(grp, a[u].k, top, form, stream, &streamed);
     if (e != hipSuccess) return e;
   }
-  if (streamed) *kname = bf ? "absorb_chunk_reg_stream_bf16x3" : "absorb_chunk_reg_stream_f32";
+  if (streamed)
+    *kname = f64 ? "absorb_chunk_reg_stream_f64"
+                 : bf ? "absorb_chunk_reg_stream_bf16x3" : "absorb_chunk_reg_stream_f32";
   return hipSuccess;
 }
 

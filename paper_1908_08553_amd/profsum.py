@@ -37,6 +37,9 @@ KERNELS = OrderedDict([
     ("absorb_chunk_reg_bf16x3", (r"absorb_chunk_reg<float, 2,",
                                  ["paper_1908_08553_amd/csrc/absorb_chunk_reg.hip",
                                   "paper_1908_08553_amd/csrc/absorb_device.hpp"])),
+    ("absorb_chunk_reg_stream_f64", (r"absorb_chunk_reg_stream<double, 1,",
+                                     ["paper_1908_08553_amd/csrc/absorb_chunk_reg.hip",
+                                      "paper_1908_08553_amd/csrc/absorb_device.hpp"])),
     ("absorb_chunk_reg_stream_f32", (r"absorb_chunk_reg_stream<float, 0,",
                                      ["paper_1908_08553_amd/csrc/absorb_chunk_reg.hip",
                                       "paper_1908_08553_amd/csrc/absorb_device.hpp"])),
