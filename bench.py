@@ -561,10 +561,6 @@ def main():
     head = run_leg(tn, torch, 12, 12, 4, "uniform", 0, tn.TN_ORDER_HEURISTIC, "f64",
                    args.steps, args.warmup, profile=True)
     log(f"headline: {head['ms']:.3f} ms/contraction, {head['gflops']:.1f} GFLOP/s")
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline()
-        log(f"cpu baseline: {json.dumps(cpu)}")
     legs = {}
     if not args.no_legs:
         spec = [x for x in LEGS if not args.leg or x[0] in args.leg]
@@ -577,16 +573,7 @@ def main():
             legs[name] = leg
             log(f"{name}: {leg['ms']:.3f} ms, {leg['gflops']:.1f} GFLOP/s, "
                 f"log|Z|={leg['log_abs']:.10f}")
-    # accuracy: |d log Z| (the relative error in Z) of every 12x12 leg against
-    # the FP64 oracle (or, without the CPU leg, against the GPU FP64 headline)
-    ref_u = cpu["log_abs"] if cpu else head["log_abs"]
-    ref_i = (cpu["ising12_d4_log_abs_transfer_matrix"] if cpu
-             else legs.get("ising12_d4_quad_f64", {}).get("log_abs"))
-    ref_name = "oracle_f64" if cpu else "gpu_f64"
-    for name, leg in list(legs.items()) + [("headline", head)]:
-        ref = {"uniform": ref_u, "ising": ref_i}.get(leg["inputs"]) if leg["rows"] == 12 else None
-        if ref is not None:
-            leg[f"abs_dlogz_vs_{ref_name}"] = abs(leg["log_abs"] - ref)
+    contraction_legs = list(legs.items())
     def want(name):
         return not args.leg or name in args.leg
 
@@ -607,15 +594,32 @@ def main():
             log(f"orders: {json.dumps(legs['orders'])}")
         if want("ite"):
             legs["ite"] = ite_leg(tn, torch)
-            if cpu:
-                for k, v in legs["ite"]["fig4"].items():
-                    v["ed_energy_per_site"] = cpu["ed_energy_per_site"][k]
-                    v["rel_error_vs_ed"] = abs(v["energy_per_site"] - v["ed_energy_per_site"]) / \
-                        abs(v["ed_energy_per_site"])
             log(f"ite: {json.dumps(legs['ite'])}")
         if not args.no_serve and want("served"):
             legs["served"] = served_leg(tn, torch)
             log(f"served: {json.dumps(legs['served'])}")
+    # the CPU leg after every GPU leg: its BLAS threads keep the host cores
+    # busy for a while after it returns, which would slow the launches of a
+    # GPU leg that followed it
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline()
+        log(f"cpu baseline: {json.dumps(cpu)}")
+    # accuracy: |d log Z| (the relative error in Z) of every 12x12 leg against
+    # the FP64 oracle (or, without the CPU leg, against the GPU FP64 headline)
+    ref_u = cpu["log_abs"] if cpu else head["log_abs"]
+    ref_i = (cpu["ising12_d4_log_abs_transfer_matrix"] if cpu
+             else legs.get("ising12_d4_quad_f64", {}).get("log_abs"))
+    ref_name = "oracle_f64" if cpu else "gpu_f64"
+    for name, leg in contraction_legs + [("headline", head)]:
+        ref = {"uniform": ref_u, "ising": ref_i}.get(leg["inputs"]) if leg["rows"] == 12 else None
+        if ref is not None:
+            leg[f"abs_dlogz_vs_{ref_name}"] = abs(leg["log_abs"] - ref)
+    if cpu and "ite" in legs:
+        for k, v in legs["ite"]["fig4"].items():
+            v["ed_energy_per_site"] = cpu["ed_energy_per_site"][k]
+            v["rel_error_vs_ed"] = abs(v["energy_per_site"] - v["ed_energy_per_site"]) / \
+                abs(v["ed_energy_per_site"])
     head_kernels = head.pop("kernels")
     line = {
         "metric": "exact contraction GFLOP/s + contractions/s, p50/p99 latency; FP64 vs split-prec",
