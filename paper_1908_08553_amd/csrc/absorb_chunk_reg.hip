@@ -600,8 +600,9 @@ __device__ inline void tile_bottom(UnitRef d, int64_t tile, T& mx, int& bad, T* 
 // entries, 3 rows of 8-byte ones): their accumulators leave one or two
 // wavefronts per SIMD, so in the one-tile form a wavefront's loads wait for
 // its own matrix work and the reverse.  Here a wavefront takes tiles b,
-// b + G, b + 2G, ... of one unit (G wavefronts, as many as fit on the CUs).  Once step 0 has read the last quarter of a tile's slice, the first
-// two quarters of its next tile are filled into the two stage buffers; they
+// b + G, b + 2G, ... of one unit (G wavefronts, as many as fit on the CUs).
+// Once step 0 has read the last quarter of a tile's slice, the first two
+// quarters of its next tile are filled into the two stage buffers; they
 // arrive during the register-only steps 1..k-1 and the stores.  Step 0's
 // operands and the scale are loaded once; those of steps 1..k-1 are loaded
 // while the last quarter is in flight and first used after the wait for it
@@ -825,7 +826,7 @@ int form_of(const ChunkArgs& a) {
   return (a.type != EL_F64 && a.post % 32 == 0) ? FORM_PAIR : FORM_DIRECT;
 }
 
-int32_t g_chunk_stream = 1;   // TN_OPT_CHUNK_STREAM: 0 off, 1 four per CU, n >= 2 at most n
+int32_t g_chunk_stream = 1;   // TN_OPT_CHUNK_STREAM: 0 off, 1 as many as fit, n >= 2 at most n
 
 // Compute units of the current device (cached per device).
 uint32_t cu_count() {
