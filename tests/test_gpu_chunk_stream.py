@@ -8,6 +8,7 @@ TN_OPT_CHUNK_STREAM = 0; they are also checked against the FP64 oracle (paper
 Small workgroup caps make each wavefront take many tiles and end on a
 ragged share.  (Quadrant units never end a column with suffix 1, so grouped
 launches keep the one-tile form.)"""
+import numpy as np
 import pytest
 
 import lattice_inputs as li
@@ -94,3 +95,19 @@ def test_streamed_bottoms_signed_entries(tn):
     want = C.contract_grid(s, 12, 8, P.QUADRANT, 0, 0)
     assert base.sign == want.sign
     assert abs(base.log_abs - want.log_abs) <= 1e-5 * max(1.0, abs(want.log_abs))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "f64"])
+def test_streamed_bottoms_flag_nonfinite(tn, prec):
+    # a NaN in a site of the bottom row of an inner column (absorbed by the
+    # streamed bottom chunk): the contraction reports TN_ENONFINITE with the
+    # streamed and the one-tile forms alike
+    rows, cols = 12, 5
+    s = li.uniform(rows, cols, 4, 5)
+    s[(rows - 1) * cols + 2] = s[(rows - 1) * cols + 2].copy()
+    s[(rows - 1) * cols + 2].flat[7] = np.nan
+    plan = tn.tn_plan_grid(rows, cols, 4, order=P.COLSWEEP)
+    sites = tn.device_sites(s)
+    for cap in (0, 1, 3):
+        got, _ = run(tn, plan, sites, prec, cap)
+        assert got.status == tn.TN_ENONFINITE, (prec, cap, got)
